@@ -1,0 +1,256 @@
+/*
+ * ens.h -- C ABI of the MI355X ensemble-PCG library (libens.so).
+ *
+ * The library solves S discretised anisotropic-diffusion systems L_m U_m = F_m
+ * at once.  All members share one sparsity pattern (a nine-point stencil on
+ * an n x n grid of interior points); each member has its own matrix values.
+ * Paper: Section 2.3, eqs. (discrete-sys), (discrete-ensemble-sys) and
+ * (discrete-comm-kron-sys); the ensemble matrix stores each nonzero as a
+ * length-S array, and inner products and norms are computed per member so
+ * that each member converges at its own rate (Section 2.3, last paragraphs;
+ * Section 4, the paragraphs on the convergence test and on the A-norm guard).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Real data are IEEE double (FP64); counts and indices are int32_t.
+ *  - N_r = n * n rows; row r = j * n + i with i (x1 direction) fastest,
+ *    i, j in [0, n).
+ *  - Ensemble layout (member index innermost, the commuted Kronecker ordering
+ *    of eq. (discrete-comm-kron-sys)):
+ *        vector X      : X[r * S + s]                      ([N_r][S])
+ *        matrix values : V[(k * N_r + r) * S + s]          ([9][N_r][S])
+ *    Stencil slot k = 3 (dj + 1) + (di + 1) couples row (i, j) to column
+ *    (i + di, j + dj): k = 0 SW, 1 S, 2 SE, 3 W, 4 C (diagonal), 5 E, 6 NW,
+ *    7 N, 8 NE -- the column order of a CSR row.  Slots that would couple to
+ *    a boundary node hold 0 (zero Dirichlet data).
+ *  - S must be a power of two, 1 <= S <= 64.  Callers with another count pad
+ *    the ensemble by repeating its last sample (paper, Section 4, Test 1
+ *    footnote).
+ *  - "_dev" pointers are device memory of the current HIP device, "_host"
+ *    pointers are host memory.  The caller owns every buffer; the library
+ *    allocates no device memory, keeps no pointer after a call returns, and
+ *    holds no state between calls.  Device buffers must be 16-byte aligned.
+ *  - `stream` is a hipStream_t passed as void* (NULL: the null stream).
+ *    Device work is enqueued on that stream.  Calls documented as blocking
+ *    synchronise that stream before returning.
+ *  - Every entry point returns ENS_OK (0) or a negative error code.  Arguments
+ *    are validated before any work is enqueued; on error nothing is written.
+ *    ENS_EHIP means a HIP call failed; ens_last_hip_error() returns its code.
+ *    A member that does not converge is NOT an error: see the status codes.
+ */
+#ifndef ENS_H
+#define ENS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- codes */
+#define ENS_OK 0
+#define ENS_EINVAL (-1)   /* bad argument (size, pointer, non-finite parameter) */
+#define ENS_ENOMEM (-2)   /* caller's workspace smaller than required            */
+#define ENS_EHIP (-3)     /* a HIP runtime call failed                           */
+#define ENS_ENOTSUP (-4)  /* valid but unsupported combination                   */
+
+/* per-member solver status */
+#define ENS_CONVERGED 0   /* ||r_k||_2 <= rtol ||b||_2 reached; iters = k          */
+#define ENS_MAX_ITER 1    /* max_iter reached without convergence                 */
+#define ENS_BREAKDOWN 2   /* p^T A p not a positive finite number: update replaced
+                             by zero and the member frozen (the paper's guard)     */
+#define ENS_ZERO_RHS 3    /* b = 0: x = 0, iters = 0                               */
+
+#define ENS_PRECOND_JACOBI 0
+#define ENS_PRECOND_CHEBYSHEV 1
+
+/* Problem descriptor: -div(a(x) K(y) grad u) = f on the unit square, u = 0 on
+ * the boundary, discretised by the conservative nine-point scheme.
+ *   K = R(theta) diag(1, eps) R(theta)^T,  theta = (pi/4)(1 + y1'),
+ *   eps = 10^-(1 + y0')            (eps_model 0)
+ *       = 10^-(1.5 + 1.5 y0')      (eps_model 1)
+ *   a(x) = 1 + amp * sum_{k=1}^{d-2} y'_{k+1} sin(k pi x1) sin(k pi x2) / k^2
+ * where y' = (y'_0 .. y'_{d-1}) is one member's parameter vector (0-based). */
+typedef struct {
+  int32_t n;          /* interior points per dimension, n >= 2            */
+  int32_t d;          /* parameters per member, 2 <= d <= 16              */
+  int32_t eps_model;  /* 0 or 1                                            */
+  int32_t reserved;   /* must be 0                                         */
+  double amp;         /* amplitude of the a(x) modes (finite, |amp| < 1)  */
+} ens_problem;
+
+/* Solver options.  Zero-initialise, then set what you need; fields left 0
+ * take the documented default. */
+typedef struct {
+  int32_t precond;      /* ENS_PRECOND_JACOBI (default) or _CHEBYSHEV          */
+  int32_t cheb_degree;  /* Chebyshev residual-polynomial degree, 2..8 (4)     */
+  double cheb_ratio;    /* lambda_max / lambda_min of the Chebyshev interval (30) */
+  double rtol;          /* relative residual tolerance (1e-8)                 */
+  int32_t max_iter;     /* iteration cap (20000)                              */
+  int32_t poll_every;   /* host checks the device done flag every m iterations (16) */
+  int32_t tile_lines;   /* stencil tile height in grid lines, 0 = heuristic   */
+  int32_t max_groups;   /* workgroups of the stencil/update kernels, 0 = heuristic */
+  int32_t flags;        /* bit 0 (ENS_FLAG_TIME_SPMV): time the fused SpMV kernel */
+  int32_t reserved;     /* must be 0                                          */
+} ens_opts;
+
+#define ENS_FLAG_TIME_SPMV 1
+
+/* Optional statistics of one solve. */
+typedef struct {
+  int32_t ens_iters;          /* iterations the ensemble ran = max_i iters_i  */
+  int32_t spmv_timed;         /* fused-SpMV launches timed with HIP events    */
+  double spmv_ms;             /* their summed duration (ms)                   */
+  int32_t spmv_groups;        /* workgroups per fused-SpMV launch             */
+  int32_t tile_lines;         /* tile height used                             */
+} ens_stats;
+
+/* ------------------------------------------------------------ assembly */
+/* Assemble the ensemble matrix and right-hand side for S members.
+ * Paper: Section 2.3 (each nonzero stored as a length-S array; mesh and graph
+ * are sample independent and shared).  y_dev: [S][d] parameters (device).
+ * Outputs V_dev [9][N_r][S] (A, with the 1/h^2 included) and b_dev [N_r][S]
+ * (f = 1).  Asynchronous on `stream`.
+ * Errors: ENS_EINVAL for a NULL pointer, n < 2, d outside [2,16], eps_model
+ * outside {0,1}, S not a power of two in [1,64], or non-finite amp.  The
+ * parameter values themselves are read on the device; a non-finite y gives
+ * non-finite matrix values for that member only (reject them on the host). */
+int ens_assemble_ensemble(const ens_problem* prob, int32_t S, const double* y_dev,
+                          double* V_dev, double* b_dev, void* stream);
+
+/* ------------------------------------------------------------- solver */
+/* Bytes of device workspace ens_pcg_solve / ens_adjoint_grad need, or 0 if
+ * the arguments are invalid. */
+size_t ens_pcg_workspace_bytes(const ens_problem* prob, const ens_opts* opts, int32_t S);
+
+/* Ensemble preconditioned CG for A_s x_s = b_s, s = 0..S-1, x_0 = 0.
+ * Paper: Section 2.3 (per-member inner products; the ensemble iterates until
+ * every member has converged) and Section 4 (each member's own convergence
+ * iteration is recorded; when p^T A p is numerically zero the member's update
+ * is replaced by zero and its x stops changing).  Each member follows the
+ * Hestenes-Stiefel PCG recurrence; a member that has converged is frozen (its
+ * x and r no longer change) while the others continue.  Preconditioner:
+ * Jacobi (diagonal = slot 4 of V) or a Chebyshev polynomial in D^-1 A over
+ * [lambda_max / cheb_ratio, lambda_max], lambda_max the member's Gershgorin
+ * bound max_i sum_j |a_ij| / a_ii.
+ * In:  V_dev [9][N_r][S] (symmetric positive definite per member),
+ *      b_dev [N_r][S].
+ * Out: x_dev [N_r][S] (overwritten); iters_host[S], status_host[S],
+ *      relres_host[S] (= ||r|| / ||b|| of the recurrence residual at exit, 0
+ *      for ENS_ZERO_RHS), *ens_iters_host = max_s iters_s; stats may be NULL.
+ * ws_dev / ws_bytes: caller-owned workspace of at least
+ * ens_pcg_workspace_bytes() bytes (ENS_ENOMEM otherwise).
+ * Blocking: synchronises `stream` before returning. */
+int ens_pcg_solve(const ens_problem* prob, const ens_opts* opts, int32_t S,
+                  const double* V_dev, const double* b_dev, double* x_dev,
+                  int32_t* iters_host, int32_t* status_host, double* relres_host,
+                  int32_t* ens_iters_host, ens_stats* stats,
+                  void* ws_dev, size_t ws_bytes, void* stream);
+
+/* One ensemble matrix-vector product q = A p (the operation the solver's fused
+ * kernel performs each iteration, without the fused updates).
+ * In: V_dev [9][N_r][S], p_dev [N_r][S]; out: q_dev [N_r][S].  Asynchronous. */
+int ens_spmv(const ens_problem* prob, int32_t S, const double* V_dev,
+             const double* p_dev, double* q_dev, void* stream);
+
+/* Apply the Chebyshev preconditioner once: z = M^-1 r per member, with the
+ * polynomial of ens_pcg_solve (degree opts->cheb_degree, ratio opts->cheb_ratio).
+ * In: V_dev, r_dev [N_r][S]; out: z_dev [N_r][S]; lmax_host[S] (may be NULL)
+ * receives each member's Gershgorin bound.  Blocking (reads back lmax). */
+int ens_cheb_apply(const ens_problem* prob, const ens_opts* opts, int32_t S,
+                   const double* V_dev, const double* r_dev, double* z_dev,
+                   double* lmax_host, void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Per-member dot products out_host[s] = sum_r a[r][s] * b[r][s].  With
+ * b_broadcast != 0, b_dev is a single vector [N_r] shared by all members.
+ * The reduction order is fixed, independent of the member index.
+ * Blocking.  Uses the first ens_pcg_workspace_bytes(...) bytes of ws. */
+int ens_member_dot(int32_t N_r, int32_t S, const double* a_dev, const double* b_dev,
+                   int32_t b_broadcast, double* out_host,
+                   void* ws_dev, size_t ws_bytes, void* stream);
+
+/* ----------------------------------------------------------- adjoint */
+/* dQ/dy for Q_s = w^T u_s, with A_s u_s = b (A symmetric, b independent of y):
+ *   solve A_s lambda_s = w by the same ensemble PCG, then
+ *   dQ_s/dy_j = -lambda_s^T (dA_s/dy_j) u_s,
+ * the bilinear form evaluated face by face and node by node from the
+ * coefficient derivatives (not from a differentiated matrix).
+ * In: y_dev [S][d], V_dev (assembled for y), u_dev [N_r][S] (forward
+ * solution), w_dev [N_r] (shared QoI weights).  Out: lambda_dev [N_r][S],
+ * grad_host [S][d], iters_host[S], status_host[S] of the adjoint solve.
+ * Blocking. */
+int ens_adjoint_grad(const ens_problem* prob, const ens_opts* opts, int32_t S,
+                     const double* y_dev, const double* V_dev, const double* u_dev,
+                     const double* w_dev, double* lambda_dev, double* grad_host,
+                     int32_t* iters_host, int32_t* status_host,
+                     void* ws_dev, size_t ws_bytes, void* stream);
+
+/* The dQ/dy kernel alone: grad_host[s][j] = -lambda_s^T (dA_s/dy_j) u_s for
+ * given u and lambda.  Blocking. */
+int ens_dqdy(const ens_problem* prob, int32_t S, const double* y_dev,
+             const double* u_dev, const double* lambda_dev, double* grad_host,
+             void* ws_dev, size_t ws_bytes, void* stream);
+
+/* --------------------------------------------------- sparse grid (host) */
+/* Nodes of the centre-rooted piecewise-linear hierarchy (paper, Section 2.2):
+ * one (level, index) pair per dimension.  1-D coordinates:
+ *   level 0: index 0 -> 0;  level 1: index 0 -> -1, index 1 -> +1;
+ *   level l >= 2: index k in [0, 2^(l-1)) -> -1 + (2k+1) 2^(1-l).
+ * node_level / node_index are [M][d] row-major.  All sparse-grid calls are
+ * host-only, synchronous and deterministic; floating-point evaluation uses a
+ * fixed order (nodes in canonical order: total level, then level vector, then
+ * index vector, lexicographic; each term c, then multiplied by the 1-D hat
+ * values for dimensions 0..d-1, then added), so results are bit-for-bit
+ * reproducible. */
+
+/* Surrogate-based grouping (paper, Section 3.1, eq. SGSiterations and the
+ * rule after it): build the surrogate I^ of node_value (e.g. iteration
+ * counts) over the M nodes by hierarchical surpluses, evaluate it at the
+ * M_new samples y_new [M_new][d], order them by increasing (I^, sample id)
+ * and cut the order into ensembles of S.  The last ensemble is padded by
+ * repeating its last sample (Section 4, Test 1 footnote).  With M == 0 the
+ * samples keep their generation order and pred_out is all zero.
+ * Out: groups_out [ceil(M_new/S)][S] sample ids, pred_out [M_new].
+ * Errors: ENS_EINVAL for bad sizes, a NULL pointer, an invalid node, a
+ * duplicate node, or a non-finite value / sample outside [-1,1]. */
+int ens_group_samples(int32_t d, int32_t M, const int32_t* node_level,
+                      const int32_t* node_index, const double* node_value,
+                      int32_t M_new, const double* y_new, int32_t S,
+                      int32_t* groups_out, double* pred_out);
+
+/* Hierarchical surpluses of node_value over the nodes (paper, Section 2.2,
+ * eq. hierSGint): c_m = v_m - sum over nodes j of lower total level of
+ * c_j psi_j(y_m).  Out: surplus_out [M] in input order. */
+int ens_sg_surpluses(int32_t d, int32_t M, const int32_t* node_level,
+                     const int32_t* node_index, const double* node_value,
+                     double* surplus_out);
+
+/* Coordinates of nodes: y_out [M][d]. */
+int ens_sg_coords(int32_t d, int32_t M, const int32_t* node_level,
+                  const int32_t* node_index, double* y_out);
+
+/* Classic surplus-based refinement (paper, Section 2.2, "Adaptivity"): every
+ * node of total level `newest_level` whose |surplus| >= tau_rel * |value of
+ * the centre node| contributes its children (one dimension at a time) that
+ * are not yet in the grid.  If more candidates exist than budget - M, they are
+ * taken in decreasing order of the largest |surplus| among their refined
+ * parents, ties in canonical order.  The accepted nodes are written in
+ * canonical order to new_level_out / new_index_out ([max_new][d]) and their
+ * count to *n_new_out.  ENS_EINVAL if max_new is too small for the result. */
+int ens_sg_refine(int32_t d, int32_t M, const int32_t* node_level,
+                  const int32_t* node_index, const double* node_value,
+                  int32_t newest_level, double tau_rel, int32_t budget,
+                  int32_t max_new, int32_t* new_level_out, int32_t* new_index_out,
+                  int32_t* n_new_out);
+
+/* ------------------------------------------------------------- misc */
+const char* ens_strerror(int code);
+int ens_last_hip_error(void);   /* hipError_t of the last ENS_EHIP, 0 if none */
+int ens_version(void);          /* library ABI version (major * 100 + minor)  */
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ENS_H */

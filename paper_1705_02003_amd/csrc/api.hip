@@ -1,0 +1,538 @@
+// C ABI of libens: argument validation, workspace carving and the host loop
+// that drives the ensemble PCG kernels.  See include/ens.h for the contract.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+
+namespace ens {
+
+static thread_local int g_last_hip_error = 0;
+
+int set_hip_error(hipError_t e) {
+  g_last_hip_error = (int)e;
+  return ENS_EHIP;
+}
+
+int valid_S(int S) { return S >= 1 && S <= kMaxS && (S & (S - 1)) == 0; }
+
+static int log2i(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Workspace: a small header (partials, per-member state, control words)
+// followed by the ensemble vectors.
+static size_t header_bytes() {
+  size_t b = 0;
+  b += align256(sizeof(double) * 3 * (size_t)kMaxGroups * kMaxS);  // partials
+  b += align256(sizeof(double) * 7 * (size_t)kMaxS);               // doubles
+  b += align256(sizeof(double) * (size_t)kMaxS * kChebCoef);       // cheb
+  b += align256(sizeof(double) * (size_t)kMaxS * 16);              // result
+  b += align256(sizeof(int) * 3 * (size_t)kMaxS);                  // ints
+  b += align256(sizeof(int) * CTL_COUNT);                          // control
+  return b;
+}
+
+static int n_vectors(bool cheb) { return cheb ? 8 : 5; }
+
+size_t workspace_bytes(int n, int S, bool cheb) {
+  const size_t vec = align256(sizeof(double) * (size_t)n * n * S);
+  return header_bytes() + vec * n_vectors(cheb);
+}
+
+static Workspace carve(void* base, int n, int S, bool cheb) {
+  Workspace w;
+  std::memset(&w, 0, sizeof(w));
+  char* p = static_cast<char*>(base);
+  w.partial = reinterpret_cast<double*>(p);
+  p += align256(sizeof(double) * 3 * (size_t)kMaxGroups * kMaxS);
+  double* dd = reinterpret_cast<double*>(p);
+  p += align256(sizeof(double) * 7 * (size_t)kMaxS);
+  w.m.rho = dd;
+  w.m.alpha = dd + kMaxS;
+  w.m.alpha_prev = dd + 2 * kMaxS;
+  w.m.beta = dd + 3 * kMaxS;
+  w.m.bnorm = dd + 4 * kMaxS;
+  w.m.relres = dd + 5 * kMaxS;
+  w.m.lmax = dd + 6 * kMaxS;
+  w.m.cheb = reinterpret_cast<double*>(p);
+  p += align256(sizeof(double) * (size_t)kMaxS * kChebCoef);
+  w.m.result = reinterpret_cast<double*>(p);
+  p += align256(sizeof(double) * (size_t)kMaxS * 16);
+  int* ii = reinterpret_cast<int*>(p);
+  p += align256(sizeof(int) * 3 * (size_t)kMaxS);
+  w.m.active = ii;
+  w.m.iters = ii + kMaxS;
+  w.m.status = ii + 2 * kMaxS;
+  w.m.ctl = reinterpret_cast<int*>(p);
+  p += align256(sizeof(int) * CTL_COUNT);
+  if (n > 0) {
+    const size_t vec = align256(sizeof(double) * (size_t)n * n * S);
+    double** slots[8] = {&w.p[0], &w.p[1], &w.q, &w.r, &w.aux, &w.z[0], &w.z[1], &w.d};
+    for (int k = 0; k < n_vectors(cheb); ++k) {
+      *slots[k] = reinterpret_cast<double*>(p);
+      p += vec;
+    }
+  }
+  return w;
+}
+
+Geometry make_geometry(int n, int S, int tile_lines, int max_groups) {
+  Geometry g;
+  g.n = n;
+  g.S = S;
+  g.logS = log2i(S);
+  g.vec = (S >= 2) ? 2 : 1;
+  g.tpp = S / g.vec;
+  g.tx = kNT * g.vec / S;
+  g.nchunk = (n + g.tx - 1) / g.tx;
+  int ty = tile_lines;
+  if (ty <= 0) {
+    ty = 16;
+    while (ty > 2 && (long long)g.nchunk * ((n + ty - 1) / ty) < 2048) ty >>= 1;
+  }
+  g.ty = std::min(ty, n);
+  g.nband = (n + g.ty - 1) / g.ty;
+  g.ntiles = g.nchunk * g.nband;
+  int G = (max_groups > 0) ? max_groups : 1024;
+  G = std::min(std::min(G, g.ntiles), kMaxGroups);
+  if (G >= 8) G &= ~7;
+  g.groups = std::max(G, 1);
+  g.nr = (size_t)n * n;
+  g.nelem = g.nr * S;
+  return g;
+}
+
+static int elem_groups(const Geometry& g) {
+  const size_t per = (size_t)kNT * g.vec;
+  const size_t need = (g.nelem + per - 1) / per;
+  return (int)std::min<size_t>(need, 1024);
+}
+
+static int check_problem(const ens_problem* p) {
+  if (!p) return ENS_EINVAL;
+  if (p->n < 2 || p->n > 16384) return ENS_EINVAL;
+  if (p->d < 2 || p->d > 16) return ENS_EINVAL;
+  if (p->eps_model != 0 && p->eps_model != 1) return ENS_EINVAL;
+  if (p->reserved != 0) return ENS_EINVAL;
+  if (!std::isfinite(p->amp) || std::fabs(p->amp) >= 1.0) return ENS_EINVAL;
+  return ENS_OK;
+}
+
+struct Opts {
+  int precond, degree, max_iter, poll, tile_lines, max_groups, flags;
+  double ratio, rtol;
+};
+
+static int resolve_opts(const ens_opts* o, Opts& r) {
+  ens_opts z;
+  std::memset(&z, 0, sizeof(z));
+  if (!o) o = &z;
+  r.precond = o->precond;
+  r.degree = o->cheb_degree ? o->cheb_degree : 4;
+  r.ratio = (o->cheb_ratio != 0.0) ? o->cheb_ratio : 30.0;
+  r.rtol = (o->rtol != 0.0) ? o->rtol : 1e-8;
+  r.max_iter = o->max_iter ? o->max_iter : 20000;
+  r.poll = o->poll_every ? o->poll_every : 16;
+  r.tile_lines = o->tile_lines;
+  r.max_groups = o->max_groups;
+  r.flags = o->flags;
+  if (r.precond != ENS_PRECOND_JACOBI && r.precond != ENS_PRECOND_CHEBYSHEV) return ENS_EINVAL;
+  if (r.degree < 2 || r.degree > kMaxCheb) return ENS_EINVAL;
+  if (!std::isfinite(r.ratio) || r.ratio <= 1.0) return ENS_EINVAL;
+  if (!std::isfinite(r.rtol) || r.rtol < 0.0) return ENS_EINVAL;
+  if (r.max_iter < 1 || r.poll < 1 || r.tile_lines < 0 || r.max_groups < 0) return ENS_EINVAL;
+  if (o->reserved != 0) return ENS_EINVAL;
+  return ENS_OK;
+}
+
+#define HIPCHECK(call)                       \
+  do {                                       \
+    hipError_t e_ = (call);                  \
+    if (e_ != hipSuccess) return set_hip_error(e_); \
+  } while (0)
+
+// One preconditioner application z = p(D^-1 A) D^-1 r: the start step
+// d = z = D^-1 r / theta (already done by the caller when `started`), then
+// degree-1 stencil steps ping-ponging z.  Returns the buffer holding z.
+static double* cheb_apply(const double* V, const Workspace& w, const Geometry& g, int degree,
+                          bool init, bool started, hipStream_t s) {
+  if (!started) launch_cheb_start(V, w.r, w.d, w.z[0], w.m, g, elem_groups(g), s);
+  for (int k = 1; k < degree; ++k) {
+    StencilArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.V = V;
+    a.r = w.r;
+    a.src = w.z[(k - 1) & 1];
+    a.zout = w.z[k & 1];
+    a.d = w.d;
+    a.partial = w.partial;
+    a.m = w.m;
+    a.g = g;
+    a.cheb_step = k;
+    a.cheb_last = (k == degree - 1);
+    a.cheb_init = init ? 1 : 0;
+    launch_stencil<M_CHEB>(a, s);
+  }
+  return w.z[(degree - 1) & 1];
+}
+
+struct SolveOut {
+  int32_t* iters;
+  int32_t* status;
+  double* relres;
+  int32_t* ens_iters;
+  ens_stats* stats;
+};
+
+static int run_solve(const ens_problem* prob, const Opts& o, int S, const double* V, const double* b,
+                     int b_bcast, double* x, const Workspace& w, hipStream_t s, SolveOut out) {
+  const int n = prob->n;
+  const bool cheb = (o.precond == ENS_PRECOND_CHEBYSHEV);
+  const Geometry g = make_geometry(n, S, o.tile_lines, o.max_groups);
+  const int ge = elem_groups(g);
+
+  HIPCHECK(hipMemsetAsync(w.m.ctl, 0, sizeof(int) * CTL_COUNT, s));
+  InitArgs ia;
+  std::memset(&ia, 0, sizeof(ia));
+  ia.V = V;
+  ia.b = b;
+  ia.b_broadcast = b_bcast;
+  ia.x = x;
+  ia.p0 = w.p[0];
+  ia.r = w.r;
+  ia.partial = w.partial;
+  ia.m = w.m;
+  ia.g = g;
+  ia.max_iter = o.max_iter;
+  ia.cheb = cheb ? 1 : 0;
+  ia.cheb_degree = o.degree;
+  ia.cheb_ratio = o.ratio;
+  launch_init(ia, ge, s);
+  double* zfinal = nullptr;
+  if (cheb) zfinal = cheb_apply(V, w, g, o.degree, true, false, s);
+  HIPCHECK(hipGetLastError());
+
+  const bool timing = (o.flags & ENS_FLAG_TIME_SPMV) != 0;
+  std::vector<hipEvent_t> evs;
+  std::vector<int> ev_iter;
+
+  int32_t* flag = nullptr;
+  HIPCHECK(hipHostMalloc((void**)&flag, 2 * sizeof(int32_t), hipHostMallocDefault));
+  hipEvent_t pe[2] = {nullptr, nullptr};
+  int rc = ENS_OK;
+  auto fail = [&](hipError_t e) { rc = set_hip_error(e); };
+  for (int k = 0; k < 2 && rc == ENS_OK; ++k) {
+    hipError_t e = hipEventCreateWithFlags(&pe[k], hipEventDisableTiming);
+    if (e != hipSuccess) fail(e);
+  }
+  int it = 0, slot = 0;
+  bool have_prev = false;
+  while (rc == ENS_OK && it < o.max_iter) {
+    const int chunk = std::min(o.poll, o.max_iter - it);
+    for (int c = 0; c < chunk; ++c) {
+      ++it;
+      StencilArgs a;
+      std::memset(&a, 0, sizeof(a));
+      a.V = V;
+      a.r = w.r;
+      a.src = zfinal;
+      a.pold = w.p[(it + 1) & 1];
+      a.pnew = w.p[it & 1];
+      a.q = w.q;
+      a.x = x;
+      a.partial = w.partial;
+      a.m = w.m;
+      a.g = g;
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (timing && c == 0) {
+        hipError_t e = hipEventCreate(&e0);
+        if (e == hipSuccess) e = hipEventCreate(&e1);
+        if (e != hipSuccess) { fail(e); break; }
+        hipEventRecord(e0, s);
+      }
+      if (cheb) launch_stencil<M_PCG_Z>(a, s);
+      else launch_stencil<M_PCG_J>(a, s);
+      if (e1) {
+        hipEventRecord(e1, s);
+        evs.push_back(e0);
+        evs.push_back(e1);
+        ev_iter.push_back(it);
+      }
+      UpdateArgs u;
+      std::memset(&u, 0, sizeof(u));
+      u.V = V;
+      u.r = w.r;
+      u.q = w.q;
+      u.d = w.d;
+      u.z = w.z[0];
+      u.partial = w.partial;
+      u.m = w.m;
+      u.g = g;
+      u.rtol = o.rtol;
+      launch_update(u, cheb, ge, s);
+      if (cheb) cheb_apply(V, w, g, o.degree, false, true, s);
+    }
+    if (rc != ENS_OK) break;
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&flag[slot], w.m.ctl + CTL_DONE, sizeof(int32_t),
+                                            hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipEventRecord(pe[slot], s);
+    if (e == hipSuccess && have_prev) e = hipEventSynchronize(pe[slot ^ 1]);
+    if (e != hipSuccess) { fail(e); break; }
+    if (have_prev && flag[slot ^ 1]) break;
+    have_prev = true;
+    slot ^= 1;
+  }
+  if (rc == ENS_OK) launch_final(x, w.p[0], w.p[1], w.m, g, ge, s);
+
+  int32_t h_iters[kMaxS], h_status[kMaxS];
+  double h_relres[kMaxS];
+  if (rc == ENS_OK) {
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(h_iters, w.m.iters, sizeof(int32_t) * S, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h_status, w.m.status, sizeof(int32_t) * S, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h_relres, w.m.relres, sizeof(double) * S, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) fail(e);
+  } else {
+    hipStreamSynchronize(s);
+  }
+  int ens_iters = 0;
+  if (rc == ENS_OK) {
+    for (int k = 0; k < S; ++k) ens_iters = std::max(ens_iters, (int)h_iters[k]);
+    if (out.iters) std::memcpy(out.iters, h_iters, sizeof(int32_t) * S);
+    if (out.status) std::memcpy(out.status, h_status, sizeof(int32_t) * S);
+    if (out.relres) std::memcpy(out.relres, h_relres, sizeof(double) * S);
+    if (out.ens_iters) *out.ens_iters = ens_iters;
+  }
+  if (out.stats) {
+    ens_stats st;
+    std::memset(&st, 0, sizeof(st));
+    st.ens_iters = ens_iters;
+    st.spmv_groups = g.groups;
+    st.tile_lines = g.ty;
+    for (size_t k = 0; k < ev_iter.size(); ++k) {
+      if (rc == ENS_OK && ev_iter[k] <= ens_iters) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, evs[2 * k], evs[2 * k + 1]) == hipSuccess) {
+          st.spmv_ms += ms;
+          st.spmv_timed += 1;
+        }
+      }
+    }
+    *out.stats = st;
+  }
+  for (hipEvent_t e : evs) hipEventDestroy(e);
+  for (int k = 0; k < 2; ++k)
+    if (pe[k]) hipEventDestroy(pe[k]);
+  hipHostFree(flag);
+  return rc;
+}
+
+}  // namespace ens
+
+using namespace ens;
+
+extern "C" {
+
+int ens_version(void) { return 100; }
+
+int ens_last_hip_error(void) { return g_last_hip_error; }
+
+const char* ens_strerror(int code) {
+  switch (code) {
+    case ENS_OK: return "ok";
+    case ENS_EINVAL: return "invalid argument";
+    case ENS_ENOMEM: return "workspace too small";
+    case ENS_EHIP: return "HIP runtime error";
+    case ENS_ENOTSUP: return "unsupported";
+    default: return "unknown error";
+  }
+}
+
+int ens_assemble_ensemble(const ens_problem* prob, int32_t S, const double* y_dev, double* V_dev,
+                          double* b_dev, void* stream) {
+  int rc = check_problem(prob);
+  if (rc) return rc;
+  if (!valid_S(S) || !y_dev || !V_dev || !b_dev) return ENS_EINVAL;
+  AsmArgs a;
+  a.y = y_dev;
+  a.V = V_dev;
+  a.b = b_dev;
+  a.n = prob->n;
+  a.S = S;
+  a.logS = log2i(S);
+  a.d = prob->d;
+  a.eps_model = prob->eps_model;
+  a.amp = prob->amp;
+  a.nelem = (size_t)prob->n * prob->n * S;
+  launch_assemble(a, (hipStream_t)stream);
+  HIPCHECK(hipGetLastError());
+  return ENS_OK;
+}
+
+size_t ens_pcg_workspace_bytes(const ens_problem* prob, const ens_opts* opts, int32_t S) {
+  Opts o;
+  if (check_problem(prob) || resolve_opts(opts, o) || !valid_S(S)) return 0;
+  return workspace_bytes(prob->n, S, o.precond == ENS_PRECOND_CHEBYSHEV);
+}
+
+int ens_pcg_solve(const ens_problem* prob, const ens_opts* opts, int32_t S, const double* V_dev,
+                  const double* b_dev, double* x_dev, int32_t* iters_host, int32_t* status_host,
+                  double* relres_host, int32_t* ens_iters_host, ens_stats* stats, void* ws_dev,
+                  size_t ws_bytes, void* stream) {
+  int rc = check_problem(prob);
+  if (rc) return rc;
+  Opts o;
+  rc = resolve_opts(opts, o);
+  if (rc) return rc;
+  if (!valid_S(S) || !V_dev || !b_dev || !x_dev || !ws_dev) return ENS_EINVAL;
+  const bool cheb = o.precond == ENS_PRECOND_CHEBYSHEV;
+  if (ws_bytes < workspace_bytes(prob->n, S, cheb)) return ENS_ENOMEM;
+  const Workspace w = carve(ws_dev, prob->n, S, cheb);
+  SolveOut out{iters_host, status_host, relres_host, ens_iters_host, stats};
+  return run_solve(prob, o, S, V_dev, b_dev, 0, x_dev, w, (hipStream_t)stream, out);
+}
+
+int ens_spmv(const ens_problem* prob, int32_t S, const double* V_dev, const double* p_dev,
+             double* q_dev, void* stream) {
+  int rc = check_problem(prob);
+  if (rc) return rc;
+  if (!valid_S(S) || !V_dev || !p_dev || !q_dev) return ENS_EINVAL;
+  StencilArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.V = V_dev;
+  a.src = p_dev;
+  a.q = q_dev;
+  a.g = make_geometry(prob->n, S, 0, 0);
+  launch_stencil<M_SPMV>(a, (hipStream_t)stream);
+  HIPCHECK(hipGetLastError());
+  return ENS_OK;
+}
+
+int ens_cheb_apply(const ens_problem* prob, const ens_opts* opts, int32_t S, const double* V_dev,
+                   const double* r_dev, double* z_dev, double* lmax_host, void* ws_dev,
+                   size_t ws_bytes, void* stream) {
+  int rc = check_problem(prob);
+  if (rc) return rc;
+  Opts o;
+  rc = resolve_opts(opts, o);
+  if (rc) return rc;
+  if (!valid_S(S) || !V_dev || !r_dev || !z_dev || !ws_dev) return ENS_EINVAL;
+  if (ws_bytes < workspace_bytes(prob->n, S, true)) return ENS_ENOMEM;
+  const Workspace w = carve(ws_dev, prob->n, S, true);
+  const Geometry g = make_geometry(prob->n, S, o.tile_lines, o.max_groups);
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHECK(hipMemsetAsync(w.m.ctl, 0, sizeof(int) * CTL_COUNT, s));
+  InitArgs ia;
+  std::memset(&ia, 0, sizeof(ia));
+  ia.V = V_dev;
+  ia.b = r_dev;
+  ia.x = w.aux;
+  ia.p0 = w.p[0];
+  ia.r = w.r;
+  ia.partial = w.partial;
+  ia.m = w.m;
+  ia.g = g;
+  ia.max_iter = 1;
+  ia.cheb = 1;
+  ia.cheb_degree = o.degree;
+  ia.cheb_ratio = o.ratio;
+  launch_init(ia, elem_groups(g), s);
+  // every member is preconditioned, whatever its residual: clear the done
+  // flag the initialisation raises when all members have r = 0
+  HIPCHECK(hipMemsetAsync(w.m.ctl + CTL_DONE, 0, sizeof(int), s));
+  double* zf = cheb_apply(V_dev, w, g, o.degree, true, false, s);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipMemcpyAsync(z_dev, zf, sizeof(double) * g.nelem, hipMemcpyDeviceToDevice, s));
+  double lm[kMaxS];
+  HIPCHECK(hipMemcpyAsync(lm, w.m.lmax, sizeof(double) * S, hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  if (lmax_host) std::memcpy(lmax_host, lm, sizeof(double) * S);
+  return ENS_OK;
+}
+
+int ens_member_dot(int32_t N_r, int32_t S, const double* a_dev, const double* b_dev,
+                   int32_t b_broadcast, double* out_host, void* ws_dev, size_t ws_bytes,
+                   void* stream) {
+  if (N_r < 1 || !valid_S(S) || !a_dev || !b_dev || !out_host || !ws_dev) return ENS_EINVAL;
+  if (ws_bytes < header_bytes()) return ENS_ENOMEM;
+  const Workspace w = carve(ws_dev, 0, S, false);
+  Geometry g = make_geometry(2, S, 0, 0);
+  g.nr = (size_t)N_r;
+  g.nelem = (size_t)N_r * S;
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHECK(hipMemsetAsync(w.m.ctl, 0, sizeof(int) * CTL_COUNT, s));
+  launch_dot(a_dev, b_dev, b_broadcast ? 1 : 0, w.partial, w.m.result, w.m.ctl + CTL_CTR_A, g,
+             elem_groups(g), s);
+  HIPCHECK(hipGetLastError());
+  double res[kMaxS];
+  HIPCHECK(hipMemcpyAsync(res, w.m.result, sizeof(double) * S, hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  std::memcpy(out_host, res, sizeof(double) * S);
+  return ENS_OK;
+}
+
+int ens_dqdy(const ens_problem* prob, int32_t S, const double* y_dev, const double* u_dev,
+             const double* lambda_dev, double* grad_host, void* ws_dev, size_t ws_bytes,
+             void* stream) {
+  int rc = check_problem(prob);
+  if (rc) return rc;
+  if (!valid_S(S) || !y_dev || !u_dev || !lambda_dev || !grad_host || !ws_dev) return ENS_EINVAL;
+  if (ws_bytes < header_bytes()) return ENS_ENOMEM;
+  const Workspace w = carve(ws_dev, 0, S, false);
+  const Geometry g = make_geometry(prob->n, S, 0, 0);
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHECK(hipMemsetAsync(w.m.ctl, 0, sizeof(int) * CTL_COUNT, s));
+  DqdyArgs a;
+  a.y = y_dev;
+  a.u = u_dev;
+  a.lam = lambda_dev;
+  a.partial = w.partial;
+  a.result = w.m.result;
+  a.ctr = w.m.ctl + CTL_CTR_A;
+  a.g = g;
+  a.d = prob->d;
+  a.eps_model = prob->eps_model;
+  a.amp = prob->amp;
+  // the partial buffer holds 3 * kMaxGroups * kMaxS doubles; d <= 16 rows of
+  // groups * S partials fit for groups <= 3 * kMaxGroups / 16
+  const int groups = std::min(elem_groups(g), 3 * kMaxGroups / 16);
+  launch_dqdy(a, groups, s);
+  HIPCHECK(hipGetLastError());
+  double res[kMaxS * 16];
+  HIPCHECK(hipMemcpyAsync(res, w.m.result, sizeof(double) * S * 16, hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  for (int k = 0; k < S; ++k)
+    for (int j = 0; j < prob->d; ++j) grad_host[(size_t)k * prob->d + j] = res[k * 16 + j];
+  return ENS_OK;
+}
+
+int ens_adjoint_grad(const ens_problem* prob, const ens_opts* opts, int32_t S, const double* y_dev,
+                     const double* V_dev, const double* u_dev, const double* w_dev,
+                     double* lambda_dev, double* grad_host, int32_t* iters_host,
+                     int32_t* status_host, void* ws_dev, size_t ws_bytes, void* stream) {
+  int rc = check_problem(prob);
+  if (rc) return rc;
+  Opts o;
+  rc = resolve_opts(opts, o);
+  if (rc) return rc;
+  if (!valid_S(S) || !y_dev || !V_dev || !u_dev || !w_dev || !lambda_dev || !grad_host || !ws_dev)
+    return ENS_EINVAL;
+  const bool cheb = o.precond == ENS_PRECOND_CHEBYSHEV;
+  if (ws_bytes < workspace_bytes(prob->n, S, cheb)) return ENS_ENOMEM;
+  const Workspace w = carve(ws_dev, prob->n, S, cheb);
+  SolveOut out{iters_host, status_host, nullptr, nullptr, nullptr};
+  rc = run_solve(prob, o, S, V_dev, w_dev, 1, lambda_dev, w, (hipStream_t)stream, out);
+  if (rc) return rc;
+  return ens_dqdy(prob, S, y_dev, u_dev, lambda_dev, grad_host, ws_dev, ws_bytes, stream);
+}
+
+}  // extern "C"

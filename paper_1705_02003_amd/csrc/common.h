@@ -1,0 +1,158 @@
+// Internal definitions shared by the HIP translation units of libens.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "ens.h"
+
+namespace ens {
+
+constexpr int kNT = 256;          // threads per workgroup (4 wave64s)
+constexpr int kWaves = kNT / 64;
+constexpr int kMaxS = 64;
+constexpr int kMaxGroups = 2048;  // cap on workgroups of reducing kernels
+constexpr int kRing = 2 * kNT + 2 * kMaxS;  // doubles per LDS ring line (tile + halo)
+constexpr int kMaxCheb = 8;       // maximum Chebyshev degree
+constexpr int kChebCoef = 2 * kMaxCheb + 2;
+
+// control words (int32) in the workspace
+enum Ctl : int {
+  CTL_DONE = 0,   // 1 when no member is active
+  CTL_K = 1,      // completed iterations
+  CTL_CTR_A = 2,  // last-block counters (one per reducing kernel kind)
+  CTL_CTR_B = 3,
+  CTL_CTR_C = 4,
+  CTL_CTR_D = 5,
+  CTL_MAXIT = 6,  // iteration cap (copied from the options)
+  CTL_COUNT = 16
+};
+
+// Per-member state of one ensemble solve (device arrays of length S).
+struct Members {
+  double* rho;         // r^T z
+  double* alpha;       // step of the current iteration (0 if inactive)
+  double* alpha_prev;  // step still to be applied to x (deferred update)
+  double* beta;        // direction update coefficient (0 if inactive)
+  double* bnorm;       // ||b||
+  double* relres;      // ||r|| / ||b|| of the latest residual
+  double* lmax;        // Gershgorin bound of D^-1 A
+  double* cheb;        // [S][kChebCoef] Chebyshev coefficients
+  double* result;      // [S][16] scratch results of member reductions
+  int* active;
+  int* iters;
+  int* status;
+  int* ctl;            // control words
+};
+
+struct Workspace {
+  double* p[2];   // search directions (ping-pong)
+  double* q;      // A p
+  double* r;      // residual
+  double* z[2];   // preconditioned residual (Chebyshev ping-pong)
+  double* d;      // Chebyshev increment
+  double* aux;    // one extra vector (adjoint right-hand side)
+  double* partial;  // [3][kMaxGroups][S]
+  Members m;
+};
+
+struct Geometry {
+  int n, S, logS, vec, tpp;  // tpp: threads per grid point
+  int tx, ty;                // tile: points per line chunk, lines per band
+  int nchunk, nband, ntiles, groups;
+  size_t nr, nelem;          // rows, rows * S
+};
+
+
+// ------------------------------------------------------------ kernel args
+struct AsmArgs {
+  const double* y;  // [S][d]
+  double* V;        // [9][N_r][S]
+  double* b;        // [N_r][S]
+  int n, S, logS, d, eps_model;
+  double amp;
+  size_t nelem;
+};
+
+enum Mode { M_SPMV = 0, M_PCG_J = 1, M_PCG_Z = 2, M_CHEB = 3 };
+
+struct StencilArgs {
+  const double* V;
+  const double* r;
+  const double* src;   // ring source: p (SPMV), z (PCG_Z direction source, CHEB)
+  const double* pold;  // previous direction (PCG)
+  double* pnew;        // new direction (PCG)
+  double* q;           // A p (PCG, SPMV)
+  double* x;           // solution, deferred update (PCG)
+  double* d;           // Chebyshev increment
+  double* zout;        // Chebyshev output z
+  double* partial;     // [groups][S]
+  Members m;
+  Geometry g;
+  int cheb_step;       // Chebyshev step 1..deg-1
+  int cheb_last;       // 1 on the final step of a preconditioner application
+  int cheb_init;       // 1 when the application yields the initial rho
+};
+
+struct UpdateArgs {
+  const double* V;
+  double* r;
+  const double* q;
+  double* d;        // Chebyshev: D^-1 r / theta
+  double* z;        // Chebyshev: z = d
+  double* partial;  // [2][groups][S]: r^T z (Jacobi), r^T r
+  Members m;
+  Geometry g;
+  double rtol;
+};
+
+struct InitArgs {
+  const double* V;
+  const double* b;
+  int b_broadcast;   // b is one vector [N_r] shared by all members
+  double* x;
+  double* p0;
+  double* r;
+  double* partial;   // [3][groups][S]: r^T z, b^T b, Gershgorin max
+  Members m;
+  Geometry g;
+  int max_iter;
+  int cheb;          // 1: Chebyshev preconditioner (Gershgorin bound, coefficients)
+  int cheb_degree;
+  double cheb_ratio;
+};
+
+struct DqdyArgs {
+  const double* y;   // [S][d]
+  const double* u;   // [N_r][S]
+  const double* lam; // [N_r][S]
+  double* partial;   // [d][groups][S]
+  double* result;    // [S][16]
+  int* ctr;
+  Geometry g;
+  int d, eps_model;
+  double amp;
+};
+
+// ------------------------------------------------------------ launchers
+void launch_assemble(const AsmArgs& a, hipStream_t s);
+template <int MODE>
+void launch_stencil(const StencilArgs& a, hipStream_t s);
+void launch_update(const UpdateArgs& a, bool cheb, int groups, hipStream_t s);
+void launch_init(const InitArgs& a, int groups, hipStream_t s);
+void launch_cheb_start(const double* V, const double* r, double* d, double* z, const Members& m,
+                       const Geometry& g, int groups, hipStream_t s);
+void launch_final(double* x, const double* p0, const double* p1, const Members& m,
+                  const Geometry& g, int groups, hipStream_t s);
+void launch_dot(const double* x, const double* y, int y_bcast, double* partial, double* out,
+                int* ctr, const Geometry& g, int groups, hipStream_t s);
+void launch_dqdy(const DqdyArgs& a, int groups, hipStream_t s);
+
+size_t workspace_bytes(int n, int S, bool cheb);
+Geometry make_geometry(int n, int S, int tile_lines, int max_groups);
+int set_hip_error(hipError_t e);
+int valid_S(int S);
+
+}  // namespace ens

@@ -1,0 +1,239 @@
+"""Python front end of libens: torch tensors in, torch tensors out.
+
+Every operation is a call into the HIP library (include/ens.h); this module
+only checks shapes and dtypes, allocates outputs and workspaces with torch,
+and passes pointers and the current HIP stream.  There is no fallback: if the
+library is missing or no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import NamedTuple, Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+@dataclass(frozen=True)
+class Problem:
+    """-div(a(x) K(y) grad u) = 1 on an n x n interior grid; see ens_problem."""
+
+    n: int
+    d: int
+    eps_model: int = 0
+    amp: float = 0.0
+
+    @property
+    def rows(self) -> int:
+        return self.n * self.n
+
+    def c(self) -> L.ens_problem:
+        return L.ens_problem(self.n, self.d, self.eps_model, 0, float(self.amp))
+
+
+@dataclass
+class SolverOptions:
+    precond: str = "jacobi"       # "jacobi" or "chebyshev"
+    cheb_degree: int = 4
+    cheb_ratio: float = 30.0
+    rtol: float = 1e-8
+    max_iter: int = 20000
+    poll_every: int = 16
+    tile_lines: int = 0           # 0: heuristic
+    max_groups: int = 0           # 0: heuristic
+    time_spmv: bool = False
+
+    def c(self) -> L.ens_opts:
+        pre = {"jacobi": L.PRECOND_JACOBI, "chebyshev": L.PRECOND_CHEBYSHEV}[self.precond]
+        return L.ens_opts(pre, self.cheb_degree, float(self.cheb_ratio), float(self.rtol),
+                          self.max_iter, self.poll_every, self.tile_lines, self.max_groups,
+                          L.FLAG_TIME_SPMV if self.time_spmv else 0, 0)
+
+
+class SolveResult(NamedTuple):
+    x: torch.Tensor          # (N_r, S)
+    iters: np.ndarray        # (S,) int32
+    status: np.ndarray       # (S,) int32
+    relres: np.ndarray       # (S,) float64
+    ens_iters: int           # max_s iters_s
+    stats: dict
+
+
+def _require_cuda(t: torch.Tensor, name: str, shape=None, dtype=torch.float64):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def _p(t: torch.Tensor) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(dev: torch.device) -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _ensemble_width(t: torch.Tensor) -> int:
+    return int(t.shape[-1])
+
+
+def workspace(prob: Problem, S: int, opts: Optional[SolverOptions] = None,
+              device=None) -> torch.Tensor:
+    """A device workspace large enough for solve / adjoint_grad / cheb_apply."""
+    opts = opts or SolverOptions()
+    o = opts.c()
+    pc = prob.c()
+    nb = L.lib().ens_pcg_workspace_bytes(C.byref(pc), C.byref(o), S)
+    if opts.precond == "jacobi":
+        # cheb_apply needs the Chebyshev layout; size for the larger one
+        o2 = SolverOptions(precond="chebyshev").c()
+        nb = max(nb, L.lib().ens_pcg_workspace_bytes(C.byref(pc), C.byref(o2), S))
+    if nb == 0:
+        raise ValueError("invalid problem / options / ensemble width")
+    return torch.empty(nb, dtype=torch.uint8, device=device or "cuda")
+
+
+def assemble(prob: Problem, y: torch.Tensor):
+    """Ensemble matrix V (9, N_r, S) and right-hand side b (N_r, S) for y (S, d)."""
+    _require_cuda(y, "y")
+    S = int(y.shape[0])
+    if y.dim() != 2 or y.shape[1] != prob.d:
+        raise ValueError(f"y must have shape (S, {prob.d})")
+    V = torch.empty((9, prob.rows, S), dtype=torch.float64, device=y.device)
+    b = torch.empty((prob.rows, S), dtype=torch.float64, device=y.device)
+    pc = prob.c()
+    L.check(L.lib().ens_assemble_ensemble(C.byref(pc), S, _p(y), _p(V), _p(b), _stream(y.device)),
+            "ens_assemble_ensemble")
+    return V, b
+
+
+def solve(prob: Problem, V: torch.Tensor, b: torch.Tensor, opts: Optional[SolverOptions] = None,
+          x: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None) -> SolveResult:
+    """Ensemble PCG for every member; blocks until the counts are known."""
+    opts = opts or SolverOptions()
+    S = _ensemble_width(b)
+    _require_cuda(V, "V", (9, prob.rows, S))
+    _require_cuda(b, "b", (prob.rows, S))
+    if x is None:
+        x = torch.empty_like(b)
+    _require_cuda(x, "x", (prob.rows, S))
+    if ws is None:
+        ws = workspace(prob, S, opts, V.device)
+    _require_cuda(ws, "ws", dtype=torch.uint8)
+    iters = np.zeros(S, np.int32)
+    status = np.zeros(S, np.int32)
+    relres = np.zeros(S, np.float64)
+    ens_iters = C.c_int32(0)
+    stats = L.ens_stats()
+    pc, oc = prob.c(), opts.c()
+    L.check(L.lib().ens_pcg_solve(
+        C.byref(pc), C.byref(oc), S, _p(V), _p(b), _p(x),
+        iters.ctypes.data_as(L.i32p), status.ctypes.data_as(L.i32p),
+        relres.ctypes.data_as(L.f64p), C.byref(ens_iters), C.byref(stats),
+        _p(ws), ws.numel(), _stream(V.device)), "ens_pcg_solve")
+    st = {"ens_iters": stats.ens_iters, "spmv_timed": stats.spmv_timed,
+          "spmv_ms": stats.spmv_ms, "spmv_groups": stats.spmv_groups,
+          "tile_lines": stats.tile_lines}
+    return SolveResult(x, iters, status, relres, int(ens_iters.value), st)
+
+
+def spmv(prob: Problem, V: torch.Tensor, p: torch.Tensor) -> torch.Tensor:
+    S = _ensemble_width(p)
+    _require_cuda(V, "V", (9, prob.rows, S))
+    _require_cuda(p, "p", (prob.rows, S))
+    q = torch.empty_like(p)
+    pc = prob.c()
+    L.check(L.lib().ens_spmv(C.byref(pc), S, _p(V), _p(p), _p(q), _stream(p.device)), "ens_spmv")
+    return q
+
+
+def cheb_apply(prob: Problem, V: torch.Tensor, r: torch.Tensor,
+               opts: Optional[SolverOptions] = None, ws: Optional[torch.Tensor] = None):
+    """z = M^-1 r for the Chebyshev preconditioner; returns (z, lambda_max per member)."""
+    opts = opts or SolverOptions(precond="chebyshev")
+    S = _ensemble_width(r)
+    _require_cuda(V, "V", (9, prob.rows, S))
+    _require_cuda(r, "r", (prob.rows, S))
+    if ws is None:
+        ws = workspace(prob, S, SolverOptions(precond="chebyshev"), r.device)
+    z = torch.empty_like(r)
+    lmax = np.zeros(S, np.float64)
+    pc, oc = prob.c(), opts.c()
+    L.check(L.lib().ens_cheb_apply(C.byref(pc), C.byref(oc), S, _p(V), _p(r), _p(z),
+                                   lmax.ctypes.data_as(L.f64p), _p(ws), ws.numel(),
+                                   _stream(r.device)), "ens_cheb_apply")
+    return z, lmax
+
+
+def member_dot(a: torch.Tensor, b: torch.Tensor, ws: Optional[torch.Tensor] = None) -> np.ndarray:
+    """Per-member dot products; b may be (N_r, S) or a shared (N_r,) vector."""
+    S = _ensemble_width(a)
+    Nr = int(a.shape[0])
+    _require_cuda(a, "a", (Nr, S))
+    bcast = b.dim() == 1
+    _require_cuda(b, "b", (Nr,) if bcast else (Nr, S))
+    if ws is None:
+        ws = workspace(Problem(2, 2), S, None, a.device)
+    out = np.zeros(S, np.float64)
+    L.check(L.lib().ens_member_dot(Nr, S, _p(a), _p(b), 1 if bcast else 0,
+                                   out.ctypes.data_as(L.f64p), _p(ws), ws.numel(),
+                                   _stream(a.device)), "ens_member_dot")
+    return out
+
+
+def dqdy(prob: Problem, y: torch.Tensor, u: torch.Tensor, lam: torch.Tensor,
+         ws: Optional[torch.Tensor] = None) -> np.ndarray:
+    """-lambda^T (dA/dy_j) u per member, shape (S, d)."""
+    S = int(y.shape[0])
+    _require_cuda(y, "y", (S, prob.d))
+    _require_cuda(u, "u", (prob.rows, S))
+    _require_cuda(lam, "lam", (prob.rows, S))
+    if ws is None:
+        ws = workspace(Problem(2, 2), S, None, y.device)
+    g = np.zeros((S, prob.d), np.float64)
+    pc = prob.c()
+    L.check(L.lib().ens_dqdy(C.byref(pc), S, _p(y), _p(u), _p(lam), g.ctypes.data_as(L.f64p),
+                             _p(ws), ws.numel(), _stream(y.device)), "ens_dqdy")
+    return g
+
+
+def adjoint_grad(prob: Problem, y: torch.Tensor, V: torch.Tensor, u: torch.Tensor,
+                 w: torch.Tensor, opts: Optional[SolverOptions] = None,
+                 ws: Optional[torch.Tensor] = None):
+    """(lambda, dQ/dy (S, d), iters, status) for Q = w^T u."""
+    opts = opts or SolverOptions()
+    S = int(y.shape[0])
+    _require_cuda(y, "y", (S, prob.d))
+    _require_cuda(V, "V", (9, prob.rows, S))
+    _require_cuda(u, "u", (prob.rows, S))
+    _require_cuda(w, "w", (prob.rows,))
+    if ws is None:
+        ws = workspace(prob, S, opts, y.device)
+    lam = torch.empty_like(u)
+    g = np.zeros((S, prob.d), np.float64)
+    iters = np.zeros(S, np.int32)
+    status = np.zeros(S, np.int32)
+    pc, oc = prob.c(), opts.c()
+    L.check(L.lib().ens_adjoint_grad(
+        C.byref(pc), C.byref(oc), S, _p(y), _p(V), _p(u), _p(w), _p(lam),
+        g.ctypes.data_as(L.f64p), iters.ctypes.data_as(L.i32p), status.ctypes.data_as(L.i32p),
+        _p(ws), ws.numel(), _stream(y.device)), "ens_adjoint_grad")
+    return lam, g, iters, status
+
+
+def qoi_weights(n: int, device=None) -> torch.Tensor:
+    """Mean over the interior nodes of [0.4, 0.6]^2 (decided in integers:
+    2(n+1) <= 5 i <= 3(n+1) for the 1-based node index i, same for j)."""
+    i = np.arange(1, n + 1)
+    inside = (5 * i >= 2 * (n + 1)) & (5 * i <= 3 * (n + 1))
+    m = np.outer(inside, inside).reshape(-1)
+    w = np.where(m, 1.0 / m.sum(), 0.0)
+    return torch.tensor(w, dtype=torch.float64, device=device or "cuda")

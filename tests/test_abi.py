@@ -1,0 +1,163 @@
+"""The C ABI without a GPU: loading, exported symbols, host-side sparse-grid
+calls bit-exact with the oracle, and argument validation (no device work)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import sparse_grid as sg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1705_02003_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1705_02003_amd import build
+        build.build()
+    _lib.lib()
+    return _lib
+
+
+def header_symbols():
+    src = open(os.path.join(ROOT, "include", "ens.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ens_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(L):
+    syms = header_symbols()
+    assert len(syms) >= 14
+    cdll = C.CDLL(L.LIB_PATH)
+    for s in syms:
+        assert hasattr(cdll, s), s
+        assert s in L.SIGNATURES, s
+    assert set(L.SIGNATURES) == set(syms)
+    assert L.lib().ens_version() >= 100
+    assert L.lib().ens_strerror(-1) == b"invalid argument"
+
+
+def nodes_to_arrays(nodes):
+    lv = np.array([[l for l, _ in nd] for nd in nodes], np.int32)
+    ix = np.array([[k for _, k in nd] for nd in nodes], np.int32)
+    return lv, ix
+
+
+def adaptive_like_grid(d, L_, keep, seed):
+    """A full grid with a random subset of its top levels removed (keeps
+    every node's ancestors only partially, like an adaptive grid)."""
+    rng = np.random.default_rng(seed)
+    g = sg.full_grid(d, L_)
+    return [nd for nd in g if sg.total_level(nd) <= 1 or rng.random() < keep]
+
+
+@pytest.mark.parametrize("d,Lv,S,seed", [(2, 5, 8, 0), (4, 4, 16, 1), (4, 5, 32, 2), (8, 2, 32, 3), (3, 3, 4, 4)])
+def test_group_samples_bit_exact_with_oracle(L, d, Lv, S, seed):
+    from paper_1705_02003_amd import grouping
+    rng = np.random.default_rng(seed)
+    nodes = adaptive_like_grid(d, Lv, 0.7, seed)
+    vals = rng.integers(50, 3000, len(nodes)).astype(float)      # iteration counts
+    y_new = rng.uniform(-1, 1, (123, d))
+    g_o, p_o = sg.group_samples(nodes, vals, y_new, S)
+    lv, ix = nodes_to_arrays(nodes)
+    g_c, p_c = grouping.group_samples(lv, ix, vals, y_new, S)
+    assert np.array_equal(np.asarray(g_o), g_c)
+    assert np.array_equal(p_o, p_c)        # bitwise
+    # non-integer node values too (fixed evaluation order on both sides)
+    vals2 = rng.standard_normal(len(nodes)) * 1e3
+    g_o2, p_o2 = sg.group_samples(nodes, vals2, y_new, S)
+    g_c2, p_c2 = grouping.group_samples(lv, ix, vals2, y_new, S)
+    assert np.array_equal(np.asarray(g_o2), g_c2) and np.array_equal(p_o2, p_c2)
+
+
+def test_group_samples_natural_order_and_padding(L):
+    from paper_1705_02003_amd import grouping
+    g, p = grouping.group_samples(None, None, None, np.zeros((9, 4)), 4)
+    assert g.tolist() == [[0, 1, 2, 3], [4, 5, 6, 7], [8, 8, 8, 8]] and not p.any()
+
+
+@pytest.mark.parametrize("d,Lv,seed", [(2, 5, 0), (4, 5, 1), (8, 2, 2)])
+def test_surpluses_and_coords_bit_exact(L, d, Lv, seed):
+    from paper_1705_02003_amd import grouping
+    rng = np.random.default_rng(seed)
+    nodes = adaptive_like_grid(d, Lv, 0.6, seed)
+    perm = rng.permutation(len(nodes))
+    nodes = [nodes[i] for i in perm]                  # any input order
+    vals = rng.standard_normal(len(nodes))
+    lv, ix = nodes_to_arrays(nodes)
+    c = grouping.surpluses(lv, ix, vals)
+    co = sg.surpluses(nodes, vals)
+    assert np.array_equal(c, np.array([co[nd] for nd in nodes]))
+    assert np.array_equal(grouping.coords(lv, ix), np.array([sg.coords(nd) for nd in nodes]))
+
+
+@pytest.mark.parametrize("d,seed,tau,budget", [(2, 0, 1e-3, 10**6), (4, 1, 1e-3, 60), (4, 2, 0.05, 10**6), (3, 3, 0.0, 40)])
+def test_refine_matches_oracle(L, d, seed, tau, budget):
+    from paper_1705_02003_amd import grouping
+    rng = np.random.default_rng(seed)
+    nodes = sg.full_grid(d, 1)
+    level = 1
+    for _ in range(3):
+        vals = [1.0 + float(np.sin(3 * sg.coords(nd)).sum()) + 0.1 * rng.random() for nd in nodes]
+        new_o = sg.refine(nodes, vals, level, tau, budget)
+        lv, ix = nodes_to_arrays(nodes)
+        nl, ni = grouping.refine(lv, ix, vals, level, tau, budget)
+        assert [tuple(zip(a, b)) for a, b in zip(nl.tolist(), ni.tolist())] == \
+               [tuple(nd) for nd in new_o]
+        if not new_o:
+            break
+        nodes = nodes + new_o
+        level += 1
+
+
+def test_initial_grid(L):
+    from paper_1705_02003_amd import grouping
+    lv, ix = grouping.initial_grid(4)
+    assert len(lv) == 9
+    got = sorted(tuple(zip(a, b)) for a, b in zip(lv.tolist(), ix.tolist()))
+    assert got == sorted(tuple(nd) for nd in sg.full_grid(4, 1))
+
+
+def test_cost_ratio_matches_oracle(L):
+    from paper_1705_02003_amd import grouping
+    rng = np.random.default_rng(3)
+    its = rng.integers(10, 900, 37)
+    for S in (4, 8, 16, 32):
+        g = grouping.chunk(list(rng.permutation(37)), S)
+        assert grouping.cost_ratio(g, its, S) == sg.ratio_R(g.tolist(), list(its), S)
+
+
+def test_argument_validation_without_gpu(L):
+    lib = L.lib()
+    lvl = np.array([[3, 0]], np.int32)
+    idx = np.array([[9, 0]], np.int32)                 # level 3 has indices 0..3
+    out = np.zeros(2)
+    rc = lib.ens_sg_coords(2, 1, lvl.ctypes.data_as(L.i32p), idx.ctypes.data_as(L.i32p),
+                           out.ctypes.data_as(L.f64p))
+    assert rc == L.ENS_EINVAL
+    dup_l = np.zeros((2, 2), np.int32)
+    rc = lib.ens_sg_surpluses(2, 2, dup_l.ctypes.data_as(L.i32p), dup_l.ctypes.data_as(L.i32p),
+                              np.ones(2).ctypes.data_as(L.f64p), np.zeros(2).ctypes.data_as(L.f64p))
+    assert rc == L.ENS_EINVAL
+    prob = L.ens_problem(64, 2, 0, 0, 0.0)
+    opts = L.ens_opts()
+    assert lib.ens_pcg_workspace_bytes(C.byref(prob), C.byref(opts), 3) == 0      # S not a power of 2
+    assert lib.ens_pcg_workspace_bytes(C.byref(prob), C.byref(opts), 128) == 0
+    assert lib.ens_pcg_workspace_bytes(C.byref(prob), C.byref(opts), 32) > 64 * 64 * 32 * 8 * 5
+    bad = L.ens_problem(1, 2, 0, 0, 0.0)
+    assert lib.ens_pcg_workspace_bytes(C.byref(bad), C.byref(opts), 8) == 0
+    # null pointers and bad sizes are rejected before any device call
+    rc = lib.ens_pcg_solve(C.byref(prob), C.byref(opts), 8, None, None, None, None, None, None,
+                           None, None, None, 0, None)
+    assert rc == L.ENS_EINVAL
+    rc = lib.ens_assemble_ensemble(C.byref(prob), 6, C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), None)
+    assert rc == L.ENS_EINVAL
+    opts_bad = L.ens_opts(5, 0, 0.0, 0.0, 0, 0, 0, 0, 0, 0)
+    assert lib.ens_pcg_workspace_bytes(C.byref(prob), C.byref(opts_bad), 8) == 0
+    # a too-small workspace is ENS_ENOMEM, still before any device work
+    rc = lib.ens_pcg_solve(C.byref(prob), C.byref(opts), 8, C.c_void_p(256), C.c_void_p(256),
+                           C.c_void_p(256), None, None, None, None, None, C.c_void_p(256), 1024, None)
+    assert rc == L.ENS_ENOMEM
