@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Benchmark of the ensemble-PCG hot path on one MI355X.
+
+Workload: -div(a(x) K(y) grad u) = 1 on a 512 x 512 interior grid (262,144
+unknowns), nine-point scheme, FP64, d = 4 parameters (anisotropy, angle, two
+a(x) modes, amp 0.4); samples are the nodes of an adaptive piecewise-linear
+sparse grid, levels 1-5, 1024-sample budget, refined on G(y) = ||u||^2;
+ensembles of S = 32 grouped by the sparse-grid surrogate of iteration counts;
+Jacobi-PCG, rtol 1e-8.  One step = the whole adaptive pass: per level,
+grouping, ensemble assembly, ensemble PCG solves, G(y), refinement.
+
+Prints one JSON line.  `value` is sample-solves/s of the whole pass (real
+samples / wall time of the step, inputs generated on the device).
+`roofline` is for the dominant kernel, the fused direction-update + SpMV
+kernel, timed live with HIP events on the solver's stream.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N_GRID = 512
+D = 4
+AMP = 0.4
+RTOL = 1e-8
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per member-row per call of the fused kernel: reads the
+# nine matrix values, r, p_old, x; writes p, q, x (15 FP64 words)
+FUSED_BYTES = 15 * 8
+# per member-row per Jacobi-PCG iteration (fused kernel + update kernel)
+ITER_BYTES = 19 * 8
+
+
+# ------------------------------------------------------------ CPU baseline
+def _oracle_one(y):
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(1):
+        import numpy as np
+        from oracle import pcg, problem
+        A, b, diag = problem.assemble(np.asarray(y), N_GRID, 0, AMP)
+        t = time.perf_counter()
+        _, I, st, _ = pcg.pcg(A, b, diag, RTOL, 20000)
+        return time.perf_counter() - t, int(I), int(st)
+
+
+def cpu_baseline(procs: int):
+    """The oracle (per-sample Jacobi-PCG) on the workload's first samples in
+    generation order: the level-1 grid (centre and the 2d axis end points),
+    then level-2 nodes in canonical order, one sample per process."""
+    from oracle import sparse_grid as sg
+    first = [sg.coords(nd) for nd in sg.full_grid(D, 1)]
+    first += [sg.coords(nd) for nd in sg.full_grid(D, 2) if sg.total_level(nd) == 2]
+    ys = first[:procs]
+    ctx = mp.get_context("fork")          # no GPU state exists yet in this process
+    t0 = time.perf_counter()
+    with ctx.Pool(procs) as pool:
+        out = pool.map(_oracle_one, ys)
+    wall = time.perf_counter() - t0
+    its = [o[1] for o in out]
+    return {
+        "value": round(len(ys) / wall, 4),
+        "unit": "sample-solves/s",
+        "cores": procs,
+        "kind": "oracle",
+        "sample": (f"{len(ys)} samples (level-1 grid then level-2 nodes, generation order), "
+                   f"one FP64 scipy Jacobi-PCG solve per process at {N_GRID}x{N_GRID}, "
+                   f"rtol {RTOL}; iterations {min(its)}-{max(its)}; wall {wall:.1f} s"),
+    }
+
+
+# ------------------------------------------------------------ GPU parts
+def s1_comparison(res, S, opts, n_groups=2):
+    """Solve the samples of the last level's first ensembles alone (S = 1) and
+    as the S-wide ensembles they belong to; same samples, same GPU."""
+    import numpy as np
+    import torch
+    from paper_1705_02003_amd import ensemble as E
+    lvl = res.levels[-1]
+    offset = sum(r.n_samples for r in res.levels[:-1])
+    groups = lvl.groups[:n_groups]
+    ys = res.y[offset:offset + lvl.n_samples]
+    prob = E.Problem(N_GRID, D, 0, AMP)
+    ws1 = E.workspace(prob, 1, opts)
+    wsS = E.workspace(prob, S, opts)
+    ids = sorted(set(int(i) for g in groups for i in g))
+
+    def run_S():
+        for g in groups:
+            V, b = E.assemble(prob, torch.tensor(ys[g], dtype=torch.float64, device="cuda"))
+            E.solve(prob, V, b, opts, ws=wsS)
+
+    def run_1():
+        its = []
+        for i in ids:
+            V, b = E.assemble(prob, torch.tensor(ys[i:i + 1], dtype=torch.float64, device="cuda"))
+            its.append(E.solve(prob, V, b, opts, ws=ws1).iters[0])
+        return its
+
+    run_1()                                   # warm the S = 1 path
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    run_S()
+    torch.cuda.synchronize()
+    tS = time.perf_counter() - t
+    t = time.perf_counter()
+    its1 = run_1()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter() - t
+    return {"samples": len(ids), "S": S, "seconds_S": round(tS, 4), "seconds_S1": round(t1, 4),
+            "sample_solves_per_s_S": round(len(ids) / tS, 3),
+            "sample_solves_per_s_S1": round(len(ids) / t1, 3),
+            "speedup_vs_S1": round(t1 / tS, 3),
+            "iters_S1": [int(min(its1)), int(max(its1))]}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--S", type=int, default=32)
+    ap.add_argument("--budget", type=int, default=1024)
+    ap.add_argument("--cpu-procs", type=int, default=0, help="0: min(16, cpu count)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-s1", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build runs the ensemble solver on a "
+              "single MI355X (ensembles are independent; see the design notes for how the "
+              "path would shard). Run with --gpus 1.", file=sys.stderr)
+        return 2
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        procs = args.cpu_procs or min(16, os.cpu_count() or 1)
+        cpu = cpu_baseline(procs)
+        print(f"[bench] cpu baseline: {cpu['value']} sample-solves/s on {procs} cores", flush=True)
+
+    import numpy as np
+    import torch
+    from paper_1705_02003_amd import ensemble as E
+    from paper_1705_02003_amd import uq
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    torch.cuda.set_device(0)
+    prob = E.Problem(N_GRID, D, 0, AMP)
+    opts = E.SolverOptions(rtol=RTOL, max_iter=20000, time_spmv=True)
+
+    def step():
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = uq.adaptive(prob, args.S, budget=args.budget, max_level=5, tau_rel=1e-3,
+                        strategy="surrogate", opts=opts, perm_seed=1)
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t
+
+    for w in range(args.warmup):
+        r, dt = step()
+        print(f"[bench] warmup {w}: {len(r.y)} samples in {dt:.2f} s", flush=True)
+    times, spmv_ms, spmv_rows, launches, res = [], 0.0, 0.0, 0, None
+    for k in range(args.steps):
+        res, dt = step()
+        times.append(dt)
+        spmv_ms += res.spmv_ms
+        spmv_rows += res.spmv_member_rows
+        launches += res.spmv_launches
+        print(f"[bench] step {k}: {len(res.y)} samples, {res.total_ensemble_iters} ensemble "
+              f"iterations in {dt:.2f} s", flush=True)
+    total = sum(times)
+    n_samples = len(res.y)
+    value = n_samples * args.steps / total
+
+    achieved = (spmv_rows * FUSED_BYTES / 1e9) / (spmv_ms / 1e3) if spmv_ms > 0 else None
+    solve_s = sum(l.solve_seconds for l in res.levels)
+    member_iter_rows = res.total_ensemble_iters * args.S * prob.rows
+    useful_rows = int(res.iters.sum()) * prob.rows
+    costs = uq.grouping_costs(res, args.S)
+
+    out = {
+        "metric": "sample-solves/s + HBM GB/s, ensemble PCG S=32 vs S=1, 512² grid, rtol 1e-8",
+        "value": round(value, 3),
+        "unit": "sample-solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * total / args.steps, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "adaptive-sg-512x512-d4", "grid": f"{N_GRID}x{N_GRID}",
+                   "samples": n_samples, "S": args.S, "precond": "jacobi", "rtol": RTOL,
+                   "grouping": "surrogate", "levels": [l.n_samples for l in res.levels]},
+        "roofline": {"bound": "hbm",
+                     "achieved": round(achieved, 1) if achieved else None,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+                     "traffic": None,
+                     "kernel": "stencil_kernel<2, M_PCG_J> (fused direction update + SpMV)",
+                     "bytes_per_member_row": FUSED_BYTES,
+                     "timed_launches": launches,
+                     "avg_launch_us": round(1e3 * spmv_ms / max(1, launches), 2)},
+        "gbps_iteration_alg": round(member_iter_rows * ITER_BYTES / solve_s / 1e9, 1),
+        "gbps_iteration_useful": round(useful_rows * ITER_BYTES / solve_s / 1e9, 1),
+        "ensemble_iterations": res.total_ensemble_iters,
+        "grouping": costs,
+        "cpu_baseline": cpu,
+    }
+    if not args.no_s1:
+        out["s1_comparison"] = s1_comparison(res, args.S, E.SolverOptions(rtol=RTOL))
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -63,8 +63,6 @@ constexpr int kMaxD = 16;
 template <int VEC>
 __global__ __launch_bounds__(kNT) void dqdy_kernel(DqdyArgs a) {
   __shared__ double red[kWaves * 64 * 2];
-  __shared__ double fin[kNT];
-  __shared__ int last;
   const Geometry& g = a.g;
   const int S = g.S, n = g.n, tpp = g.tpp, t = threadIdx.x, d = a.d;
   const int sv = (t % tpp) * VEC;
@@ -130,7 +128,7 @@ __global__ __launch_bounds__(kNT) void dqdy_kernel(DqdyArgs a) {
     for (int c = 0; c < VEC; ++c) aC[c] = aE[c] = aW[c] = aN[c] = aS[c] = 1.0;
 #pragma unroll
     for (int k = 1; k <= kMaxD - 2; ++k) {
-      if (k > d - 2) break;
+      if (k <= d - 2) {
       const double kp = (double)k * M_PI;
       const double sIm = sin(kp * ((double)(I - 1) / np1)), sI = sin(kp * ((double)I / np1));
       const double sIp = sin(kp * ((double)(I + 1) / np1));
@@ -152,6 +150,7 @@ __global__ __launch_bounds__(kNT) void dqdy_kernel(DqdyArgs a) {
         const double gy = ((mC + mN) / 2.0) * fN[c] + ((mS + mC) / 2.0) * fS[c];
         acc[k + 1][c] += k11[c] * gx + k22[c] * gy + k12[c] * mC * fm[c] / 4.0;
       }
+      }
     }
 #pragma unroll
     for (int c = 0; c < VEC; ++c) {
@@ -165,40 +164,16 @@ __global__ __launch_bounds__(kNT) void dqdy_kernel(DqdyArgs a) {
   const size_t ps = (size_t)gridDim.x * S;
 #pragma unroll
   for (int q = 0; q < kMaxD; ++q) {
-    if (q >= d) break;
-    double v[VEC];
+    if (q < d) {
+      double v[VEC];
 #pragma unroll
-    for (int c = 0; c < VEC; ++c) v[c] = acc[q][c];
-    reduce_group<VEC>(v, tpp, red);
-    if (t < tpp) {
+      for (int c = 0; c < VEC; ++c) v[c] = acc[q][c];
+      reduce_group<VEC>(v, tpp, red);
+      if (t < tpp) {
 #pragma unroll
-      for (int c = 0; c < VEC; ++c) a.partial[q * ps + (size_t)blockIdx.x * S + t * VEC + c] = v[c];
-      __threadfence();
+        for (int c = 0; c < VEC; ++c) a.partial[q * ps + (size_t)blockIdx.x * S + t * VEC + c] = v[c];
+      }
     }
-  }
-  __syncthreads();
-  if (t == 0) {
-    const unsigned prev = __hip_atomic_fetch_add(reinterpret_cast<unsigned*>(a.ctr), 1u,
-                                                 __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last = (prev == gridDim.x - 1);
-    if (last) __hip_atomic_store(a.ctr, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  const double inv_h2 = (double)(n + 1) * (double)(n + 1);
-  const int T = kNT / S, s = t & (S - 1), kk = t / S;
-  for (int q = 0; q < d; ++q) {
-    double sum = 0.0;
-    for (int gi = kk; gi < (int)gridDim.x; gi += T) sum += a.partial[q * ps + (size_t)gi * S + s];
-    __syncthreads();
-    fin[t] = sum;
-    __syncthreads();
-    for (int st = kNT / 2; st >= S; st >>= 1) {
-      if (t < st) fin[t] += fin[t + st];
-      __syncthreads();
-    }
-    if (t < S) a.result[(size_t)t * 16 + q] = -inv_h2 * fin[t];
   }
 }
 

@@ -92,15 +92,18 @@ Geometry make_geometry(int n, int S, int tile_lines, int max_groups) {
   g.tpp = S / g.vec;
   g.tx = kNT * g.vec / S;
   g.nchunk = (n + g.tx - 1) / g.tx;
+  // Defaults measured on MI355X at 512^2 and S = 1..64: 512 workgroups (two
+  // per CU) with the tallest tile of at most 32 lines that still gives every
+  // workgroup a tile.
+  int G = (max_groups > 0) ? max_groups : 512;
   int ty = tile_lines;
   if (ty <= 0) {
-    ty = 16;
-    while (ty > 2 && (long long)g.nchunk * ((n + ty - 1) / ty) < 2048) ty >>= 1;
+    ty = 32;
+    while (ty > 1 && (long long)g.nchunk * ((n + ty - 1) / ty) < G) ty >>= 1;
   }
   g.ty = std::min(ty, n);
   g.nband = (n + g.ty - 1) / g.ty;
   g.ntiles = g.nchunk * g.nband;
-  int G = (max_groups > 0) ? max_groups : 1024;
   G = std::min(std::min(G, g.ntiles), kMaxGroups);
   if (G >= 8) G &= ~7;
   g.groups = std::max(G, 1);
@@ -112,7 +115,7 @@ Geometry make_geometry(int n, int S, int tile_lines, int max_groups) {
 static int elem_groups(const Geometry& g) {
   const size_t per = (size_t)kNT * g.vec;
   const size_t need = (g.nelem + per - 1) / per;
-  return (int)std::min<size_t>(need, 1024);
+  return (int)std::min<size_t>(need, 512);
 }
 
 static int check_problem(const ens_problem* p) {
@@ -158,6 +161,20 @@ static int resolve_opts(const ens_opts* o, Opts& r) {
     if (e_ != hipSuccess) return set_hip_error(e_); \
   } while (0)
 
+static void finish(const Workspace& w, const Geometry& g, int G, int kind, hipStream_t s,
+                   double rtol = 0.0, int cheb_init = 0) {
+  FinishArgs f;
+  std::memset(&f, 0, sizeof(f));
+  f.partial = w.partial;
+  f.G = G;
+  f.kind = kind;
+  f.m = w.m;
+  f.g = g;
+  f.rtol = rtol;
+  f.cheb_init = cheb_init;
+  launch_finish(f, s);
+}
+
 // One preconditioner application z = p(D^-1 A) D^-1 r: the start step
 // d = z = D^-1 r / theta (already done by the caller when `started`), then
 // degree-1 stencil steps ping-ponging z.  Returns the buffer holding z.
@@ -180,6 +197,7 @@ static double* cheb_apply(const double* V, const Workspace& w, const Geometry& g
     a.cheb_init = init ? 1 : 0;
     launch_stencil<M_CHEB>(a, s);
   }
+  finish(w, g, g.groups, F_CHEB, s, 0.0, init ? 1 : 0);
   return w.z[(degree - 1) & 1];
 }
 
@@ -215,6 +233,20 @@ static int run_solve(const ens_problem* prob, const Opts& o, int S, const double
   ia.cheb_degree = o.degree;
   ia.cheb_ratio = o.ratio;
   launch_init(ia, ge, s);
+  {
+    FinishArgs f;
+    std::memset(&f, 0, sizeof(f));
+    f.partial = w.partial;
+    f.G = ge;
+    f.kind = F_INIT;
+    f.m = w.m;
+    f.g = g;
+    f.cheb = cheb ? 1 : 0;
+    f.cheb_degree = o.degree;
+    f.cheb_ratio = o.ratio;
+    f.max_iter = o.max_iter;
+    launch_finish(f, s);
+  }
   double* zfinal = nullptr;
   if (cheb) zfinal = cheb_apply(V, w, g, o.degree, true, false, s);
   HIPCHECK(hipGetLastError());
@@ -255,16 +287,17 @@ static int run_solve(const ens_problem* prob, const Opts& o, int S, const double
         hipError_t e = hipEventCreate(&e0);
         if (e == hipSuccess) e = hipEventCreate(&e1);
         if (e != hipSuccess) { fail(e); break; }
-        hipEventRecord(e0, s);
+        (void)hipEventRecord(e0, s);
       }
       if (cheb) launch_stencil<M_PCG_Z>(a, s);
       else launch_stencil<M_PCG_J>(a, s);
       if (e1) {
-        hipEventRecord(e1, s);
+        (void)hipEventRecord(e1, s);
         evs.push_back(e0);
         evs.push_back(e1);
         ev_iter.push_back(it);
       }
+      finish(w, g, g.groups, F_ALPHA, s);
       UpdateArgs u;
       std::memset(&u, 0, sizeof(u));
       u.V = V;
@@ -277,6 +310,7 @@ static int run_solve(const ens_problem* prob, const Opts& o, int S, const double
       u.g = g;
       u.rtol = o.rtol;
       launch_update(u, cheb, ge, s);
+      finish(w, g, ge, cheb ? F_UPDATE_C : F_UPDATE_J, s, o.rtol);
       if (cheb) cheb_apply(V, w, g, o.degree, false, true, s);
     }
     if (rc != ENS_OK) break;
@@ -302,7 +336,7 @@ static int run_solve(const ens_problem* prob, const Opts& o, int S, const double
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) fail(e);
   } else {
-    hipStreamSynchronize(s);
+    (void)hipStreamSynchronize(s);
   }
   int ens_iters = 0;
   if (rc == ENS_OK) {
@@ -329,10 +363,10 @@ static int run_solve(const ens_problem* prob, const Opts& o, int S, const double
     }
     *out.stats = st;
   }
-  for (hipEvent_t e : evs) hipEventDestroy(e);
+  for (hipEvent_t e : evs) (void)hipEventDestroy(e);
   for (int k = 0; k < 2; ++k)
-    if (pe[k]) hipEventDestroy(pe[k]);
-  hipHostFree(flag);
+    if (pe[k]) (void)hipEventDestroy(pe[k]);
+  (void)hipHostFree(flag);
   return rc;
 }
 
@@ -446,6 +480,20 @@ int ens_cheb_apply(const ens_problem* prob, const ens_opts* opts, int32_t S, con
   ia.cheb_degree = o.degree;
   ia.cheb_ratio = o.ratio;
   launch_init(ia, elem_groups(g), s);
+  {
+    FinishArgs f;
+    std::memset(&f, 0, sizeof(f));
+    f.partial = w.partial;
+    f.G = elem_groups(g);
+    f.kind = F_INIT;
+    f.m = w.m;
+    f.g = g;
+    f.cheb = 1;
+    f.cheb_degree = o.degree;
+    f.cheb_ratio = o.ratio;
+    f.max_iter = 1;
+    launch_finish(f, s);
+  }
   // every member is preconditioned, whatever its residual: clear the done
   // flag the initialisation raises when all members have r = 0
   HIPCHECK(hipMemsetAsync(w.m.ctl + CTL_DONE, 0, sizeof(int), s));
@@ -470,13 +518,24 @@ int ens_member_dot(int32_t N_r, int32_t S, const double* a_dev, const double* b_
   g.nelem = (size_t)N_r * S;
   hipStream_t s = (hipStream_t)stream;
   HIPCHECK(hipMemsetAsync(w.m.ctl, 0, sizeof(int) * CTL_COUNT, s));
-  launch_dot(a_dev, b_dev, b_broadcast ? 1 : 0, w.partial, w.m.result, w.m.ctl + CTL_CTR_A, g,
-             elem_groups(g), s);
+  launch_dot(a_dev, b_dev, b_broadcast ? 1 : 0, w.partial, g, elem_groups(g), s);
+  {
+    FinishArgs f;
+    std::memset(&f, 0, sizeof(f));
+    f.partial = w.partial;
+    f.G = elem_groups(g);
+    f.kind = F_DOT;
+    f.m = w.m;
+    f.g = g;
+    f.nsum = 1;
+    f.scale = 1.0;
+    launch_finish(f, s);
+  }
   HIPCHECK(hipGetLastError());
-  double res[kMaxS];
-  HIPCHECK(hipMemcpyAsync(res, w.m.result, sizeof(double) * S, hipMemcpyDeviceToHost, s));
+  double res[kMaxS * 16];
+  HIPCHECK(hipMemcpyAsync(res, w.m.result, sizeof(double) * S * 16, hipMemcpyDeviceToHost, s));
   HIPCHECK(hipStreamSynchronize(s));
-  std::memcpy(out_host, res, sizeof(double) * S);
+  for (int k = 0; k < S; ++k) out_host[k] = res[k * 16];
   return ENS_OK;
 }
 
@@ -496,8 +555,6 @@ int ens_dqdy(const ens_problem* prob, int32_t S, const double* y_dev, const doub
   a.u = u_dev;
   a.lam = lambda_dev;
   a.partial = w.partial;
-  a.result = w.m.result;
-  a.ctr = w.m.ctl + CTL_CTR_A;
   a.g = g;
   a.d = prob->d;
   a.eps_model = prob->eps_model;
@@ -506,6 +563,19 @@ int ens_dqdy(const ens_problem* prob, int32_t S, const double* y_dev, const doub
   // groups * S partials fit for groups <= 3 * kMaxGroups / 16
   const int groups = std::min(elem_groups(g), 3 * kMaxGroups / 16);
   launch_dqdy(a, groups, s);
+  {
+    // dQ/dy_j = -(n+1)^2 * (the face/node sums of h^2 lambda^T dA/dy_j u)
+    FinishArgs f;
+    std::memset(&f, 0, sizeof(f));
+    f.partial = w.partial;
+    f.G = groups;
+    f.kind = F_SUMS;
+    f.m = w.m;
+    f.g = g;
+    f.nsum = prob->d;
+    f.scale = -(double)(prob->n + 1) * (double)(prob->n + 1);
+    launch_finish(f, s);
+  }
   HIPCHECK(hipGetLastError());
   double res[kMaxS * 16];
   HIPCHECK(hipMemcpyAsync(res, w.m.result, sizeof(double) * S * 16, hipMemcpyDeviceToHost, s));

@@ -129,11 +129,27 @@ struct DqdyArgs {
   const double* u;   // [N_r][S]
   const double* lam; // [N_r][S]
   double* partial;   // [d][groups][S]
-  double* result;    // [S][16]
-  int* ctr;
   Geometry g;
   int d, eps_model;
   double amp;
+};
+
+enum Finish { F_ALPHA = 0, F_UPDATE_J = 1, F_UPDATE_C = 2, F_CHEB = 3, F_INIT = 4, F_DOT = 5, F_SUMS = 6 };
+
+struct FinishArgs {
+  const double* partial;  // consecutive arrays of G * S partials
+  int G;                  // workgroups of the producer kernel
+  int kind;               // Finish
+  Members m;
+  Geometry g;
+  double rtol;
+  int cheb;               // F_INIT: Chebyshev (Gershgorin bound, coefficients)
+  int cheb_init;          // F_CHEB: the application that yields the initial rho
+  int cheb_degree;
+  double cheb_ratio;
+  int max_iter;
+  int nsum;               // F_DOT / F_SUMS: number of partial arrays
+  double scale;           // F_DOT / F_SUMS: factor applied to each sum
 };
 
 // ------------------------------------------------------------ launchers
@@ -146,8 +162,9 @@ void launch_cheb_start(const double* V, const double* r, double* d, double* z, c
                        const Geometry& g, int groups, hipStream_t s);
 void launch_final(double* x, const double* p0, const double* p1, const Members& m,
                   const Geometry& g, int groups, hipStream_t s);
-void launch_dot(const double* x, const double* y, int y_bcast, double* partial, double* out,
-                int* ctr, const Geometry& g, int groups, hipStream_t s);
+void launch_dot(const double* x, const double* y, int y_bcast, double* partial, const Geometry& g,
+                int groups, hipStream_t s);
+void launch_finish(const FinishArgs& a, hipStream_t s);
 void launch_dqdy(const DqdyArgs& a, int groups, hipStream_t s);
 
 size_t workspace_bytes(int n, int S, bool cheb);

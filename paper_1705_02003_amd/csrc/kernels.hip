@@ -111,46 +111,86 @@ __device__ __forceinline__ void group_max(double (&v)[VEC], int tpp, double* lds
   }
 }
 
-// write this workgroup's partial [S] (threads t < tpp) and publish it
+// write this workgroup's partial [S] (threads t < tpp); a finish kernel
+// launched after this one reads them (the kernel boundary makes them visible
+// across XCDs, so no in-kernel device-scope fence is needed)
 template <int VEC>
 __device__ __forceinline__ void put_partial(double* partial, int S, int tpp, const double (&v)[VEC]) {
   if ((int)threadIdx.x < tpp) {
 #pragma unroll
     for (int c = 0; c < VEC; ++c) partial[(size_t)blockIdx.x * S + threadIdx.x * VEC + c] = v[c];
-    __threadfence();
   }
 }
 
-// true in exactly one workgroup: the last to arrive; it then sees every
-// workgroup's published partials.  Resets the counter for the next launch.
-__device__ __forceinline__ bool arrive_last(int* ctr) {
-  __shared__ int last;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned prev = __hip_atomic_fetch_add(reinterpret_cast<unsigned*>(ctr), 1u,
-                                                 __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last = (prev == gridDim.x - 1);
-    if (last) __hip_atomic_store(ctr, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Member sums of NARR partial arrays P[a][g][s] over the workgroups g < G,
+// returned for member s = threadIdx.x (t < S).  Thread t loads VEC members
+// per row (16-byte loads when VEC = 2); the R = kNT * VEC / S row sets are
+// k, k + R, k + 2R, ... with k = t / (S / VEC), summed in that order with up
+// to 16 loads in flight, then a fixed halving tree over k.  The order does
+// not depend on the member.  `lds` holds NARR * kNT * VEC doubles.
+template <int VEC, int NARR>
+__device__ __forceinline__ void final_sums(const double* const (&P)[NARR], int G, int S,
+                                           double* lds, double (&out)[NARR]) {
+  const int t = threadIdx.x;
+  const int W = S / VEC, R = kNT / W;
+  const int pr = t % W, k = t / W;
+  const int col = pr * VEC;
+  constexpr int B = 16 / NARR;
+  double acc[NARR][VEC];
+#pragma unroll
+  for (int a = 0; a < NARR; ++a)
+#pragma unroll
+    for (int c = 0; c < VEC; ++c) acc[a][c] = 0.0;
+  int g = k;
+  for (; g + (B - 1) * R < G; g += B * R) {
+    double v[NARR][B][VEC];
+#pragma unroll
+    for (int a = 0; a < NARR; ++a)
+#pragma unroll
+      for (int u = 0; u < B; ++u) ld<VEC>(v[a][u], P[a] + (size_t)(g + u * R) * S + col);
+#pragma unroll
+    for (int a = 0; a < NARR; ++a)
+#pragma unroll
+      for (int u = 0; u < B; ++u)
+#pragma unroll
+        for (int c = 0; c < VEC; ++c) acc[a][c] += v[a][u][c];
+  }
+  for (; g < G; g += R) {
+#pragma unroll
+    for (int a = 0; a < NARR; ++a) {
+      double v[VEC];
+      ld<VEC>(v, P[a] + (size_t)g * S + col);
+#pragma unroll
+      for (int c = 0; c < VEC; ++c) acc[a][c] += v[c];
+    }
   }
   __syncthreads();
-  if (last) __threadfence();
-  return last;
-}
-
-// Sum of partial[g][s] over g = 0..G-1 for member s = threadIdx.x (t < S):
-// per-thread strided sums then a fixed halving tree.  `lds` holds kNT doubles.
-__device__ __forceinline__ double final_sum(const double* partial, int G, int S, double* lds) {
-  const int t = threadIdx.x, s = t & (S - 1), k = t / S, T = kNT / S;
-  double acc = 0.0;
-  for (int g = k; g < G; g += T) acc += partial[(size_t)g * S + s];
+#pragma unroll
+  for (int a = 0; a < NARR; ++a)
+#pragma unroll
+    for (int c = 0; c < VEC; ++c) lds[a * kNT * VEC + k * S + col + c] = acc[a][c];
   __syncthreads();
-  lds[t] = acc;
-  __syncthreads();
-  for (int stride = kNT / 2; stride >= S; stride >>= 1) {
-    if (t < stride) lds[t] += lds[t + stride];
+  for (int stride = (R / 2) * S; stride >= S; stride >>= 1) {
+#pragma unroll
+    for (int a = 0; a < NARR; ++a)
+#pragma unroll
+      for (int c = 0; c < VEC; ++c) {
+        const int i = t * VEC + c;
+        if (i < stride) lds[a * kNT * VEC + i] += lds[a * kNT * VEC + i + stride];
+      }
     __syncthreads();
   }
-  return lds[s];
+  const int s = t & (S - 1);
+#pragma unroll
+  for (int a = 0; a < NARR; ++a) out[a] = lds[a * kNT * VEC + s];
+}
+
+template <int VEC>
+__device__ __forceinline__ double final_sum(const double* partial, int G, int S, double* lds) {
+  const double* const P[1] = {partial};
+  double out[1];
+  final_sums<VEC, 1>(P, G, S, lds, out);
+  return out[0];
 }
 
 __device__ __forceinline__ double final_max(const double* partial, int G, int S, double* lds) {
@@ -165,17 +205,6 @@ __device__ __forceinline__ double final_max(const double* partial, int G, int S,
     __syncthreads();
   }
   return lds[s];
-}
-
-// count of active members, computed by the whole (last) workgroup
-__device__ __forceinline__ int count_active(const int* active, int S) {
-  __shared__ int cnt;
-  __syncthreads();
-  if (threadIdx.x == 0) cnt = 0;
-  __syncthreads();
-  if ((int)threadIdx.x < S && active[threadIdx.x]) atomicAdd(&cnt, 1);
-  __syncthreads();
-  return cnt;
 }
 
 // ------------------------------------------------------------ assembly
@@ -280,7 +309,6 @@ template <int VEC, int MODE>
 __global__ __launch_bounds__(kNT) void stencil_kernel(StencilArgs a) {
   __shared__ __attribute__((aligned(16))) double ring[4][kRing];
   __shared__ double red[kWaves * 64 * 2];
-  __shared__ double fin[kNT];
   const Geometry& g = a.g;
   if constexpr (MODE != M_SPMV) {
     if (a.m.ctl[CTL_DONE]) return;
@@ -404,11 +432,12 @@ __global__ __launch_bounds__(kNT) void stencil_kernel(StencilArgs a) {
     }
     fill(j0, true, cur_pold, cur_v4, cur_val);
     for (int j = j0; j < j1; ++j) {
-      fill(j + 1, j + 1 < j1, nxt_pold, nxt_v4, nxt_val);
-      __syncthreads();
+      // Issue this line's matrix values (and x, or the Chebyshev r and d)
+      // before forming the next ring line: both sets of loads are then in
+      // flight together and the line costs one memory round trip.
+      const size_t e = ((size_t)j * n + i) * S + sv;
+      double vk[9][VEC], xv[VEC], rr[VEC], dd[VEC];
       if (own_i) {
-        const size_t e = ((size_t)j * n + i) * S + sv;
-        double vk[9][VEC];
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
           if (k == 4 && MODE == M_PCG_J) {
@@ -418,6 +447,15 @@ __global__ __launch_bounds__(kNT) void stencil_kernel(StencilArgs a) {
             ld_stream<VEC>(vk[k], a.V + (size_t)k * slot_stride + e);
           }
         }
+        if constexpr (MODE == M_PCG_J || MODE == M_PCG_Z) ld<VEC>(xv, a.x + e);
+        if constexpr (MODE == M_CHEB) {
+          ld<VEC>(rr, a.r + e);
+          ld<VEC>(dd, a.d + e);
+        }
+      }
+      fill(j + 1, j + 1 < j1, nxt_pold, nxt_v4, nxt_val);
+      __syncthreads();
+      if (own_i) {
         double q[VEC];
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
@@ -438,8 +476,6 @@ __global__ __launch_bounds__(kNT) void stencil_kernel(StencilArgs a) {
           st<VEC>(a.q + e, q);
         } else if constexpr (MODE == M_PCG_J || MODE == M_PCG_Z) {
           st<VEC>(a.q + e, q);
-          double xv[VEC];
-          ld<VEC>(xv, a.x + e);
 #pragma unroll
           for (int c = 0; c < VEC; ++c) {
             acc[c] = fma(cur_val[c], q[c], acc[c]);
@@ -447,9 +483,7 @@ __global__ __launch_bounds__(kNT) void stencil_kernel(StencilArgs a) {
           }
           st<VEC>(a.x + e, xv);
         } else {  // M_CHEB
-          double rr[VEC], dd[VEC], zn[VEC];
-          ld<VEC>(rr, a.r + e);
-          ld<VEC>(dd, a.d + e);
+          double zn[VEC];
 #pragma unroll
           for (int c = 0; c < VEC; ++c) {
             dd[c] = c1[c] * dd[c] + c2[c] * ((rr[c] - q[c]) / vk[4][c]);
@@ -477,35 +511,6 @@ __global__ __launch_bounds__(kNT) void stencil_kernel(StencilArgs a) {
     }
     group_reduce<VEC>(acc, tpp, red);
     put_partial<VEC>(a.partial, S, tpp, acc);
-    if (!arrive_last(&a.m.ctl[MODE == M_CHEB ? CTL_CTR_C : CTL_CTR_A])) return;
-    const double tot = final_sum(a.partial, gridDim.x, S, fin);
-    if (t < S) {
-      Members& m = a.m;
-      if constexpr (MODE == M_CHEB) {
-        // tot = r^T z for the freshly preconditioned residual
-        if (a.cheb_init) {
-          m.rho[t] = tot;
-          m.beta[t] = 0.0;
-        } else if (m.active[t]) {
-          m.beta[t] = tot / m.rho[t];
-          m.rho[t] = tot;
-        } else {
-          m.beta[t] = 0.0;
-        }
-      } else {
-        double al = 0.0;
-        if (m.active[t]) {
-          if (isfinite(tot) && tot > 0.0) {
-            al = m.rho[t] / tot;
-          } else {
-            m.active[t] = 0;
-            m.status[t] = ENS_BREAKDOWN;
-            m.iters[t] = m.ctl[CTL_K] + 1;
-          }
-        }
-        m.alpha[t] = al;
-      }
-    }
   }
 }
 
@@ -518,7 +523,6 @@ __global__ __launch_bounds__(kNT) void stencil_kernel(StencilArgs a) {
 template <int VEC, bool CHEB>
 __global__ __launch_bounds__(kNT) void update_kernel(UpdateArgs a) {
   __shared__ double red[kWaves * 64 * 2];
-  __shared__ double fin[kNT];
   if (a.m.ctl[CTL_DONE]) return;
   const Geometry& g = a.g;
   const int S = g.S, tpp = g.tpp;
@@ -533,27 +537,40 @@ __global__ __launch_bounds__(kNT) void update_kernel(UpdateArgs a) {
     rz[c] = 0.0;
     rr[c] = 0.0;
   }
+  // grid-stride loop, four strides per pass so 12 loads are in flight
+  constexpr int U = 4;
   const size_t stride = (size_t)gridDim.x * kNT * VEC;
-  for (size_t e = ((size_t)blockIdx.x * kNT + t) * VEC; e < g.nelem; e += stride) {
-    double rv[VEC], qv[VEC], dv[VEC];
-    ld<VEC>(rv, a.r + e);
-    ld<VEC>(qv, a.q + e);
-    ld<VEC>(dv, a.V + 4 * g.nelem + e);
+  for (size_t e0 = ((size_t)blockIdx.x * kNT + t) * VEC; e0 < g.nelem; e0 += U * stride) {
+    double rv[U][VEC], qv[U][VEC], dv[U][VEC];
 #pragma unroll
-    for (int c = 0; c < VEC; ++c) {
-      if (act[c] != 0.0 && alpha[c] != 0.0) rv[c] = fma(-alpha[c], qv[c], rv[c]);
-      rr[c] = fma(rv[c], rv[c], rr[c]);
+    for (int u = 0; u < U; ++u) {
+      const size_t e = e0 + u * stride;
+      if (e < g.nelem) {
+        ld<VEC>(rv[u], a.r + e);
+        ld<VEC>(qv[u], a.q + e);
+        ld<VEC>(dv[u], a.V + 4 * g.nelem + e);
+      }
     }
-    st<VEC>(a.r + e, rv);
-    if constexpr (!CHEB) {
 #pragma unroll
-      for (int c = 0; c < VEC; ++c) rz[c] = fma(rv[c], rv[c] / dv[c], rz[c]);
-    } else {
-      double zz[VEC];
+    for (int u = 0; u < U; ++u) {
+      const size_t e = e0 + u * stride;
+      if (e >= g.nelem) break;
 #pragma unroll
-      for (int c = 0; c < VEC; ++c) zz[c] = (rv[c] / dv[c]) / ith[c];
-      st<VEC>(a.d + e, zz);
-      st<VEC>(a.z + e, zz);
+      for (int c = 0; c < VEC; ++c) {
+        if (act[c] != 0.0 && alpha[c] != 0.0) rv[u][c] = fma(-alpha[c], qv[u][c], rv[u][c]);
+        rr[c] = fma(rv[u][c], rv[u][c], rr[c]);
+      }
+      st<VEC>(a.r + e, rv[u]);
+      if constexpr (!CHEB) {
+#pragma unroll
+        for (int c = 0; c < VEC; ++c) rz[c] = fma(rv[u][c], rv[u][c] / dv[u][c], rz[c]);
+      } else {
+        double zz[VEC];
+#pragma unroll
+        for (int c = 0; c < VEC; ++c) zz[c] = (rv[u][c] / dv[u][c]) / ith[c];
+        st<VEC>(a.d + e, zz);
+        st<VEC>(a.z + e, zz);
+      }
     }
   }
   const size_t pstride = (size_t)gridDim.x * S;
@@ -562,41 +579,6 @@ __global__ __launch_bounds__(kNT) void update_kernel(UpdateArgs a) {
   if constexpr (!CHEB) {
     group_reduce<VEC>(rz, tpp, red);
     put_partial<VEC>(a.partial, S, tpp, rz);
-  }
-  if (!arrive_last(&a.m.ctl[CTL_CTR_B])) return;
-  const double rrs = final_sum(a.partial + pstride, gridDim.x, S, fin);
-  double rzs = 0.0;
-  if constexpr (!CHEB) rzs = final_sum(a.partial, gridDim.x, S, fin);
-  Members& m = a.m;
-  const int k = m.ctl[CTL_K] + 1;
-  if (t < S) {
-    if (m.active[t]) {
-      const double rn = sqrt(rrs);
-      m.relres[t] = rn / m.bnorm[t];
-      if (rn <= a.rtol * m.bnorm[t]) {
-        m.active[t] = 0;
-        m.status[t] = ENS_CONVERGED;
-        m.iters[t] = k;
-      } else if (k >= m.ctl[CTL_MAXIT]) {
-        m.active[t] = 0;
-        m.status[t] = ENS_MAX_ITER;
-        m.iters[t] = k;
-      }
-    }
-    m.alpha_prev[t] = m.alpha[t];
-    if (m.active[t]) {
-      if constexpr (!CHEB) {
-        m.beta[t] = rzs / m.rho[t];
-        m.rho[t] = rzs;
-      }
-    } else {
-      m.beta[t] = 0.0;
-    }
-  }
-  const int live = count_active(m.active, S);
-  if (t == 0) {
-    m.ctl[CTL_K] = k;
-    m.ctl[CTL_DONE] = (live == 0) ? 1 : 0;
   }
 }
 
@@ -607,7 +589,6 @@ __global__ __launch_bounds__(kNT) void update_kernel(UpdateArgs a) {
 template <int VEC>
 __global__ __launch_bounds__(kNT) void init_kernel(InitArgs a) {
   __shared__ double red[kWaves * 64 * 2];
-  __shared__ double fin[kNT];
   const Geometry& g = a.g;
   const int S = g.S, tpp = g.tpp, t = threadIdx.x;
   double rz[VEC], bb[VEC], gm[VEC];
@@ -656,55 +637,6 @@ __global__ __launch_bounds__(kNT) void init_kernel(InitArgs a) {
   } else {
     group_max<VEC>(gm, tpp, red);
     put_partial<VEC>(a.partial + 2 * ps, S, tpp, gm);
-  }
-  if (!arrive_last(&a.m.ctl[CTL_CTR_D])) return;
-  const double bbs = final_sum(a.partial + ps, gridDim.x, S, fin);
-  double rzs = 0.0, lmax = 0.0;
-  if (!a.cheb) rzs = final_sum(a.partial, gridDim.x, S, fin);
-  else lmax = final_max(a.partial + 2 * ps, gridDim.x, S, fin);
-  Members& m = a.m;
-  if (t < S) {
-    const double bn = sqrt(bbs);
-    m.bnorm[t] = bn;
-    m.alpha[t] = 0.0;
-    m.alpha_prev[t] = 0.0;
-    m.beta[t] = 0.0;
-    m.rho[t] = rzs;
-    m.iters[t] = 0;
-    if (bn == 0.0) {
-      m.active[t] = 0;
-      m.status[t] = ENS_ZERO_RHS;
-      m.relres[t] = 0.0;
-    } else {
-      m.active[t] = 1;
-      m.status[t] = ENS_MAX_ITER;
-      m.relres[t] = 1.0;
-    }
-    if (a.cheb) {
-      // Chebyshev semi-iteration on [lmax / ratio, lmax]: theta, delta the
-      // centre and half-width; step k uses c1 = rho_k rho_{k-1},
-      // c2 = 2 rho_k / delta with rho_k = 1 / (2 sigma1 - rho_{k-1}).
-      m.lmax[t] = lmax;
-      const double lmin = lmax / a.cheb_ratio;
-      const double theta = (lmax + lmin) / 2.0;
-      const double delta = (lmax - lmin) / 2.0;
-      const double sigma1 = theta / delta;
-      double rho0 = 1.0 / sigma1;
-      double* cf = m.cheb + (size_t)t * kChebCoef;
-      cf[0] = theta;
-      for (int k = 1; k < a.cheb_degree; ++k) {
-        const double rho1 = 1.0 / (2.0 * sigma1 - rho0);
-        cf[2 * k - 1] = rho1 * rho0;
-        cf[2 * k] = 2.0 * rho1 / delta;
-        rho0 = rho1;
-      }
-    }
-  }
-  const int live = count_active(m.active, S);
-  if (t == 0) {
-    m.ctl[CTL_K] = 0;
-    m.ctl[CTL_MAXIT] = a.max_iter;
-    m.ctl[CTL_DONE] = (live == 0) ? 1 : 0;
   }
 }
 
@@ -757,9 +689,8 @@ __global__ __launch_bounds__(kNT) void final_kernel(double* x, const double* p0,
 // per-member dot products (b optionally broadcast over members)
 template <int VEC>
 __global__ __launch_bounds__(kNT) void dot_kernel(const double* x, const double* y, int y_bcast,
-                                                  double* partial, double* out, int* ctr, Geometry g) {
+                                                  double* partial, Geometry g) {
   __shared__ double red[kWaves * 64 * 2];
-  __shared__ double fin[kNT];
   const int t = threadIdx.x, S = g.S, tpp = g.tpp;
   double acc[VEC];
 #pragma unroll
@@ -779,9 +710,169 @@ __global__ __launch_bounds__(kNT) void dot_kernel(const double* x, const double*
   }
   group_reduce<VEC>(acc, tpp, red);
   put_partial<VEC>(partial, S, tpp, acc);
-  if (!arrive_last(ctr)) return;
-  const double tot = final_sum(partial, gridDim.x, S, fin);
-  if (t < S) out[t] = tot;
+}
+
+
+// ------------------------------------------------------------ finish
+// One workgroup, launched right after a producer kernel: reduces the
+// producer's per-workgroup partials in a fixed order and applies the
+// per-member scalar logic of the step.
+template <int VEC>
+__global__ __launch_bounds__(kNT) void finish_kernel(FinishArgs a) {
+  __shared__ double fin[2 * kNT * 2];
+  __shared__ int live;
+  const int S = a.g.S, t = threadIdx.x;
+  const Members& m = a.m;
+  const size_t ps = (size_t)a.G * S;
+  if (a.kind != F_INIT && a.kind != F_DOT && a.kind != F_SUMS) {
+    if (m.ctl[CTL_DONE]) return;
+  }
+  switch (a.kind) {
+    case F_ALPHA: {
+      // p^T A p per member -> alpha, or freeze the member (the guard)
+      const double sig = final_sum<VEC>(a.partial, a.G, S, fin);
+      if (t < S) {
+        double al = 0.0;
+        if (m.active[t]) {
+          if (isfinite(sig) && sig > 0.0) {
+            al = m.rho[t] / sig;
+          } else {
+            m.active[t] = 0;
+            m.status[t] = ENS_BREAKDOWN;
+            m.iters[t] = m.ctl[CTL_K] + 1;
+          }
+        }
+        m.alpha[t] = al;
+      }
+      return;
+    }
+    case F_CHEB: {
+      // r^T z of a fresh preconditioner application -> rho (and beta)
+      const double rz = final_sum<VEC>(a.partial, a.G, S, fin);
+      if (t < S) {
+        if (a.cheb_init) {
+          m.rho[t] = rz;
+          m.beta[t] = 0.0;
+        } else if (m.active[t]) {
+          m.beta[t] = rz / m.rho[t];
+          m.rho[t] = rz;
+        } else {
+          m.beta[t] = 0.0;
+        }
+      }
+      return;
+    }
+    case F_UPDATE_J:
+    case F_UPDATE_C: {
+      // convergence test ||r_k|| <= rtol ||b||, iteration count, beta
+      double rrs, rzs = 0.0;
+      if (a.kind == F_UPDATE_J) {
+        const double* const P[2] = {a.partial + ps, a.partial};
+        double o2[2];
+        final_sums<VEC, 2>(P, a.G, S, fin, o2);
+        rrs = o2[0];
+        rzs = o2[1];
+      } else {
+        rrs = final_sum<VEC>(a.partial + ps, a.G, S, fin);
+      }
+      const int k = m.ctl[CTL_K] + 1;
+      if (t == 0) live = 0;
+      __syncthreads();
+      if (t < S) {
+        if (m.active[t]) {
+          const double rn = sqrt(rrs);
+          m.relres[t] = rn / m.bnorm[t];
+          if (rn <= a.rtol * m.bnorm[t]) {
+            m.active[t] = 0;
+            m.status[t] = ENS_CONVERGED;
+            m.iters[t] = k;
+          } else if (k >= m.ctl[CTL_MAXIT]) {
+            m.active[t] = 0;
+            m.status[t] = ENS_MAX_ITER;
+            m.iters[t] = k;
+          }
+        }
+        m.alpha_prev[t] = m.alpha[t];
+        if (m.active[t]) {
+          if (a.kind == F_UPDATE_J) {
+            m.beta[t] = rzs / m.rho[t];
+            m.rho[t] = rzs;
+          }
+          atomicAdd(&live, 1);
+        } else {
+          m.beta[t] = 0.0;
+        }
+      }
+      __syncthreads();
+      if (t == 0) {
+        m.ctl[CTL_K] = k;
+        m.ctl[CTL_DONE] = (live == 0) ? 1 : 0;
+      }
+      return;
+    }
+    case F_INIT: {
+      const double bbs = final_sum<VEC>(a.partial + ps, a.G, S, fin);
+      double rzs = 0.0, lmax = 0.0;
+      if (!a.cheb) rzs = final_sum<VEC>(a.partial, a.G, S, fin);
+      else lmax = final_max(a.partial + 2 * ps, a.G, S, fin);
+      if (t == 0) live = 0;
+      __syncthreads();
+      if (t < S) {
+        const double bn = sqrt(bbs);
+        m.bnorm[t] = bn;
+        m.alpha[t] = 0.0;
+        m.alpha_prev[t] = 0.0;
+        m.beta[t] = 0.0;
+        m.rho[t] = rzs;
+        m.iters[t] = 0;
+        if (bn == 0.0) {
+          m.active[t] = 0;
+          m.status[t] = ENS_ZERO_RHS;
+          m.relres[t] = 0.0;
+        } else {
+          m.active[t] = 1;
+          m.status[t] = ENS_MAX_ITER;
+          m.relres[t] = 1.0;
+          atomicAdd(&live, 1);
+        }
+        if (a.cheb) {
+          // Chebyshev semi-iteration on [lmax / ratio, lmax]: theta, delta the
+          // centre and half-width; step k uses c1 = rho_k rho_{k-1},
+          // c2 = 2 rho_k / delta with rho_k = 1 / (2 sigma1 - rho_{k-1}).
+          m.lmax[t] = lmax;
+          const double lmin = lmax / a.cheb_ratio;
+          const double theta = (lmax + lmin) / 2.0;
+          const double delta = (lmax - lmin) / 2.0;
+          const double sigma1 = theta / delta;
+          double rho0 = 1.0 / sigma1;
+          double* cf = m.cheb + (size_t)t * kChebCoef;
+          cf[0] = theta;
+          for (int k = 1; k < a.cheb_degree; ++k) {
+            const double rho1 = 1.0 / (2.0 * sigma1 - rho0);
+            cf[2 * k - 1] = rho1 * rho0;
+            cf[2 * k] = 2.0 * rho1 / delta;
+            rho0 = rho1;
+          }
+        }
+      }
+      __syncthreads();
+      if (t == 0) {
+        m.ctl[CTL_K] = 0;
+        m.ctl[CTL_MAXIT] = a.max_iter;
+        m.ctl[CTL_DONE] = (live == 0) ? 1 : 0;
+      }
+      return;
+    }
+    case F_DOT:
+    case F_SUMS: {
+      // nsum member sums, scaled, into result[s][q]
+      for (int q = 0; q < a.nsum; ++q) {
+        const double v = final_sum<VEC>(a.partial + q * ps, a.G, S, fin);
+        if (t < S) m.result[(size_t)t * 16 + q] = a.scale * v;
+      }
+      return;
+    }
+  }
 }
 
 // ------------------------------------------------------------ launchers
@@ -830,9 +921,13 @@ void launch_final(double* x, const double* p0, const double* p1, const Members& 
   ENS_LAUNCH_VEC(g.vec, final_kernel, dim3(groups), s, x, p0, p1, m, g);
 }
 
-void launch_dot(const double* x, const double* y, int y_bcast, double* partial, double* out,
-                int* ctr, const Geometry& g, int groups, hipStream_t s) {
-  ENS_LAUNCH_VEC(g.vec, dot_kernel, dim3(groups), s, x, y, y_bcast, partial, out, ctr, g);
+void launch_finish(const FinishArgs& a, hipStream_t s) {
+  ENS_LAUNCH_VEC(a.g.vec, finish_kernel, dim3(1), s, a);
+}
+
+void launch_dot(const double* x, const double* y, int y_bcast, double* partial, const Geometry& g,
+                int groups, hipStream_t s) {
+  ENS_LAUNCH_VEC(g.vec, dot_kernel, dim3(groups), s, x, y, y_bcast, partial, g);
 }
 
 }  // namespace ens
