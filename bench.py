@@ -38,6 +38,31 @@ FUSED_BYTES = 15 * 8
 ITER_BYTES = 19 * 8
 
 
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "stencil_pcg_512x512_S32_traffic.json")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "common.h"):
+        with open(os.path.join(ROOT, "paper_1705_02003_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(S: int):
+    """HBM bytes per launch of the fused kernel from the committed counter
+    record, or None if it was taken on other kernel source or another width."""
+    try:
+        with open(TRAFFIC_RECORD) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if S != 32 or rec.get("source_sha256_16") != kernel_source_hash():
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
 # ------------------------------------------------------------ CPU baseline
 def _oracle_one(y):
     from threadpoolctl import threadpool_limits
@@ -120,6 +145,44 @@ def s1_comparison(res, S, opts, n_groups=2):
             "iters_S1": [int(min(its1)), int(max(its1))]}
 
 
+def kernel_mode(args) -> int:
+    """One S-wide ensemble of the workload's coefficient model, solved for a
+    fixed number of iterations (rtol 0) in the default launch configuration,
+    then a plain 1 GiB device-to-device copy whose counter readings calibrate
+    FETCH_SIZE / WRITE_SIZE.  Prints one JSON line with the measured times."""
+    import torch
+    import workloads
+    from paper_1705_02003_amd import ensemble as E
+    torch.cuda.set_device(0)
+    prob = E.Problem(N_GRID, D, 0, AMP)
+    y = torch.tensor(workloads.uniform_samples(1, args.S, D), dtype=torch.float64, device="cuda")
+    V, b = E.assemble(prob, y)
+    opts = E.SolverOptions(rtol=0.0, max_iter=args.iters, time_spmv=True)
+    ws = E.workspace(prob, args.S, opts)
+    E.solve(prob, V, b, opts, ws=ws)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    r = E.solve(prob, V, b, opts, ws=ws)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    us = 1e3 * r.stats["spmv_ms"] / max(1, r.stats["spmv_timed"])
+    rows = prob.rows * args.S
+    print(json.dumps({"mode": "kernel", "S": args.S, "iterations": args.iters,
+                      "fused_avg_us": round(us, 2),
+                      "fused_alg_GBs": round(rows * FUSED_BYTES / (us * 1e-6) / 1e9, 1),
+                      "iteration_us": round(1e6 * dt / args.iters, 2),
+                      "iteration_alg_GBs": round(rows * ITER_BYTES * args.iters / dt / 1e9, 1),
+                      "fused_alg_bytes": rows * FUSED_BYTES,
+                      "copy_bytes_each_way": src.numel() * 8,
+                      "tile_lines": r.stats["tile_lines"], "groups": r.stats["spmv_groups"]}),
+          flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -130,12 +193,19 @@ def main() -> int:
     ap.add_argument("--cpu-procs", type=int, default=0, help="0: min(16, cpu count)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-s1", action="store_true")
+    ap.add_argument("--mode", choices=["full", "kernel"], default="full",
+                    help="kernel: a fixed-iteration solve of one ensemble plus a 1 GiB "
+                         "copy, for hardware-counter runs")
+    ap.add_argument("--iters", type=int, default=100, help="iterations in --mode kernel")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs the ensemble solver on a "
               "single MI355X (ensembles are independent; see the design notes for how the "
               "path would shard). Run with --gpus 1.", file=sys.stderr)
         return 2
+
+    if args.mode == "kernel":
+        return kernel_mode(args)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -205,7 +275,8 @@ def main() -> int:
                      "achieved": round(achieved, 1) if achieved else None,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-                     "traffic": None,
+                     "traffic": measured_traffic(args.S),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "stencil_kernel<2, M_PCG_J> (fused direction update + SpMV)",
                      "bytes_per_member_row": FUSED_BYTES,
                      "timed_launches": launches,
