@@ -183,6 +183,102 @@ def kernel_mode(args) -> int:
     return 0
 
 
+def adjoint_mode(args) -> int:
+    """Differentiation workload: 512x512, d = 6, 512 uniform samples (seed 4)
+    in ensembles of S; forward ensemble PCG + QoI, then the adjoint ensemble
+    PCG + dQ/dy kernel through EnsembleQoI.  The first ensemble's gradient is
+    checked against central differences (h = 1e-6, forward solves at rtol
+    1e-13, all members perturbed at once)."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_1705_02003_amd import autograd as A
+    from paper_1705_02003_amd import ensemble as E
+    torch.cuda.set_device(0)
+    w = workloads.ADJOINT_512
+    prob = E.Problem(w.n, w.d, w.eps_model, w.amp)
+    ys = workloads.uniform_samples(w.seed, w.n_samples, w.d)
+    S = args.S
+    n_ens = args.ensembles or (w.n_samples // S)
+    opts = E.SolverOptions(rtol=w.rtol)
+    fwd = bwd = 0.0
+    grads, fits, bits = [], [], []
+    for k in range(n_ens):
+        y = torch.tensor(ys[k * S:(k + 1) * S], dtype=torch.float64, device="cuda",
+                         requires_grad=True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        Q = A.EnsembleQoI.apply(y, prob, opts)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        Q.sum().backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        fwd += t1 - t
+        bwd += t2 - t1
+        grads.append(y.grad.cpu().numpy())
+        print(f"[bench] adjoint ensemble {k}: forward {t1 - t:.2f} s, backward {t2 - t1:.2f} s",
+              flush=True)
+    y0 = torch.tensor(ys[:S], dtype=torch.float64, device="cuda")
+    fd = A.central_difference(prob, y0, 1e-6, E.SolverOptions(rtol=1e-13))
+    scale = np.maximum(np.abs(fd), 1e-2 * np.abs(fd).max(axis=1, keepdims=True))
+    errs = {}
+    for rtol, g0 in ((w.rtol, grads[0]), (1e-10, None)):
+        if g0 is None:
+            yt = y0.clone().requires_grad_(True)
+            A.EnsembleQoI.apply(yt, prob, E.SolverOptions(rtol=rtol)).sum().backward()
+            g0 = yt.grad.cpu().numpy()
+        errs[f"{rtol:g}"] = {"componentwise": float(np.max(np.abs(g0 - fd) / scale)),
+                             "normwise": float(np.max(np.abs(g0 - fd)) / np.abs(fd).max())}
+    out = {"mode": "adjoint", "workload": w.name, "S": S, "ensembles": n_ens,
+           "samples": n_ens * S, "forward_s": round(fwd, 3), "backward_s": round(bwd, 3),
+           "sample_gradients_per_s": round(n_ens * S / (fwd + bwd), 3),
+           "fd_check": {"h": 1e-6, "fd_rtol": 1e-13, "max_rel_err_by_solve_rtol": errs,
+                        "componentwise": "|g - fd| / max(|fd|, 1e-2 max_j |fd_j|)",
+                        "normwise": "max |g - fd| / max |fd| (per member row)"}}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def cheb_mode(args) -> int:
+    """1024x1024, d = 8, degree-4 Jacobi-Chebyshev: the full level-2 sparse
+    grid (145 nodes) is solved to build the iteration surrogate, the 4096
+    uniform samples (seed 2) are ordered by it into ensembles of S, and
+    ensembles spread evenly over that order are solved."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_1705_02003_amd import ensemble as E
+    from paper_1705_02003_amd import uq
+    torch.cuda.set_device(0)
+    w = workloads.CHEB_1024
+    prob = E.Problem(w.n, w.d, w.eps_model, w.amp)
+    ys = workloads.uniform_samples(w.seed, w.n_samples, w.d)
+    S = args.S
+    ng = (w.n_samples + S - 1) // S
+    k = args.ensembles or 4
+    sel = sorted(set(int(v) for v in np.linspace(0, ng - 1, k).round()))
+    opts = E.SolverOptions(precond="chebyshev", rtol=w.rtol, max_iter=w.max_iter, time_spmv=True)
+    res = uq.nonadaptive(prob, S, ys, 2, opts, solve_groups=sel)
+    solved = [i for g in res.groups[sel] for i in g]
+    real = sorted(set(solved))
+    its = res.iters[real]
+    us = 1e3 * res.spmv_ms / max(1, res.spmv_launches)
+    rows = prob.rows * S
+    out = {"mode": "cheb", "workload": w.name, "S": S, "ensembles_solved": sel,
+           "samples_solved": len(real), "train_samples": len(res.train_iters),
+           "train_seconds": round(res.train_seconds, 2), "solve_seconds": round(res.solve_seconds, 2),
+           "sample_solves_per_s": round(len(real) / res.solve_seconds, 3),
+           "iters_train": [int(res.train_iters.min()), int(res.train_iters.max())],
+           "iters_solved": [int(its.min()), int(its.max())], "ens_iters": res.ens_iters,
+           "R_solved": round(S * sum(res.ens_iters) / float(its.sum()), 4),
+           "fused_avg_us": round(us, 2),
+           "fused_alg_GBs": round(rows * FUSED_BYTES / (us * 1e-6) / 1e9, 1),
+           "iteration_alg_GBs": round(sum(res.ens_iters) * rows * 504 / res.solve_seconds / 1e9, 1)}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -193,10 +289,12 @@ def main() -> int:
     ap.add_argument("--cpu-procs", type=int, default=0, help="0: min(16, cpu count)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-s1", action="store_true")
-    ap.add_argument("--mode", choices=["full", "kernel"], default="full",
+    ap.add_argument("--mode", choices=["full", "kernel", "adjoint", "cheb"], default="full",
                     help="kernel: a fixed-iteration solve of one ensemble plus a 1 GiB "
                          "copy, for hardware-counter runs")
     ap.add_argument("--iters", type=int, default=100, help="iterations in --mode kernel")
+    ap.add_argument("--ensembles", type=int, default=0,
+                    help="ensembles to solve in --mode adjoint / cheb (0: the mode's default)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs the ensemble solver on a "
@@ -206,6 +304,10 @@ def main() -> int:
 
     if args.mode == "kernel":
         return kernel_mode(args)
+    if args.mode == "adjoint":
+        return adjoint_mode(args)
+    if args.mode == "cheb":
+        return cheb_mode(args)
 
     cpu = None
     if not args.no_cpu_baseline:

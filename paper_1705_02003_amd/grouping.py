@@ -116,3 +116,16 @@ def cost_ratio(groups: np.ndarray, iters: Sequence[int], S: int) -> float:
 def ensemble_iteration_total(groups: np.ndarray, iters: Sequence[int]) -> int:
     iters = np.asarray(iters)
     return int(sum(int(iters[g].max()) for g in np.asarray(groups)))
+
+
+def full_grid(d: int, L: int):
+    """Every node of total level <= L (refine all nodes level by level)."""
+    lv = np.zeros((1, d), np.int32)
+    ix = np.zeros((1, d), np.int32)
+    for level in range(L):
+        vals = np.ones(len(lv))
+        nl, ni = refine(lv, ix, vals, level, 0.0, 1 << 30)
+        if len(nl) == 0:
+            break
+        lv, ix = np.vstack([lv, nl]), np.vstack([ix, ni])
+    return lv, ix

@@ -151,3 +151,50 @@ def grouping_costs(res: UQResult, S: int, perm_seed: int = 1) -> dict:
         out[k] = {"sum_ensemble_iters": int(num), "R": S * num / den,
                   "R_levels": [round(G.cost_ratio(g, it, S), 4) for g, it in lst]}
     return out
+
+
+@dataclass
+class NonAdaptiveResult:
+    train_iters: np.ndarray       # iteration counts at the training grid nodes
+    groups: np.ndarray            # (K, S) indices into the samples
+    pred: np.ndarray              # surrogate prediction per sample
+    iters: np.ndarray             # per sample (solved ensembles only; -1 otherwise)
+    ens_iters: List[int]
+    solve_seconds: float
+    train_seconds: float
+    spmv_ms: float = 0.0
+    spmv_launches: int = 0
+    spmv_member_rows: float = 0.0
+
+
+def nonadaptive(prob: E.Problem, S: int, y: np.ndarray, train_level: int,
+                opts: Optional[E.SolverOptions] = None, solve_groups: Optional[List[int]] = None,
+                device="cuda") -> NonAdaptiveResult:
+    """Surrogate grouping without adaptivity (paper, Section 5: pre-select
+    samples, evaluate them, build the iteration surrogate, group the rest).
+
+    The training set is the full sparse grid of total level ``train_level``,
+    solved in generation order; its iteration counts define I^, which orders
+    the samples ``y`` into ensembles of S.  ``solve_groups`` selects which of
+    the resulting ensembles are solved (all by default)."""
+    opts = opts or E.SolverOptions()
+    ws = E.workspace(prob, S, opts, device)
+    lv, ix = G.full_grid(prob.d, train_level)
+    yt = G.coords(lv, ix)
+    acc = [0.0, 0, 0.0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it_train, _, _ = _solve_groups(prob, S, yt, G.chunk(list(range(len(yt))), S), opts, ws,
+                                   device, [0.0, 0, 0.0])
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    groups, pred = G.group_samples(lv, ix, it_train, y, S)
+    sel = range(len(groups)) if solve_groups is None else solve_groups
+    chosen = np.asarray([groups[k] for k in sel])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters, _, ens_iters = _solve_groups(prob, S, y, chosen, opts, ws, device, acc)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return NonAdaptiveResult(it_train, groups, pred, iters, ens_iters, dt, t_train,
+                             acc[0], int(acc[1]), acc[2])
