@@ -279,6 +279,66 @@ def cheb_mode(args) -> int:
     return 0
 
 
+def batch_mode(args) -> int:
+    """64 ensembles, widths drawn from {4..64}, grids from {256, 512, 1024}^2,
+    d = 8 coefficient model (seed 3), Jacobi-PCG rtol 1e-8, solved together by
+    the graph-replayed batched solver.  Launch shapes (member tile width, tile
+    height) come from the autotuner (untimed).  Reports total sample-solves/s
+    and p50 / p99 of the per-ensemble retirement latency."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_1705_02003_amd import autotune
+    from paper_1705_02003_amd import ensemble as E
+    torch.cuda.set_device(0)
+    w = workloads.BATCHED
+    draw = workloads.batched_draw(w.seed)
+    k = args.ensembles or len(draw.widths)
+    widths, grids, samples = draw.widths[:k], draw.grids[:k], draw.samples[:k]
+    t0 = time.perf_counter()
+    shapes = {key: autotune.tune(*key) for key in sorted(set(zip(grids, widths)))}
+    tune_s = time.perf_counter() - t0
+    print(f"[bench] autotuned {len(shapes)} (n, S) shapes in {tune_s:.1f} s", flush=True)
+    items = []
+    for S, n, y in zip(widths, grids, samples):
+        prob = E.Problem(n, w.d, w.eps_model, w.amp)
+        V, b = E.assemble(prob, torch.tensor(y, dtype=torch.float64, device="cuda"))
+        sh = shapes[(n, S)]
+        items.append({"prob": prob, "V": V, "b": b, "tile_lines": sh["tile_lines"],
+                      "member_tile": sh["member_tile"]})
+    opts = E.SolverOptions(rtol=w.rtol, max_iter=w.max_iter)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    res = E.batch_solve(items, opts)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    lat = np.array([r.seconds for r in res])
+    n_samples = int(sum(widths))
+    rows = sum(r.ens_iters * it["prob"].rows * int(it["b"].shape[1]) for r, it in zip(res, items))
+    out = {"mode": "batch", "workload": w.name, "ensembles": k, "samples": n_samples,
+           "seconds": round(dt, 3), "sample_solves_per_s": round(n_samples / dt, 3),
+           "latency_p50_s": round(float(np.percentile(lat, 50)), 4),
+           "latency_p99_s": round(float(np.percentile(lat, 99)), 4),
+           "latency_max_s": round(float(lat.max()), 4),
+           "ensemble_iters": [int(r.ens_iters) for r in res],
+           "iteration_alg_GBs": round(rows * ITER_BYTES / dt / 1e9, 1),
+           "all_converged": bool(all(np.all(r.status == 0) for r in res)),
+           "shapes": {f"{n}x{S}": [v["member_tile"], v["tile_lines"]] for (n, S), v in shapes.items()}}
+    if args.sequential:
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for it in items:
+            E.solve(it["prob"], it["V"], it["b"],
+                    E.SolverOptions(rtol=w.rtol, max_iter=w.max_iter, tile_lines=it["tile_lines"],
+                                    member_tile=it["member_tile"]))
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t
+        out["sequential_seconds"] = round(ts, 3)
+        out["batch_speedup_vs_sequential"] = round(ts / dt, 3)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -289,10 +349,12 @@ def main() -> int:
     ap.add_argument("--cpu-procs", type=int, default=0, help="0: min(16, cpu count)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-s1", action="store_true")
-    ap.add_argument("--mode", choices=["full", "kernel", "adjoint", "cheb"], default="full",
+    ap.add_argument("--mode", choices=["full", "kernel", "adjoint", "cheb", "batch"], default="full",
                     help="kernel: a fixed-iteration solve of one ensemble plus a 1 GiB "
                          "copy, for hardware-counter runs")
     ap.add_argument("--iters", type=int, default=100, help="iterations in --mode kernel")
+    ap.add_argument("--sequential", action="store_true",
+                    help="--mode batch: also solve the ensembles one after another")
     ap.add_argument("--ensembles", type=int, default=0,
                     help="ensembles to solve in --mode adjoint / cheb (0: the mode's default)")
     args = ap.parse_args()
@@ -308,6 +370,8 @@ def main() -> int:
         return adjoint_mode(args)
     if args.mode == "cheb":
         return cheb_mode(args)
+    if args.mode == "batch":
+        return batch_mode(args)
 
     cpu = None
     if not args.no_cpu_baseline:

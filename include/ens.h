@@ -92,7 +92,8 @@ typedef struct {
   int32_t tile_lines;   /* stencil tile height in grid lines, 0 = heuristic   */
   int32_t max_groups;   /* workgroups of the stencil/update kernels, 0 = heuristic */
   int32_t flags;        /* bit 0 (ENS_FLAG_TIME_SPMV): time the fused SpMV kernel */
-  int32_t reserved;     /* must be 0                                          */
+  int32_t member_tile;  /* members per stencil tile: a power of two dividing S
+                           (a wide ensemble is swept in member tiles); 0 = S  */
 } ens_opts;
 
 #define ENS_FLAG_TIME_SPMV 1
@@ -191,6 +192,44 @@ int ens_adjoint_grad(const ens_problem* prob, const ens_opts* opts, int32_t S,
 int ens_dqdy(const ens_problem* prob, int32_t S, const double* y_dev,
              const double* u_dev, const double* lambda_dev, double* grad_host,
              void* ws_dev, size_t ws_bytes, void* stream);
+
+/* ----------------------------------------------------------- batching */
+/* One ensemble of a batch.  The caller assembles it (ens_assemble_ensemble)
+ * and gives it its own ens_pcg_solve workspace (Jacobi layout). */
+typedef struct {
+  ens_problem prob;        /* grid size n (the coefficient model is not used here) */
+  int32_t S;               /* ensemble width, a power of two in [2, 64]            */
+  int32_t tile_lines;      /* stencil tile height, 0 = heuristic                   */
+  const double* V_dev;     /* [9][N_r][S]                                          */
+  const double* b_dev;     /* [N_r][S]                                             */
+  double* x_dev;           /* [N_r][S], overwritten                                */
+  void* ws_dev;            /* >= ens_pcg_workspace_bytes(&prob, Jacobi, S) bytes   */
+  size_t ws_bytes;
+  int32_t* iters_host;     /* [S] out, may be NULL                                 */
+  int32_t* status_host;    /* [S] out, may be NULL                                 */
+  double* relres_host;     /* [S] out, may be NULL                                 */
+  int32_t ens_iters;       /* out: max over members                                */
+  int32_t member_tile;     /* members per stencil tile (power of two <= S), 0 = S  */
+  double seconds;          /* out: device time from the batch start until this
+                              ensemble's last member stopped                       */
+} ens_batch_item;
+
+/* Bytes of the batch workspace for n_items ensembles (descriptor table,
+ * unit prefixes, retirement flags and clocks), 0 if n_items is invalid. */
+size_t ens_batch_workspace_bytes(int32_t n_items);
+
+/* Solve n_items ensembles of different width, grid and iteration count
+ * together (Jacobi-PCG, the semantics of ens_pcg_solve for each).  One CG
+ * step for all ensembles is a graph of four kernels (fused stencil, finish,
+ * update, finish) whose stencil and update kernels stride over the work of
+ * every unfinished ensemble; the graph is replayed until every ensemble has
+ * retired.  Paper: Section 5 names ensembles of varying size as future work;
+ * each ensemble here still runs max over its members iterations (eqs. (Rl),
+ * (R)).  opts: Jacobi only (ENS_ENOTSUP otherwise); max_groups sets the grid
+ * of the strided kernels (default 512, a multiple of 8).  Blocking.
+ * Errors: ENS_EINVAL (bad item), ENS_ENOMEM (a workspace too small). */
+int ens_batch_solve(const ens_opts* opts, int32_t n_items, ens_batch_item* items,
+                    void* batch_ws, size_t batch_ws_bytes, void* stream);
 
 /* --------------------------------------------------- sparse grid (host) */
 /* Nodes of the centre-rooted piecewise-linear hierarchy (paper, Section 2.2):

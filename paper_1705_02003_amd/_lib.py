@@ -31,12 +31,19 @@ class ens_problem(C.Structure):
 class ens_opts(C.Structure):
     _fields_ = [("precond", i32), ("cheb_degree", i32), ("cheb_ratio", f64), ("rtol", f64),
                 ("max_iter", i32), ("poll_every", i32), ("tile_lines", i32),
-                ("max_groups", i32), ("flags", i32), ("reserved", i32)]
+                ("max_groups", i32), ("flags", i32), ("member_tile", i32)]
 
 
 class ens_stats(C.Structure):
     _fields_ = [("ens_iters", i32), ("spmv_timed", i32), ("spmv_ms", f64),
                 ("spmv_groups", i32), ("tile_lines", i32)]
+
+
+class ens_batch_item(C.Structure):
+    _fields_ = [("prob", ens_problem), ("S", i32), ("tile_lines", i32),
+                ("V_dev", vp), ("b_dev", vp), ("x_dev", vp), ("ws_dev", vp), ("ws_bytes", sz),
+                ("iters_host", i32p), ("status_host", i32p), ("relres_host", f64p),
+                ("ens_iters", i32), ("member_tile", i32), ("seconds", f64)]
 
 
 PP = C.POINTER(ens_problem)
@@ -57,6 +64,8 @@ SIGNATURES = {
     "ens_sg_surpluses": (C.c_int, [i32, i32, i32p, i32p, f64p, f64p]),
     "ens_sg_coords": (C.c_int, [i32, i32, i32p, i32p, f64p]),
     "ens_sg_refine": (C.c_int, [i32, i32, i32p, i32p, f64p, i32, f64, i32, i32, i32p, i32p, i32p]),
+    "ens_batch_workspace_bytes": (sz, [i32]),
+    "ens_batch_solve": (C.c_int, [OP, i32, C.POINTER(ens_batch_item), vp, sz, vp]),
     "ens_strerror": (C.c_char_p, [C.c_int]),
     "ens_last_hip_error": (C.c_int, []),
     "ens_version": (C.c_int, []),

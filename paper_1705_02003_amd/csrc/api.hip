@@ -46,7 +46,7 @@ size_t workspace_bytes(int n, int S, bool cheb) {
   return header_bytes() + vec * n_vectors(cheb);
 }
 
-static Workspace carve(void* base, int n, int S, bool cheb) {
+Workspace carve_workspace(void* base, int n, int S, bool cheb) {
   Workspace w;
   std::memset(&w, 0, sizeof(w));
   char* p = static_cast<char*>(base);
@@ -83,14 +83,20 @@ static Workspace carve(void* base, int n, int S, bool cheb) {
   return w;
 }
 
-Geometry make_geometry(int n, int S, int tile_lines, int max_groups) {
+Geometry make_geometry(int n, int S, int tile_lines, int max_groups, int member_tile) {
   Geometry g;
   g.n = n;
   g.S = S;
   g.logS = log2i(S);
   g.vec = (S >= 2) ? 2 : 1;
   g.tpp = S / g.vec;
-  g.tx = kNT * g.vec / S;
+  // member tile: a power of two dividing S, at least one thread pair wide
+  int sw = (member_tile > 0) ? std::min(member_tile, S) : S;
+  if (sw < g.vec) sw = g.vec;
+  g.sw = sw;
+  g.nstile = S / sw;
+  g.stpp = sw / g.vec;
+  g.tx = kNT * g.vec / sw;
   g.nchunk = (n + g.tx - 1) / g.tx;
   // Defaults measured on MI355X at 512^2 and S = 1..64: 512 workgroups (two
   // per CU) with the tallest tile of at most 32 lines that still gives every
@@ -112,7 +118,7 @@ Geometry make_geometry(int n, int S, int tile_lines, int max_groups) {
   return g;
 }
 
-static int elem_groups(const Geometry& g) {
+int init_groups(const Geometry& g) {
   const size_t per = (size_t)kNT * g.vec;
   const size_t need = (g.nelem + per - 1) / per;
   return (int)std::min<size_t>(need, 512);
@@ -129,7 +135,7 @@ static int check_problem(const ens_problem* p) {
 }
 
 struct Opts {
-  int precond, degree, max_iter, poll, tile_lines, max_groups, flags;
+  int precond, degree, max_iter, poll, tile_lines, max_groups, flags, member_tile;
   double ratio, rtol;
 };
 
@@ -146,12 +152,14 @@ static int resolve_opts(const ens_opts* o, Opts& r) {
   r.tile_lines = o->tile_lines;
   r.max_groups = o->max_groups;
   r.flags = o->flags;
+  r.member_tile = o->member_tile;
   if (r.precond != ENS_PRECOND_JACOBI && r.precond != ENS_PRECOND_CHEBYSHEV) return ENS_EINVAL;
   if (r.degree < 2 || r.degree > kMaxCheb) return ENS_EINVAL;
   if (!std::isfinite(r.ratio) || r.ratio <= 1.0) return ENS_EINVAL;
   if (!std::isfinite(r.rtol) || r.rtol < 0.0) return ENS_EINVAL;
   if (r.max_iter < 1 || r.poll < 1 || r.tile_lines < 0 || r.max_groups < 0) return ENS_EINVAL;
-  if (o->reserved != 0) return ENS_EINVAL;
+  if (r.member_tile < 0 || (r.member_tile & (r.member_tile - 1)) != 0 || r.member_tile > kMaxS)
+    return ENS_EINVAL;
   return ENS_OK;
 }
 
@@ -180,7 +188,7 @@ static void finish(const Workspace& w, const Geometry& g, int G, int kind, hipSt
 // degree-1 stencil steps ping-ponging z.  Returns the buffer holding z.
 static double* cheb_apply(const double* V, const Workspace& w, const Geometry& g, int degree,
                           bool init, bool started, hipStream_t s) {
-  if (!started) launch_cheb_start(V, w.r, w.d, w.z[0], w.m, g, elem_groups(g), s);
+  if (!started) launch_cheb_start(V, w.r, w.d, w.z[0], w.m, g, init_groups(g), s);
   for (int k = 1; k < degree; ++k) {
     StencilArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -213,8 +221,8 @@ static int run_solve(const ens_problem* prob, const Opts& o, int S, const double
                      int b_bcast, double* x, const Workspace& w, hipStream_t s, SolveOut out) {
   const int n = prob->n;
   const bool cheb = (o.precond == ENS_PRECOND_CHEBYSHEV);
-  const Geometry g = make_geometry(n, S, o.tile_lines, o.max_groups);
-  const int ge = elem_groups(g);
+  const Geometry g = make_geometry(n, S, o.tile_lines, o.max_groups, o.member_tile);
+  const int ge = init_groups(g);
 
   HIPCHECK(hipMemsetAsync(w.m.ctl, 0, sizeof(int) * CTL_COUNT, s));
   InitArgs ia;
@@ -430,7 +438,7 @@ int ens_pcg_solve(const ens_problem* prob, const ens_opts* opts, int32_t S, cons
   if (!valid_S(S) || !V_dev || !b_dev || !x_dev || !ws_dev) return ENS_EINVAL;
   const bool cheb = o.precond == ENS_PRECOND_CHEBYSHEV;
   if (ws_bytes < workspace_bytes(prob->n, S, cheb)) return ENS_ENOMEM;
-  const Workspace w = carve(ws_dev, prob->n, S, cheb);
+  const Workspace w = carve_workspace(ws_dev, prob->n, S, cheb);
   SolveOut out{iters_host, status_host, relres_host, ens_iters_host, stats};
   return run_solve(prob, o, S, V_dev, b_dev, 0, x_dev, w, (hipStream_t)stream, out);
 }
@@ -461,8 +469,8 @@ int ens_cheb_apply(const ens_problem* prob, const ens_opts* opts, int32_t S, con
   if (rc) return rc;
   if (!valid_S(S) || !V_dev || !r_dev || !z_dev || !ws_dev) return ENS_EINVAL;
   if (ws_bytes < workspace_bytes(prob->n, S, true)) return ENS_ENOMEM;
-  const Workspace w = carve(ws_dev, prob->n, S, true);
-  const Geometry g = make_geometry(prob->n, S, o.tile_lines, o.max_groups);
+  const Workspace w = carve_workspace(ws_dev, prob->n, S, true);
+  const Geometry g = make_geometry(prob->n, S, o.tile_lines, o.max_groups, o.member_tile);
   hipStream_t s = (hipStream_t)stream;
   HIPCHECK(hipMemsetAsync(w.m.ctl, 0, sizeof(int) * CTL_COUNT, s));
   InitArgs ia;
@@ -479,12 +487,12 @@ int ens_cheb_apply(const ens_problem* prob, const ens_opts* opts, int32_t S, con
   ia.cheb = 1;
   ia.cheb_degree = o.degree;
   ia.cheb_ratio = o.ratio;
-  launch_init(ia, elem_groups(g), s);
+  launch_init(ia, init_groups(g), s);
   {
     FinishArgs f;
     std::memset(&f, 0, sizeof(f));
     f.partial = w.partial;
-    f.G = elem_groups(g);
+    f.G = init_groups(g);
     f.kind = F_INIT;
     f.m = w.m;
     f.g = g;
@@ -512,18 +520,18 @@ int ens_member_dot(int32_t N_r, int32_t S, const double* a_dev, const double* b_
                    void* stream) {
   if (N_r < 1 || !valid_S(S) || !a_dev || !b_dev || !out_host || !ws_dev) return ENS_EINVAL;
   if (ws_bytes < header_bytes()) return ENS_ENOMEM;
-  const Workspace w = carve(ws_dev, 0, S, false);
+  const Workspace w = carve_workspace(ws_dev, 0, S, false);
   Geometry g = make_geometry(2, S, 0, 0);
   g.nr = (size_t)N_r;
   g.nelem = (size_t)N_r * S;
   hipStream_t s = (hipStream_t)stream;
   HIPCHECK(hipMemsetAsync(w.m.ctl, 0, sizeof(int) * CTL_COUNT, s));
-  launch_dot(a_dev, b_dev, b_broadcast ? 1 : 0, w.partial, g, elem_groups(g), s);
+  launch_dot(a_dev, b_dev, b_broadcast ? 1 : 0, w.partial, g, init_groups(g), s);
   {
     FinishArgs f;
     std::memset(&f, 0, sizeof(f));
     f.partial = w.partial;
-    f.G = elem_groups(g);
+    f.G = init_groups(g);
     f.kind = F_DOT;
     f.m = w.m;
     f.g = g;
@@ -546,7 +554,7 @@ int ens_dqdy(const ens_problem* prob, int32_t S, const double* y_dev, const doub
   if (rc) return rc;
   if (!valid_S(S) || !y_dev || !u_dev || !lambda_dev || !grad_host || !ws_dev) return ENS_EINVAL;
   if (ws_bytes < header_bytes()) return ENS_ENOMEM;
-  const Workspace w = carve(ws_dev, 0, S, false);
+  const Workspace w = carve_workspace(ws_dev, 0, S, false);
   const Geometry g = make_geometry(prob->n, S, 0, 0);
   hipStream_t s = (hipStream_t)stream;
   HIPCHECK(hipMemsetAsync(w.m.ctl, 0, sizeof(int) * CTL_COUNT, s));
@@ -561,7 +569,7 @@ int ens_dqdy(const ens_problem* prob, int32_t S, const double* y_dev, const doub
   a.amp = prob->amp;
   // the partial buffer holds 3 * kMaxGroups * kMaxS doubles; d <= 16 rows of
   // groups * S partials fit for groups <= 3 * kMaxGroups / 16
-  const int groups = std::min(elem_groups(g), 3 * kMaxGroups / 16);
+  const int groups = std::min(init_groups(g), 3 * kMaxGroups / 16);
   launch_dqdy(a, groups, s);
   {
     // dQ/dy_j = -(n+1)^2 * (the face/node sums of h^2 lambda^T dA/dy_j u)
@@ -598,7 +606,7 @@ int ens_adjoint_grad(const ens_problem* prob, const ens_opts* opts, int32_t S, c
     return ENS_EINVAL;
   const bool cheb = o.precond == ENS_PRECOND_CHEBYSHEV;
   if (ws_bytes < workspace_bytes(prob->n, S, cheb)) return ENS_ENOMEM;
-  const Workspace w = carve(ws_dev, prob->n, S, cheb);
+  const Workspace w = carve_workspace(ws_dev, prob->n, S, cheb);
   SolveOut out{iters_host, status_host, nullptr, nullptr, nullptr};
   rc = run_solve(prob, o, S, V_dev, w_dev, 1, lambda_dev, w, (hipStream_t)stream, out);
   if (rc) return rc;

@@ -59,9 +59,10 @@ struct Workspace {
 };
 
 struct Geometry {
-  int n, S, logS, vec, tpp;  // tpp: threads per grid point
+  int n, S, logS, vec, tpp;  // tpp: threads per grid point of the flat kernels (S / vec)
+  int sw, nstile, stpp;      // member tile: sw members per stencil tile, S / sw tiles, sw / vec threads
   int tx, ty;                // tile: points per line chunk, lines per band
-  int nchunk, nband, ntiles, groups;
+  int nchunk, nband, ntiles, groups;   // ntiles counts spatial tiles (per member tile)
   size_t nr, nelem;          // rows, rows * S
 };
 
@@ -168,7 +169,9 @@ void launch_finish(const FinishArgs& a, hipStream_t s);
 void launch_dqdy(const DqdyArgs& a, int groups, hipStream_t s);
 
 size_t workspace_bytes(int n, int S, bool cheb);
-Geometry make_geometry(int n, int S, int tile_lines, int max_groups);
+Workspace carve_workspace(void* base, int n, int S, bool cheb);
+int init_groups(const Geometry& g);   // workgroups of the element-wise kernels
+Geometry make_geometry(int n, int S, int tile_lines, int max_groups, int member_tile = 0);
 int set_hip_error(hipError_t e);
 int valid_S(int S);
 

@@ -45,12 +45,13 @@ class SolverOptions:
     tile_lines: int = 0           # 0: heuristic
     max_groups: int = 0           # 0: heuristic
     time_spmv: bool = False
+    member_tile: int = 0          # members per stencil tile, 0: the whole ensemble
 
     def c(self) -> L.ens_opts:
         pre = {"jacobi": L.PRECOND_JACOBI, "chebyshev": L.PRECOND_CHEBYSHEV}[self.precond]
         return L.ens_opts(pre, self.cheb_degree, float(self.cheb_ratio), float(self.rtol),
                           self.max_iter, self.poll_every, self.tile_lines, self.max_groups,
-                          L.FLAG_TIME_SPMV if self.time_spmv else 0, 0)
+                          L.FLAG_TIME_SPMV if self.time_spmv else 0, int(self.member_tile))
 
 
 class SolveResult(NamedTuple):
@@ -237,3 +238,65 @@ def qoi_weights(n: int, device=None) -> torch.Tensor:
     m = np.outer(inside, inside).reshape(-1)
     w = np.where(m, 1.0 / m.sum(), 0.0)
     return torch.tensor(w, dtype=torch.float64, device=device or "cuda")
+
+
+class BatchResult(NamedTuple):
+    x: torch.Tensor
+    iters: np.ndarray
+    status: np.ndarray
+    relres: np.ndarray
+    ens_iters: int
+    seconds: float           # device time from the batch start to this ensemble's retirement
+
+
+def batch_solve(items, opts: Optional[SolverOptions] = None, batch_ws: Optional[torch.Tensor] = None):
+    """Solve several ensembles together (ens_batch_solve).
+
+    ``items``: sequence of dicts with keys ``prob`` (Problem), ``V``, ``b`` and
+    optionally ``x``, ``ws`` (a Jacobi workspace of that ensemble) and
+    ``tile_lines``.  Returns one BatchResult per item."""
+    opts = opts or SolverOptions()
+    n = len(items)
+    if n == 0:
+        return []
+    c_items = (L.ens_batch_item * n)()
+    keep = []
+    outs = []
+    dev = None
+    for k, it in enumerate(items):
+        prob, V, b = it["prob"], it["V"], it["b"]
+        S = _ensemble_width(b)
+        _require_cuda(V, "V", (9, prob.rows, S))
+        _require_cuda(b, "b", (prob.rows, S))
+        x = it.get("x")
+        if x is None:
+            x = torch.empty_like(b)
+        _require_cuda(x, "x", (prob.rows, S))
+        ws = it.get("ws")
+        if ws is None:
+            ws = workspace(prob, S, SolverOptions(), V.device)
+        _require_cuda(ws, "ws", dtype=torch.uint8)
+        iters = np.zeros(S, np.int32)
+        status = np.zeros(S, np.int32)
+        relres = np.zeros(S, np.float64)
+        ci = c_items[k]
+        ci.prob = prob.c()
+        ci.S = S
+        ci.tile_lines = int(it.get("tile_lines", 0))
+        ci.member_tile = int(it.get("member_tile", 0))
+        ci.V_dev, ci.b_dev, ci.x_dev = V.data_ptr(), b.data_ptr(), x.data_ptr()
+        ci.ws_dev, ci.ws_bytes = ws.data_ptr(), ws.numel()
+        ci.iters_host = iters.ctypes.data_as(L.i32p)
+        ci.status_host = status.ctypes.data_as(L.i32p)
+        ci.relres_host = relres.ctypes.data_as(L.f64p)
+        keep.append((x, ws))
+        outs.append((x, iters, status, relres))
+        dev = V.device
+    nb = L.lib().ens_batch_workspace_bytes(n)
+    if batch_ws is None or batch_ws.numel() < nb:
+        batch_ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    oc = opts.c()
+    L.check(L.lib().ens_batch_solve(C.byref(oc), n, c_items, _p(batch_ws), batch_ws.numel(),
+                                    _stream(dev)), "ens_batch_solve")
+    return [BatchResult(x, it_, st_, rr_, int(c_items[k].ens_iters), float(c_items[k].seconds))
+            for k, (x, it_, st_, rr_) in enumerate(outs)]

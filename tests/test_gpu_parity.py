@@ -304,3 +304,26 @@ def test_adjoint_gradient_matches_oracle():
         Q, gref, _, _ = oadj.qoi_and_grad(ys[s], n, 0, 0.4)
         scale = np.maximum(np.abs(gref), 1e-2 * np.abs(gref).max())
         assert np.max(np.abs(g[s] - gref) / scale) <= 1e-8
+
+
+@pytest.mark.parametrize("S,tiles", [(64, (32, 16, 8)), (32, (16, 2)), (8, (4, 2))])
+def test_member_tiles_agree(S, tiles):
+    """Sweeping a wide ensemble in member tiles changes only which threads
+    hold which members: counts agree, solutions agree to rounding, and each
+    member's reduction tree stays member-independent (bitwise permutation)."""
+    ens = E()
+    n = 56
+    prob = ens.Problem(n, 4, 0, 0.4)
+    ys = np.random.default_rng(S).uniform(-1, 1, (S, 4))
+    V, b = gpu_stencil(prob, ys)
+    base = ens.solve(prob, V, b)
+    for sw in tiles:
+        log_case(test="member_tiles", S=S, member_tile=sw)
+        r = ens.solve(prob, V, b, ens.SolverOptions(member_tile=sw))
+        assert np.all(np.abs(r.iters - base.iters) <= 1)
+        rel = (torch.linalg.norm(r.x - base.x, dim=0) / torch.linalg.norm(base.x, dim=0)).cpu().numpy()
+        assert np.all(rel[r.iters == base.iters] <= 1e-9)
+        perm = np.random.default_rng(sw).permutation(S)
+        V2, b2 = gpu_stencil(prob, ys[perm])
+        r2 = ens.solve(prob, V2, b2, ens.SolverOptions(member_tile=sw))
+        assert torch.equal(r2.x, r.x[:, perm]) and np.array_equal(r2.iters, r.iters[perm])
