@@ -31,11 +31,24 @@ D = 4
 AMP = 0.4
 RTOL = 1e-8
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per member-row per call of the fused kernel: reads the
-# nine matrix values, r, p_old, x; writes p, q, x (15 FP64 words)
-FUSED_BYTES = 15 * 8
-# per member-row per Jacobi-PCG iteration (fused kernel + update kernel)
-ITER_BYTES = 19 * 8
+# Algorithmic bytes per member-row.  The fused kernel reads five matrix
+# values (C, E, N, NE, NW; the other four are the neighbours' by symmetry),
+# r, p_old, x and writes p, q, x: 11 FP64 words (15 with --full-stencil,
+# which reads all nine).  A Jacobi-PCG iteration adds the update kernel's
+# 4 words; a Jacobi-Chebyshev-4 iteration is 47 words (63 with nine).
+FULL_STENCIL = False
+FUSED_BYTES = 11 * 8
+ITER_BYTES = 15 * 8
+CHEB_ITER_BYTES = 47 * 8
+
+
+def set_byte_model(full: bool) -> None:
+    global FULL_STENCIL, FUSED_BYTES, ITER_BYTES, CHEB_ITER_BYTES
+    FULL_STENCIL = full
+    extra = 4 if full else 0
+    FUSED_BYTES = (11 + extra) * 8
+    ITER_BYTES = (15 + extra) * 8
+    CHEB_ITER_BYTES = (47 + 4 * extra) * 8
 
 
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "stencil_pcg_512x512_S32_traffic.json")
@@ -44,7 +57,7 @@ TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "stencil_pcg_512x512_S32_traffic
 def kernel_source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hip", "common.h"):
+    for f in ("kernels.hip", "common.h", "device.h"):
         with open(os.path.join(ROOT, "paper_1705_02003_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -59,6 +72,8 @@ def measured_traffic(S: int):
     except (OSError, ValueError):
         return None
     if S != 32 or rec.get("source_sha256_16") != kernel_source_hash():
+        return None
+    if bool(rec.get("full_stencil", False)) != FULL_STENCIL:
         return None
     return rec.get("traffic_bytes_per_launch")
 
@@ -157,7 +172,8 @@ def kernel_mode(args) -> int:
     prob = E.Problem(N_GRID, D, 0, AMP)
     y = torch.tensor(workloads.uniform_samples(1, args.S, D), dtype=torch.float64, device="cuda")
     V, b = E.assemble(prob, y)
-    opts = E.SolverOptions(rtol=0.0, max_iter=args.iters, time_spmv=True)
+    opts = E.SolverOptions(rtol=0.0, max_iter=args.iters, time_spmv=True,
+                           full_stencil=FULL_STENCIL)
     ws = E.workspace(prob, args.S, opts)
     E.solve(prob, V, b, opts, ws=ws)
     torch.cuda.synchronize()
@@ -169,6 +185,22 @@ def kernel_mode(args) -> int:
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
+    # STREAM-style calibration of achievable HBM bandwidth (1 GiB arrays)
+    other = torch.empty_like(src).fill_(2.0)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * src.numel() * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    e0.record()
+    for _ in range(reps):
+        torch.add(src, other, alpha=2.0, out=dst)
+    e1.record()
+    torch.cuda.synchronize()
+    triad_gbs = 3 * src.numel() * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
     us = 1e3 * r.stats["spmv_ms"] / max(1, r.stats["spmv_timed"])
     rows = prob.rows * args.S
     print(json.dumps({"mode": "kernel", "S": args.S, "iterations": args.iters,
@@ -178,6 +210,7 @@ def kernel_mode(args) -> int:
                       "iteration_alg_GBs": round(rows * ITER_BYTES * args.iters / dt / 1e9, 1),
                       "fused_alg_bytes": rows * FUSED_BYTES,
                       "copy_bytes_each_way": src.numel() * 8,
+                      "stream_copy_GBs": round(copy_gbs, 1), "stream_triad_GBs": round(triad_gbs, 1),
                       "tile_lines": r.stats["tile_lines"], "groups": r.stats["spmv_groups"]}),
           flush=True)
     return 0
@@ -258,7 +291,8 @@ def cheb_mode(args) -> int:
     ng = (w.n_samples + S - 1) // S
     k = args.ensembles or 4
     sel = sorted(set(int(v) for v in np.linspace(0, ng - 1, k).round()))
-    opts = E.SolverOptions(precond="chebyshev", rtol=w.rtol, max_iter=w.max_iter, time_spmv=True)
+    opts = E.SolverOptions(precond="chebyshev", rtol=w.rtol, max_iter=w.max_iter, time_spmv=True,
+                           full_stencil=FULL_STENCIL)
     res = uq.nonadaptive(prob, S, ys, 2, opts, solve_groups=sel)
     solved = [i for g in res.groups[sel] for i in g]
     real = sorted(set(solved))
@@ -274,7 +308,7 @@ def cheb_mode(args) -> int:
            "R_solved": round(S * sum(res.ens_iters) / float(its.sum()), 4),
            "fused_avg_us": round(us, 2),
            "fused_alg_GBs": round(rows * FUSED_BYTES / (us * 1e-6) / 1e9, 1),
-           "iteration_alg_GBs": round(sum(res.ens_iters) * rows * 504 / res.solve_seconds / 1e9, 1)}
+           "iteration_alg_GBs": round(sum(res.ens_iters) * rows * CHEB_ITER_BYTES / res.solve_seconds / 1e9, 1)}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -306,7 +340,7 @@ def batch_mode(args) -> int:
         sh = shapes[(n, S)]
         items.append({"prob": prob, "V": V, "b": b, "tile_lines": sh["tile_lines"],
                       "member_tile": sh["member_tile"]})
-    opts = E.SolverOptions(rtol=w.rtol, max_iter=w.max_iter)
+    opts = E.SolverOptions(rtol=w.rtol, max_iter=w.max_iter, full_stencil=FULL_STENCIL)
     torch.cuda.synchronize()
     t = time.perf_counter()
     res = E.batch_solve(items, opts)
@@ -329,7 +363,8 @@ def batch_mode(args) -> int:
         t = time.perf_counter()
         for it in items:
             E.solve(it["prob"], it["V"], it["b"],
-                    E.SolverOptions(rtol=w.rtol, max_iter=w.max_iter, tile_lines=it["tile_lines"],
+                    E.SolverOptions(rtol=w.rtol, max_iter=w.max_iter, full_stencil=FULL_STENCIL,
+                                    tile_lines=it["tile_lines"],
                                     member_tile=it["member_tile"]))
         torch.cuda.synchronize()
         ts = time.perf_counter() - t
@@ -353,11 +388,14 @@ def main() -> int:
                     help="kernel: a fixed-iteration solve of one ensemble plus a 1 GiB "
                          "copy, for hardware-counter runs")
     ap.add_argument("--iters", type=int, default=100, help="iterations in --mode kernel")
+    ap.add_argument("--full-stencil", action="store_true",
+                    help="read all nine matrix values per row (no symmetric reuse)")
     ap.add_argument("--sequential", action="store_true",
                     help="--mode batch: also solve the ensembles one after another")
     ap.add_argument("--ensembles", type=int, default=0,
                     help="ensembles to solve in --mode adjoint / cheb (0: the mode's default)")
     args = ap.parse_args()
+    set_byte_model(args.full_stencil)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs the ensemble solver on a "
               "single MI355X (ensembles are independent; see the design notes for how the "
@@ -389,7 +427,7 @@ def main() -> int:
         return 1
     torch.cuda.set_device(0)
     prob = E.Problem(N_GRID, D, 0, AMP)
-    opts = E.SolverOptions(rtol=RTOL, max_iter=20000, time_spmv=True)
+    opts = E.SolverOptions(rtol=RTOL, max_iter=20000, time_spmv=True, full_stencil=FULL_STENCIL)
 
     def step():
         torch.cuda.synchronize()

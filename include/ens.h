@@ -91,12 +91,21 @@ typedef struct {
   int32_t poll_every;   /* host checks the device done flag every m iterations (16) */
   int32_t tile_lines;   /* stencil tile height in grid lines, 0 = heuristic   */
   int32_t max_groups;   /* workgroups of the stencil/update kernels, 0 = heuristic */
-  int32_t flags;        /* bit 0 (ENS_FLAG_TIME_SPMV): time the fused SpMV kernel */
+  int32_t flags;        /* ENS_FLAG_* bits below                              */
   int32_t member_tile;  /* members per stencil tile: a power of two dividing S
                            (a wide ensemble is swept in member tiles); 0 = S  */
 } ens_opts;
 
+/* Time the fused SpMV kernel with HIP events (ens_stats.spmv_ms). */
 #define ENS_FLAG_TIME_SPMV 1
+/* Solves and Chebyshev applications: read all nine stored matrix values of
+   every row.  By default they use the symmetry that CG requires of A and read
+   only the centre, E, N, NE and NW values, taking W, S, SW, SE of row (i, j)
+   from E(i-1, j), N(i, j-1), NE(i-1, j-1), NW(i+1, j-1); both give the same
+   bits on the bitwise-symmetric matrices ens_assemble_ensemble writes.  The
+   full read is kept for verification and for matrices stored otherwise.
+   ens_spmv always reads all nine values. */
+#define ENS_FLAG_FULL_STENCIL 2
 
 /* Optional statistics of one solve. */
 typedef struct {

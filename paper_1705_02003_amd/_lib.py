@@ -15,6 +15,7 @@ ENS_ENOTSUP = -4
 CONVERGED, MAX_ITER, BREAKDOWN, ZERO_RHS = 0, 1, 2, 3
 PRECOND_JACOBI, PRECOND_CHEBYSHEV = 0, 1
 FLAG_TIME_SPMV = 1
+FLAG_FULL_STENCIL = 2
 
 i32 = C.c_int32
 i32p = C.POINTER(C.c_int32)

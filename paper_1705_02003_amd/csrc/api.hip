@@ -115,6 +115,7 @@ Geometry make_geometry(int n, int S, int tile_lines, int max_groups, int member_
   g.groups = std::max(G, 1);
   g.nr = (size_t)n * n;
   g.nelem = g.nr * S;
+  g.full = 0;
   return g;
 }
 
@@ -221,7 +222,8 @@ static int run_solve(const ens_problem* prob, const Opts& o, int S, const double
                      int b_bcast, double* x, const Workspace& w, hipStream_t s, SolveOut out) {
   const int n = prob->n;
   const bool cheb = (o.precond == ENS_PRECOND_CHEBYSHEV);
-  const Geometry g = make_geometry(n, S, o.tile_lines, o.max_groups, o.member_tile);
+  Geometry g = make_geometry(n, S, o.tile_lines, o.max_groups, o.member_tile);
+  g.full = (o.flags & ENS_FLAG_FULL_STENCIL) ? 1 : 0;
   const int ge = init_groups(g);
 
   HIPCHECK(hipMemsetAsync(w.m.ctl, 0, sizeof(int) * CTL_COUNT, s));
@@ -454,6 +456,7 @@ int ens_spmv(const ens_problem* prob, int32_t S, const double* V_dev, const doub
   a.src = p_dev;
   a.q = q_dev;
   a.g = make_geometry(prob->n, S, 0, 0);
+  a.g.full = 1;   // any stored matrix, symmetric or not
   launch_stencil<M_SPMV>(a, (hipStream_t)stream);
   HIPCHECK(hipGetLastError());
   return ENS_OK;
@@ -470,7 +473,8 @@ int ens_cheb_apply(const ens_problem* prob, const ens_opts* opts, int32_t S, con
   if (!valid_S(S) || !V_dev || !r_dev || !z_dev || !ws_dev) return ENS_EINVAL;
   if (ws_bytes < workspace_bytes(prob->n, S, true)) return ENS_ENOMEM;
   const Workspace w = carve_workspace(ws_dev, prob->n, S, true);
-  const Geometry g = make_geometry(prob->n, S, o.tile_lines, o.max_groups, o.member_tile);
+  Geometry g = make_geometry(prob->n, S, o.tile_lines, o.max_groups, o.member_tile);
+  g.full = (o.flags & ENS_FLAG_FULL_STENCIL) ? 1 : 0;
   hipStream_t s = (hipStream_t)stream;
   HIPCHECK(hipMemsetAsync(w.m.ctl, 0, sizeof(int) * CTL_COUNT, s));
   InitArgs ia;

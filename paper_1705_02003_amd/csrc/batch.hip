@@ -89,8 +89,10 @@ __device__ __forceinline__ int partial_row(int L, int first, int G) {
   return r < 0 ? r + G : r;
 }
 
+template <bool SYM>
 __global__ __launch_bounds__(kNT) void batch_stencil_kernel(BatchArgs a) {
   __shared__ __attribute__((aligned(16))) double ring[4][kRing];
+  __shared__ __attribute__((aligned(16))) double sym[SYM ? 6 * kRing : 2];
   __shared__ double red[kWaves * 64 * 2];
   __shared__ int s_prefix[kMaxBatch + 1];
   __shared__ int s_done[kMaxBatch];
@@ -150,7 +152,7 @@ __global__ __launch_bounds__(kNT) void batch_stencil_kernel(BatchArgs a) {
         acc[c] = 0.0;
       }
     }
-    stencil_tile<2, M_PCG_J>(tv, local - js * E.ntiles, ring, beta, aprev, zero2, zero2, acc);
+    stencil_tile<2, M_PCG_J, SYM>(tv, local - js * E.ntiles, ring, sym, beta, aprev, zero2, zero2, acc);
   }
   if (cur >= 0) flush();
 }
@@ -439,10 +441,13 @@ int ens_batch_solve(const ens_opts* opts, int32_t n_items, ens_batch_item* items
   he = hipGraphCreate(&graph, 0);
   void* args[1] = {&ba};
   hipGraphNode_t prev = nullptr;
+  const void* stencil_fn = (o->flags & ENS_FLAG_FULL_STENCIL)
+                               ? reinterpret_cast<const void*>(&batch_stencil_kernel<false>)
+                               : reinterpret_cast<const void*>(&batch_stencil_kernel<true>);
   struct NodeSpec {
     const void* fn;
     unsigned grid;
-  } specs[4] = {{reinterpret_cast<const void*>(&batch_stencil_kernel), (unsigned)G},
+  } specs[4] = {{stencil_fn, (unsigned)G},
                 {reinterpret_cast<const void*>(&batch_finish_kernel<0>), (unsigned)n_items},
                 {reinterpret_cast<const void*>(&batch_update_kernel), (unsigned)G},
                 {reinterpret_cast<const void*>(&batch_finish_kernel<1>), (unsigned)n_items}};

@@ -64,6 +64,7 @@ struct Geometry {
   int tx, ty;                // tile: points per line chunk, lines per band
   int nchunk, nband, ntiles, groups;   // ntiles counts spatial tiles (per member tile)
   size_t nr, nelem;          // rows, rows * S
+  int full;                  // 1: the sweep reads all nine matrix values per row
 };
 
 

@@ -243,8 +243,17 @@ struct TileView {
 //            x += alpha_prev p_old;
 //   M_CHEB:  one Chebyshev step d = c1 d + c2 D^-1 (r - A z), z += d, and
 //            on the last step accumulate r^T z.
-template <int VEC, int MODE>
+//
+// SYM: the matrix is symmetric, so only C, E, N, NE, NW are read; the lower
+// coefficients of row (i, j) are W = E(i-1, j), S = N(i, j-1), SW = NE(i-1,
+// j-1) and SE = NW(i+1, j-1).  Each thread keeps N, NE, NW of its point's
+// previous line in registers; E of the current line and NE, NW of the
+// previous line are exchanged through `sym` (LDS, 2 x 3 lines of kRing
+// doubles).  The products are formed in the same order as the nine-value
+// sweep, so on a bitwise-symmetric matrix both give the same bits.
+template <int VEC, int MODE, bool SYM>
 __device__ __forceinline__ void stencil_tile(const TileView& a, int tile, double (*ring)[kRing],
+                                             double* sym,
                                              const double (&beta)[VEC], const double (&aprev)[VEC],
                                              const double (&c1)[VEC], const double (&c2)[VEC],
                                              double (&acc)[VEC]) {
@@ -337,10 +346,27 @@ __device__ __forceinline__ void stencil_tile(const TileView& a, int tile, double
     }
   };
 
+  // symmetric sweep: per line slot (j - j0) & 1, LDS lines of E (line j),
+  // NE and NW (line j - 1), each with the one-point halo
+  auto symL = [&](int jj, int w) { return sym + (((jj - j0) & 1) * 3 + w) * kRing; };
+  const bool left_halo = t < tpp, halo = t < 2 * tpp;
+  const int hi = i0 + (left_halo ? -1 : a.tx);   // halo point of this thread
+  double prevN[VEC], prevNE[VEC], prevNW[VEC];   // own point, line j - 1
+#pragma unroll
+  for (int c = 0; c < VEC; ++c) prevN[c] = prevNE[c] = prevNW[c] = 0.0;
+
   __syncthreads();  // the previous tile's readers are done with the ring
   {
     double d0[VEC], d1[VEC], d2v[VEC];
     fill(j0 - 1, false, d0, d1, d2v);
+  }
+  if constexpr (SYM) {
+    if (j0 > 0 && own_i) {
+      const size_t ep = ((size_t)(j0 - 1) * n + i) * S + sv;
+      ld_stream<VEC>(prevN, a.V + 7 * slot_stride + ep);
+      ld_stream<VEC>(prevNE, a.V + 8 * slot_stride + ep);
+      ld_stream<VEC>(prevNW, a.V + 6 * slot_stride + ep);
+    }
   }
   fill(j0, true, cur_pold, cur_v4, cur_val);
   for (int j = j0; j < j1; ++j) {
@@ -348,10 +374,19 @@ __device__ __forceinline__ void stencil_tile(const TileView& a, int tile, double
     // before forming the next ring line: both sets of loads are then in
     // flight together and the line costs one memory round trip.
     const size_t e = ((size_t)j * n + i) * S + sv;
-    double vk[9][VEC], xv[VEC], rr[VEC], dd[VEC];
+    double vk[9][VEC], xv[VEC], rr[VEC], dd[VEC], hE[VEC], hX[VEC];
+    if constexpr (SYM) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k)
+#pragma unroll
+        for (int c = 0; c < VEC; ++c) vk[k][c] = 0.0;
+#pragma unroll
+      for (int c = 0; c < VEC; ++c) hE[c] = hX[c] = 0.0;
+    }
     if (own_i) {
 #pragma unroll
       for (int k = 0; k < 9; ++k) {
+        if (SYM && k < 4) continue;   // lower coefficients: from neighbours
         if (k == 4 && MODE == M_PCG_J) {
 #pragma unroll
           for (int c = 0; c < VEC; ++c) vk[4][c] = cur_v4[c];
@@ -365,9 +400,58 @@ __device__ __forceinline__ void stencil_tile(const TileView& a, int tile, double
         ld<VEC>(dd, a.d + e);
       }
     }
+    if constexpr (SYM) {
+      // halo: E(i0 - 1, j) and NE(i0 - 1, j - 1) left of the chunk,
+      // NW(i0 + tx, j - 1) right of it
+      if (halo && hi >= 0 && hi < n) {
+        const size_t he = ((size_t)j * n + hi) * S + sv;
+        if (left_halo) {
+          ld_stream<VEC>(hE, a.V + 5 * slot_stride + he);
+          if (j > 0) ld_stream<VEC>(hX, a.V + 8 * slot_stride + he - (size_t)n * S);
+        } else if (j > 0) {
+          ld_stream<VEC>(hX, a.V + 6 * slot_stride + he - (size_t)n * S);
+        }
+      }
+    }
     fill(j + 1, j + 1 < j1, nxt_pold, nxt_v4, nxt_val);
+    if constexpr (SYM) {
+      double* lE = symL(j, 0);
+      double* lNE = symL(j, 1);
+      double* lNW = symL(j, 2);
+#pragma unroll
+      for (int c = 0; c < VEC; ++c) {
+        lE[(lp + 1) * sw + cl + c] = vk[5][c];
+        lNE[(lp + 1) * sw + cl + c] = prevNE[c];
+        lNW[(lp + 1) * sw + cl + c] = prevNW[c];
+        if (halo) {
+          if (left_halo) {
+            lE[cl + c] = hE[c];
+            lNE[cl + c] = hX[c];
+          } else {
+            lNW[(a.tx + 1) * sw + cl + c] = hX[c];
+          }
+        }
+      }
+    }
     __syncthreads();
     if (own_i) {
+      if constexpr (SYM) {
+        // lower coefficients of row (i, j): SW = NE(i-1, j-1), S = N(i, j-1),
+        // SE = NW(i+1, j-1), W = E(i-1, j)
+        const double* pSW = symL(j, 1) + lp * sw + cl;
+        const double* pSE = symL(j, 2) + (lp + 2) * sw + cl;
+        const double* pW = symL(j, 0) + lp * sw + cl;
+#pragma unroll
+        for (int c = 0; c < VEC; ++c) {
+          vk[0][c] = pSW[c];
+          vk[1][c] = prevN[c];
+          vk[2][c] = pSE[c];
+          vk[3][c] = pW[c];
+          prevN[c] = vk[7][c];
+          prevNE[c] = vk[8][c];
+          prevNW[c] = vk[6][c];
+        }
+      }
       double q[VEC];
 #pragma unroll
       for (int k = 0; k < 9; ++k) {

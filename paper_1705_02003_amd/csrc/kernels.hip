@@ -102,9 +102,10 @@ __global__ __launch_bounds__(kNT) void assemble_kernel(AsmArgs a) {
 //            number -- the paper's guard).
 //   M_CHEB:  one Chebyshev step d = c1 d + c2 D^-1 (r - A z), z += d; the
 //            last step accumulates r^T z and the last workgroup forms beta.
-template <int VEC, int MODE>
+template <int VEC, int MODE, bool SYM>
 __global__ __launch_bounds__(kNT) void stencil_kernel(StencilArgs a) {
   __shared__ __attribute__((aligned(16))) double ring[4][kRing];
+  __shared__ __attribute__((aligned(16))) double sym[SYM ? 6 * kRing : 2];
   __shared__ double red[kWaves * 64 * 2];
   const Geometry& g = a.g;
   if constexpr (MODE != M_SPMV) {
@@ -155,7 +156,7 @@ __global__ __launch_bounds__(kNT) void stencil_kernel(StencilArgs a) {
     }
     int tile, tstep, tend;
     tile_range(g, tile, tstep, tend);
-    for (; tile < tend; tile += tstep) stencil_tile<VEC, MODE>(tv, tile, ring, beta, aprev, c1, c2, acc);
+    for (; tile < tend; tile += tstep) stencil_tile<VEC, MODE, SYM>(tv, tile, ring, sym, beta, aprev, c1, c2, acc);
     if constexpr (MODE == M_PCG_J || MODE == M_PCG_Z) {
       group_reduce<VEC>(acc, tpp, red);
       put_partial<VEC>(a.partial, g.S, tpp, acc, tv.s0);
@@ -392,8 +393,14 @@ void launch_assemble(const AsmArgs& a, hipStream_t s) {
 
 template <int MODE>
 void launch_stencil(const StencilArgs& a, hipStream_t s) {
-  if (a.g.vec == 2) hipLaunchKernelGGL((stencil_kernel<2, MODE>), dim3(a.g.groups), dim3(kNT), 0, s, a);
-  else hipLaunchKernelGGL((stencil_kernel<1, MODE>), dim3(a.g.groups), dim3(kNT), 0, s, a);
+  const dim3 grid(a.g.groups), block(kNT);
+  if (a.g.vec == 2) {
+    if (a.g.full) hipLaunchKernelGGL((stencil_kernel<2, MODE, false>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((stencil_kernel<2, MODE, true>), grid, block, 0, s, a);
+  } else {
+    if (a.g.full) hipLaunchKernelGGL((stencil_kernel<1, MODE, false>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((stencil_kernel<1, MODE, true>), grid, block, 0, s, a);
+  }
 }
 template void launch_stencil<M_SPMV>(const StencilArgs&, hipStream_t);
 template void launch_stencil<M_PCG_J>(const StencilArgs&, hipStream_t);

@@ -46,12 +46,15 @@ class SolverOptions:
     max_groups: int = 0           # 0: heuristic
     time_spmv: bool = False
     member_tile: int = 0          # members per stencil tile, 0: the whole ensemble
+    full_stencil: bool = False    # read all nine matrix values (no symmetric reuse)
 
     def c(self) -> L.ens_opts:
         pre = {"jacobi": L.PRECOND_JACOBI, "chebyshev": L.PRECOND_CHEBYSHEV}[self.precond]
         return L.ens_opts(pre, self.cheb_degree, float(self.cheb_ratio), float(self.rtol),
                           self.max_iter, self.poll_every, self.tile_lines, self.max_groups,
-                          L.FLAG_TIME_SPMV if self.time_spmv else 0, int(self.member_tile))
+                          (L.FLAG_TIME_SPMV if self.time_spmv else 0)
+                          | (L.FLAG_FULL_STENCIL if self.full_stencil else 0),
+                          int(self.member_tile))
 
 
 class SolveResult(NamedTuple):

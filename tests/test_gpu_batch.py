@@ -89,3 +89,15 @@ def test_batch_with_retired_and_capped_ensembles():
     capped = E.batch_solve(items, E.SolverOptions(rtol=1e-8, max_iter=5))
     for k in (0, 2):
         assert np.all(capped[k].status == 1) and np.all(capped[k].iters == 5)
+
+
+def test_batch_symmetric_sweep_bitwise():
+    """The batched step's five-value symmetric sweep equals its nine-value
+    sweep bit for bit."""
+    from paper_1705_02003_amd import ensemble as E
+    items, _ = make_batch(seed=3, member_tiles=True)
+    r1 = E.batch_solve(items, E.SolverOptions(rtol=1e-8))
+    r2 = E.batch_solve(items, E.SolverOptions(rtol=1e-8, full_stencil=True))
+    for a, b in zip(r1, r2):
+        assert np.array_equal(a.iters, b.iters)
+        assert torch.equal(a.x, b.x)

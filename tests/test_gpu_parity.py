@@ -327,3 +327,44 @@ def test_member_tiles_agree(S, tiles):
         V2, b2 = gpu_stencil(prob, ys[perm])
         r2 = ens.solve(prob, V2, b2, ens.SolverOptions(member_tile=sw))
         assert torch.equal(r2.x, r.x[:, perm]) and np.array_equal(r2.iters, r.iters[perm])
+
+
+@pytest.mark.parametrize("n,S,kw", [
+    (64, 32, {}),
+    (45, 8, {"tile_lines": 1}),
+    (37, 1, {"tile_lines": 3, "max_groups": 40}),
+    (70, 64, {"member_tile": 16}),
+    (19, 2, {"tile_lines": 5, "max_groups": 2048}),
+    (33, 16, {"precond": "chebyshev"}),
+    (29, 4, {"precond": "chebyshev", "cheb_degree": 3, "tile_lines": 2}),
+])
+def test_symmetric_sweep_bitwise(n, S, kw):
+    """The default sweep reads five matrix values per row and takes the other
+    four from the neighbouring rows; on the bitwise-symmetric assembled
+    matrix it must reproduce the nine-value sweep bit for bit, including the
+    tile edges (one-point halos, first line of a band, last partial chunk)."""
+    ens = E()
+    d = 8 if kw.get("precond") == "chebyshev" else 4
+    prob = ens.Problem(n, d, 1 if d == 8 else 0, 0.45 if d == 8 else 0.4)
+    ys = np.random.default_rng(n * 7 + S).uniform(-1, 1, (S, d))
+    V, b = gpu_stencil(prob, ys)
+    log_case(test="symmetric", n=n, S=S, **kw)
+    Vh = V.cpu().numpy()
+    # the assembled storage is bitwise symmetric: W(i,j) = E(i-1,j), ...
+    V4 = Vh.reshape(9, n, n, S)                      # [slot][j][i][s]
+    assert np.array_equal(V4[3][:, 1:], V4[5][:, :-1])
+    assert np.array_equal(V4[1][1:], V4[7][:-1])
+    assert np.array_equal(V4[0][1:, 1:], V4[8][:-1, :-1])
+    assert np.array_equal(V4[2][1:, :-1], V4[6][:-1, 1:])
+    sym = ens.solve(prob, V, b, ens.SolverOptions(**kw))
+    full = ens.solve(prob, V, b, ens.SolverOptions(full_stencil=True, **kw))
+    assert np.array_equal(sym.iters, full.iters)
+    assert np.array_equal(sym.status, full.status)
+    assert torch.equal(sym.x, full.x)
+    if kw.get("precond") == "chebyshev":
+        R = to_dev(np.random.default_rng(5).standard_normal((n * n, S)))
+        kc = {k: v for k, v in kw.items() if k != "precond"}
+        z1, l1 = ens.cheb_apply(prob, V, R, ens.SolverOptions(precond="chebyshev", **kc))
+        z2, l2 = ens.cheb_apply(prob, V, R, ens.SolverOptions(precond="chebyshev",
+                                                             full_stencil=True, **kc))
+        assert torch.equal(z1, z2) and np.array_equal(l1, l2)
