@@ -76,6 +76,23 @@ __device__ __forceinline__ int owner(const int* prefix, int n, int u) {
   return lo;
 }
 
+// A value that is the same in every lane (an ensemble's descriptor field):
+// moving it to a scalar register right after its load keeps later address
+// arithmetic off vector registers whose loads the compiler would otherwise
+// wait for again at every branch merge.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ size_t uni(size_t v) {
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return ((size_t)hi << 32) | lo;
+}
+
+template <class T>
+__device__ __forceinline__ T* uni(T* p) {
+  return reinterpret_cast<T*>(uni(reinterpret_cast<size_t>(p)));
+}
+
 // stage the unit prefix table and the retirement flags in LDS
 __device__ __forceinline__ void stage_tables(const int* prefix, const int* done, int n, int* s_prefix,
                                              int* s_done) {
@@ -100,61 +117,80 @@ __global__ __launch_bounds__(kNT) void batch_stencil_kernel(BatchArgs a) {
   const int t = threadIdx.x;
   const int L = logical_group(blockIdx.x, a.G);
   const double zero2[2] = {0.0, 0.0};
-  int cur = -1, cur_js = 0, cur_first = 0, tpp = 1, S = 2;
+  int cur = -1, cur_js = 0, cur_first = 0, tpp = 1, S = 2, ntiles = 1;
+  double* partial = nullptr;
   double beta[2] = {0.0, 0.0}, aprev[2] = {0.0, 0.0}, acc[2] = {0.0, 0.0};
   TileView tv = {};
   // rows of a member tile's partials: row r holds its units r, r + G, ...
   auto flush = [&]() {
     group_reduce<2>(acc, tpp, red);
-    const BatchEns& E = a.ens[cur];
     if (t < tpp) {
       const int row = partial_row(L, cur_first, a.G);
 #pragma unroll
-      for (int c = 0; c < 2; ++c) E.partial[(size_t)row * S + tv.s0 + t * 2 + c] = acc[c];
+      for (int c = 0; c < 2; ++c) gstore(&partial[(size_t)row * S + tv.s0 + t * 2 + c], acc[c]);
     }
   };
   int e = 0;
   for (int u = L; u < a.U; u += a.G) {
     if (u >= s_prefix[e + 1]) e = owner(s_prefix, a.n_ens, u);   // next ensemble
-    if (s_done[e]) continue;
-    const BatchEns& E = a.ens[e];
+    e = uni(e);
+    if (uni(s_done[e])) continue;
     const int local = u - s_prefix[e];
-    const int js = local / E.ntiles;          // member tile
-    const int first = s_prefix[e] + js * E.ntiles;
+    if (e != cur) ntiles = uni(a.ens[e].ntiles);
+    const int js = local / ntiles;            // member tile
+    const int first = s_prefix[e] + js * ntiles;
     if (e != cur || js != cur_js) {
       if (cur >= 0) flush();
+      const BatchEns& E = a.ens[e];
       cur = e;
       cur_js = js;
       cur_first = first;
-      S = E.S;
-      tpp = E.stpp;
-      tv.s0 = js * E.sw;
+      S = uni(E.S);
+      tpp = uni(E.stpp);
+      partial = uni(E.partial);
+      tv.s0 = js * uni(E.sw);
       const int sv = tv.s0 + (t % tpp) * 2;
-      const int it = E.m.ctl[CTL_K] + 1;   // the iteration this launch performs
-      tv.V = E.V;
-      tv.r = E.r;
-      tv.pold = E.p[(it + 1) & 1];
-      tv.pnew = E.p[it & 1];
-      tv.q = E.q;
-      tv.x = E.x;
-      tv.n = E.n;
+      const int it = uni(gload(&E.m.ctl[CTL_K])) + 1;   // the iteration this launch performs
+      double* const* pp = E.p;
+      tv.V = uni(E.V);
+      tv.r = uni(E.r);
+      tv.pold = uni(pp[(it + 1) & 1]);
+      tv.pnew = uni(pp[it & 1]);
+      tv.q = uni(E.q);
+      tv.x = uni(E.x);
+      tv.n = uni(E.n);
       tv.S = S;
-      tv.sw = E.sw;
+      tv.sw = uni(E.sw);
       tv.tpp = tpp;
-      tv.tx = E.tx;
-      tv.ty = E.ty;
-      tv.nchunk = E.nchunk;
-      tv.nelem = E.nelem;
+      tv.tx = uni(E.tx);
+      tv.ty = uni(E.ty);
+      tv.nchunk = uni(E.nchunk);
+      tv.nelem = uni(E.nelem);
+      const double* mb = uni(E.m.beta);
+      const double* ma = uni(E.m.alpha_prev);
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
-        beta[c] = E.m.beta[sv + c];
-        aprev[c] = E.m.alpha_prev[sv + c];
+        beta[c] = gload(&mb[sv + c]);
+        aprev[c] = gload(&ma[sv + c]);
         acc[c] = 0.0;
       }
     }
-    stencil_tile<2, M_PCG_J, SYM>(tv, local - js * E.ntiles, ring, sym, beta, aprev, zero2, zero2, acc);
+    stencil_tile<2, M_PCG_J, SYM>(tv, local - js * ntiles, ring, sym, beta, aprev, zero2, zero2, acc);
   }
   if (cur >= 0) flush();
+}
+
+// r -= alpha q for active members, then the partial sums r^T r and r^T z
+// (z = r / diag) of two members
+__device__ __forceinline__ void update_pair(double (&rv)[2], const double (&qv)[2], const double (&dv)[2],
+                                            const double (&act)[2], const double (&alpha)[2],
+                                            double (&rr)[2], double (&rz)[2]) {
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    if (act[c] != 0.0 && alpha[c] != 0.0) rv[c] = fma(-alpha[c], qv[c], rv[c]);
+    rr[c] = fma(rv[c], rv[c], rr[c]);
+    rz[c] = fma(rv[c], rv[c] / dv[c], rz[c]);
+  }
 }
 
 __global__ __launch_bounds__(kNT) void batch_update_kernel(BatchArgs a) {
@@ -172,67 +208,77 @@ __global__ __launch_bounds__(kNT) void batch_update_kernel(BatchArgs a) {
   const double* q_in = nullptr;
   const double* d_in = nullptr;
   size_t nelem = 0;
-  int first = 0;
+  int first = 0, rows = 1;
+  double* partial = nullptr;
   auto flush = [&]() {
     group_reduce<2>(rr, tpp, red);
     group_reduce<2>(rz, tpp, red);
-    const BatchEns& E = a.ens[cur];
     if (t < tpp) {
-      const int rows = min(a.G, E.neunits);
       const int row = partial_row(L, first, a.G);
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
-        E.partial[(size_t)row * S + t * 2 + c] = rz[c];
-        E.partial[(size_t)rows * S + (size_t)row * S + t * 2 + c] = rr[c];
+        gstore(&partial[(size_t)row * S + t * 2 + c], rz[c]);
+        gstore(&partial[(size_t)rows * S + (size_t)row * S + t * 2 + c], rr[c]);
       }
     }
   };
   for (int u = L; u < a.EU; u += a.G) {
     if (u >= s_prefix[e + 1]) e = owner(s_prefix, a.n_ens, u);   // next ensemble
-    if (s_done[e]) continue;
+    e = uni(e);
+    if (uni(s_done[e])) continue;
     if (e != cur) {
       if (cur >= 0) flush();
       cur = e;
       const BatchEns& E = a.ens[e];
-      S = E.S;
-      tpp = E.tpp;
-      nelem = E.nelem;
+      S = uni(E.S);
+      tpp = uni(E.tpp);
+      nelem = uni(E.nelem);
       first = s_prefix[e];
-      r_in = E.r;
-      r_out = E.r;
-      q_in = E.q;
-      d_in = E.V + 4 * E.nelem;
+      rows = min(a.G, uni(E.neunits));
+      partial = uni(E.partial);
+      r_in = uni(E.r);
+      r_out = uni(E.r);
+      q_in = uni(E.q);
+      d_in = uni(E.V) + 4 * nelem;
       const int sv = (t % tpp) * 2;
+      const int* ma = uni(E.m.active);
+      const double* mal = uni(E.m.alpha);
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
-        act[c] = E.m.active[sv + c] ? 1.0 : 0.0;
-        alpha[c] = E.m.alpha[sv + c];
+        act[c] = gload(&ma[sv + c]) ? 1.0 : 0.0;
+        alpha[c] = gload(&mal[sv + c]);
         rz[c] = 0.0;
         rr[c] = 0.0;
       }
     }
     const size_t base = (size_t)(u - first) * kUpdateChunk;
-    double rv[4][2], qv[4][2], dv[4][2];
+    if (base + kUpdateChunk <= nelem) {
+      // a whole chunk: twelve loads in flight, no per-lane predicates
+      double rv[4][2], qv[4][2], dv[4][2];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const size_t el = base + ((size_t)k * kNT + t) * 2;
-      if (el < nelem) {
+      for (int k = 0; k < 4; ++k) {
+        const size_t el = base + ((size_t)k * kNT + t) * 2;
         ld<2>(rv[k], r_in + el);
         ld<2>(qv[k], q_in + el);
         ld<2>(dv[k], d_in + el);
       }
-    }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const size_t el = base + ((size_t)k * kNT + t) * 2;
-      if (el < nelem) {
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          if (act[c] != 0.0 && alpha[c] != 0.0) rv[k][c] = fma(-alpha[c], qv[k][c], rv[k][c]);
-          rr[c] = fma(rv[k][c], rv[k][c], rr[c]);
-          rz[c] = fma(rv[k][c], rv[k][c] / dv[k][c], rz[c]);
+      for (int k = 0; k < 4; ++k) {
+        update_pair(rv[k], qv[k], dv[k], act, alpha, rr, rz);
+        st<2>(r_out + base + ((size_t)k * kNT + t) * 2, rv[k]);
+      }
+    } else {
+      // the ensemble's last, partial chunk
+      for (int k = 0; k < 4; ++k) {
+        const size_t el = base + ((size_t)k * kNT + t) * 2;
+        if (el < nelem) {
+          double rv[2], qv[2], dv[2];
+          ld<2>(rv, r_in + el);
+          ld<2>(qv, q_in + el);
+          ld<2>(dv, d_in + el);
+          update_pair(rv, qv, dv, act, alpha, rr, rz);
+          st<2>(r_out + el, rv);
         }
-        st<2>(r_out + el, rv[k]);
       }
     }
   }
@@ -242,13 +288,13 @@ __global__ __launch_bounds__(kNT) void batch_update_kernel(BatchArgs a) {
 // one workgroup per ensemble: alpha (stage 0) or the convergence test and
 // beta (stage 1), which retires the ensemble when its last member stops
 template <int STAGE>
-__global__ __launch_bounds__(kNT) void batch_finish_kernel(BatchArgs a) {
-  __shared__ double fin[2 * kNT * 2];
+__global__ __launch_bounds__(kFinNT) void batch_finish_kernel(BatchArgs a) {
+  __shared__ double fin[2 * kFinNT * 2];
   __shared__ int live;
   const int e = blockIdx.x;
   if (a.done[e]) return;
   const BatchEns& E = a.ens[e];
-  if (E.m.ctl[CTL_DONE]) {
+  if (gload(&E.m.ctl[CTL_DONE])) {
     // retired before the first step (every member had b = 0)
     if (STAGE == 0 && threadIdx.x == 0) {
       a.clock[1 + e] = wall_clock64();
@@ -446,17 +492,17 @@ int ens_batch_solve(const ens_opts* opts, int32_t n_items, ens_batch_item* items
                                : reinterpret_cast<const void*>(&batch_stencil_kernel<true>);
   struct NodeSpec {
     const void* fn;
-    unsigned grid;
-  } specs[4] = {{stencil_fn, (unsigned)G},
-                {reinterpret_cast<const void*>(&batch_finish_kernel<0>), (unsigned)n_items},
-                {reinterpret_cast<const void*>(&batch_update_kernel), (unsigned)G},
-                {reinterpret_cast<const void*>(&batch_finish_kernel<1>), (unsigned)n_items}};
+    unsigned grid, block;
+  } specs[4] = {{stencil_fn, (unsigned)G, (unsigned)kNT},
+                {reinterpret_cast<const void*>(&batch_finish_kernel<0>), (unsigned)n_items, (unsigned)kFinNT},
+                {reinterpret_cast<const void*>(&batch_update_kernel), (unsigned)G, (unsigned)kNT},
+                {reinterpret_cast<const void*>(&batch_finish_kernel<1>), (unsigned)n_items, (unsigned)kFinNT}};
   for (int k = 0; k < 4 && he == hipSuccess; ++k) {
     hipKernelNodeParams kp;
     std::memset(&kp, 0, sizeof(kp));
     kp.func = const_cast<void*>(specs[k].fn);
     kp.gridDim = dim3(specs[k].grid);
-    kp.blockDim = dim3(kNT);
+    kp.blockDim = dim3(specs[k].block);
     kp.sharedMemBytes = 0;
     kp.kernelParams = args;
     kp.extra = nullptr;

@@ -12,6 +12,7 @@ namespace ens {
 
 constexpr int kNT = 256;          // threads per workgroup (4 wave64s)
 constexpr int kWaves = kNT / 64;
+constexpr int kFinNT = 256;       // threads of a one-workgroup finishing kernel
 constexpr int kMaxS = 64;
 constexpr int kMaxGroups = 2048;  // cap on workgroups of reducing kernels
 constexpr int kRing = 2 * kNT + 2 * kMaxS;  // doubles per LDS ring line (tile + halo)

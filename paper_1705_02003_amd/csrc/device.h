@@ -10,14 +10,37 @@ namespace ens {
 typedef double d2 __attribute__((ext_vector_type(2)));
 
 // ------------------------------------------------------------ load/store
+// Every buffer of this library is in global memory.  The helpers below
+// access it through global-address-space pointers: a pointer loaded from
+// memory (rather than passed as a kernel argument) is otherwise generic to
+// the compiler, which then emits flat instructions, and flat loads also count
+// against the LDS wait counter, so every LDS wait of the tile sweep would
+// stall on them.
+#define ENS_GLOBAL __attribute__((address_space(1)))
+
+template <class T>
+__device__ __forceinline__ T gload(const T* p) {
+  return *(const ENS_GLOBAL T*)p;
+}
+
+template <class T>
+struct same_type {
+  using type = T;
+};
+
+template <class T>
+__device__ __forceinline__ void gstore(T* p, typename same_type<T>::type v) {
+  *(ENS_GLOBAL T*)p = v;
+}
+
 template <int VEC>
 __device__ __forceinline__ void ld(double (&v)[VEC], const double* p) {
   if constexpr (VEC == 2) {
-    const d2 t = *reinterpret_cast<const d2*>(p);
+    const d2 t = *(const ENS_GLOBAL d2*)p;
     v[0] = t.x;
     v[1] = t.y;
   } else {
-    v[0] = *p;
+    v[0] = *(const ENS_GLOBAL double*)p;
   }
 }
 
@@ -26,11 +49,11 @@ __device__ __forceinline__ void ld(double (&v)[VEC], const double* p) {
 template <int VEC>
 __device__ __forceinline__ void ld_stream(double (&v)[VEC], const double* p) {
   if constexpr (VEC == 2) {
-    const d2 t = __builtin_nontemporal_load(reinterpret_cast<const d2*>(p));
+    const d2 t = __builtin_nontemporal_load((const ENS_GLOBAL d2*)p);
     v[0] = t.x;
     v[1] = t.y;
   } else {
-    v[0] = __builtin_nontemporal_load(p);
+    v[0] = __builtin_nontemporal_load((const ENS_GLOBAL double*)p);
   }
 }
 
@@ -40,9 +63,9 @@ __device__ __forceinline__ void st(double* p, const double (&v)[VEC]) {
     d2 t;
     t.x = v[0];
     t.y = v[1];
-    *reinterpret_cast<d2*>(p) = t;
+    *(ENS_GLOBAL d2*)p = t;
   } else {
-    *p = v[0];
+    *(ENS_GLOBAL double*)p = v[0];
   }
 }
 
@@ -107,31 +130,40 @@ __device__ __forceinline__ void put_partial(double* partial, int S, int tpp, con
 }
 
 // Member sums of NARR partial arrays P[a][g][s] over the workgroups g < G,
-// returned for member s = threadIdx.x (t < S).  Thread t loads VEC members
-// per row (16-byte loads when VEC = 2); the R = kNT * VEC / S row sets are
-// k, k + R, k + 2R, ... with k = t / (S / VEC), summed in that order with up
-// to 16 loads in flight, then a fixed halving tree over k.  The order does
-// not depend on the member.  `lds` holds NARR * kNT * VEC doubles.
+// returned for member s = threadIdx.x (t < S), in a block of kFinNT
+// threads.  Thread t loads VEC members per row (16-byte loads when VEC = 2);
+// the R = kFinNT * VEC / S row sets are k, k + R, k + 2R, ... with
+// k = t / (S / VEC), summed in that order with up to 32 loads in flight,
+// then a fixed halving tree over k.  The order does not depend on the
+// member.  `lds` holds NARR * kFinNT * VEC doubles.
 template <int VEC, int NARR>
 __device__ __forceinline__ void final_sums(const double* const (&P)[NARR], int G, int S,
                                            double* lds, double (&out)[NARR]) {
   const int t = threadIdx.x;
-  const int W = S / VEC, R = kNT / W;
+  const int W = S / VEC, R = kFinNT / W;
   const int pr = t % W, k = t / W;
   const int col = pr * VEC;
-  constexpr int B = 16 / NARR;
+  constexpr int B = 32 / NARR;
   double acc[NARR][VEC];
 #pragma unroll
   for (int a = 0; a < NARR; ++a)
 #pragma unroll
     for (int c = 0; c < VEC; ++c) acc[a][c] = 0.0;
-  int g = k;
-  for (; g + (B - 1) * R < G; g += B * R) {
+  // rows k, k + R, k + 2R, ... in increasing order, B of them in flight;
+  // rows past G contribute +0
+  for (int g = k; g < G; g += B * R) {
     double v[NARR][B][VEC];
 #pragma unroll
     for (int a = 0; a < NARR; ++a)
 #pragma unroll
-      for (int u = 0; u < B; ++u) ld<VEC>(v[a][u], P[a] + (size_t)(g + u * R) * S + col);
+      for (int u = 0; u < B; ++u) {
+        if (g + u * R < G) {
+          ld<VEC>(v[a][u], P[a] + (size_t)(g + u * R) * S + col);
+        } else {
+#pragma unroll
+          for (int c = 0; c < VEC; ++c) v[a][u][c] = 0.0;
+        }
+      }
 #pragma unroll
     for (int a = 0; a < NARR; ++a)
 #pragma unroll
@@ -139,20 +171,11 @@ __device__ __forceinline__ void final_sums(const double* const (&P)[NARR], int G
 #pragma unroll
         for (int c = 0; c < VEC; ++c) acc[a][c] += v[a][u][c];
   }
-  for (; g < G; g += R) {
-#pragma unroll
-    for (int a = 0; a < NARR; ++a) {
-      double v[VEC];
-      ld<VEC>(v, P[a] + (size_t)g * S + col);
-#pragma unroll
-      for (int c = 0; c < VEC; ++c) acc[a][c] += v[c];
-    }
-  }
   __syncthreads();
 #pragma unroll
   for (int a = 0; a < NARR; ++a)
 #pragma unroll
-    for (int c = 0; c < VEC; ++c) lds[a * kNT * VEC + k * S + col + c] = acc[a][c];
+    for (int c = 0; c < VEC; ++c) lds[a * kFinNT * VEC + k * S + col + c] = acc[a][c];
   __syncthreads();
   for (int stride = (R / 2) * S; stride >= S; stride >>= 1) {
 #pragma unroll
@@ -160,13 +183,13 @@ __device__ __forceinline__ void final_sums(const double* const (&P)[NARR], int G
 #pragma unroll
       for (int c = 0; c < VEC; ++c) {
         const int i = t * VEC + c;
-        if (i < stride) lds[a * kNT * VEC + i] += lds[a * kNT * VEC + i + stride];
+        if (i < stride) lds[a * kFinNT * VEC + i] += lds[a * kFinNT * VEC + i + stride];
       }
     __syncthreads();
   }
   const int s = t & (S - 1);
 #pragma unroll
-  for (int a = 0; a < NARR; ++a) out[a] = lds[a * kNT * VEC + s];
+  for (int a = 0; a < NARR; ++a) out[a] = lds[a * kFinNT * VEC + s];
 }
 
 template <int VEC>
@@ -178,13 +201,13 @@ __device__ __forceinline__ double final_sum(const double* partial, int G, int S,
 }
 
 __device__ __forceinline__ double final_max(const double* partial, int G, int S, double* lds) {
-  const int t = threadIdx.x, s = t & (S - 1), k = t / S, T = kNT / S;
+  const int t = threadIdx.x, s = t & (S - 1), k = t / S, T = kFinNT / S;
   double acc = 0.0;
-  for (int g = k; g < G; g += T) acc = fmax(acc, partial[(size_t)g * S + s]);
+  for (int g = k; g < G; g += T) acc = fmax(acc, gload(&partial[(size_t)g * S + s]));
   __syncthreads();
   lds[t] = acc;
   __syncthreads();
-  for (int stride = kNT / 2; stride >= S; stride >>= 1) {
+  for (int stride = kFinNT / 2; stride >= S; stride >>= 1) {
     if (t < stride) lds[t] = fmax(lds[t], lds[t + stride]);
     __syncthreads();
   }
@@ -257,235 +280,242 @@ __device__ __forceinline__ void stencil_tile(const TileView& a, int tile, double
                                              const double (&beta)[VEC], const double (&aprev)[VEC],
                                              const double (&c1)[VEC], const double (&c2)[VEC],
                                              double (&acc)[VEC]) {
+  constexpr bool PCG = (MODE == M_PCG_J || MODE == M_PCG_Z);
   const int t = threadIdx.x;
   const int S = a.S, n = a.n, tpp = a.tpp, sw = a.sw;
   const int lp = t / tpp;
   const int cl = (t % tpp) * VEC;   // first member of this thread within the tile
   const int sv = a.s0 + cl;         // ... within the ensemble
   const size_t slot_stride = a.nelem;
+  const size_t line_stride = (size_t)n * S;
   const int chunk = tile % a.nchunk, band = tile / a.nchunk;
   const int i0 = chunk * a.tx, j0 = band * a.ty;
   const int j1 = min(j0 + a.ty, n);
   const int i = i0 + lp;
   const bool own_i = i < n;
+  // halo duty: threads t < tpp also hold the point left of the chunk,
+  // threads tpp <= t < 2 tpp the point right of it
+  const bool halo = t < 2 * tpp, left_halo = t < tpp;
+  const int hpt = left_halo ? -1 : a.tx;
+  const int hi = i0 + hpt;
+  const bool halo_i = hi >= 0 && hi < n;
+  // Loads are issued by every lane at a point clamped into the grid and the
+  // values of lanes without that point are replaced by zero afterwards: a
+  // load inside a lane-dependent branch whose value is used after the branch
+  // makes the compiler wait for it at the branch's end, before the line's
+  // other loads are issued.
+  const size_t col = (size_t)min(i, n - 1) * S + sv;
+  const size_t hcol = (size_t)min(max(hi, 0), n - 1) * S + sv;
+  auto row = [&](int jj) { return (size_t)min(max(jj, 0), n - 1) * line_stride; };
 
   // retained per own point: previous direction, diagonal, ring value
   double cur_pold[VEC], cur_v4[VEC], cur_val[VEC];
   double nxt_pold[VEC], nxt_v4[VEC], nxt_val[VEC];
 
-  // form the ring values of line jj; `own` marks a line of this tile
-  auto fill = [&](int jj, bool own, double (&rp)[VEC], double (&rv4)[VEC], double (&rval)[VEC]) {
-    double* line = ring[(jj - j0 + 4) & 3];
-    double val[VEC];
-    const bool in_line = (jj >= 0 && jj < n);
-    if (in_line && own_i) {
-      const size_t e = ((size_t)jj * n + i) * S + sv;
-      if constexpr (MODE == M_SPMV || MODE == M_CHEB) {
-        ld<VEC>(val, a.src + e);
-      } else if constexpr (MODE == M_PCG_J) {
-        double rr[VEC], pp[VEC], dd[VEC];
-        ld<VEC>(rr, a.r + e);
-        ld<VEC>(pp, a.pold + e);
-        ld<VEC>(dd, a.V + 4 * slot_stride + e);
-#pragma unroll
-        for (int c = 0; c < VEC; ++c) {
-          val[c] = fma(beta[c], pp[c], rr[c] / dd[c]);
-          rp[c] = pp[c];
-          rv4[c] = dd[c];
-        }
-        if (own) st<VEC>(a.pnew + e, val);
-      } else {  // M_PCG_Z
-        double zz[VEC], pp[VEC];
-        ld<VEC>(zz, a.src + e);
-        ld<VEC>(pp, a.pold + e);
-#pragma unroll
-        for (int c = 0; c < VEC; ++c) {
-          val[c] = fma(beta[c], pp[c], zz[c]);
-          rp[c] = pp[c];
-        }
-        if (own) st<VEC>(a.pnew + e, val);
-      }
-    } else {
-#pragma unroll
-      for (int c = 0; c < VEC; ++c) val[c] = 0.0;
+  // the inputs of a ring value at element e, and the value itself:
+  // M_PCG_J r / diag + beta p_old, M_PCG_Z z + beta p_old, else the source
+  auto fill_load = [&](size_t e, double (&v0)[VEC], double (&v1)[VEC], double (&v2)[VEC]) {
+    if constexpr (MODE == M_SPMV || MODE == M_CHEB) {
+      ld<VEC>(v0, a.src + e);
+    } else if constexpr (MODE == M_PCG_J) {
+      ld<VEC>(v0, a.r + e);
+      ld<VEC>(v1, a.pold + e);
+      ld<VEC>(v2, a.V + 4 * slot_stride + e);
+    } else {  // M_PCG_Z
+      ld<VEC>(v0, a.src + e);
+      ld<VEC>(v1, a.pold + e);
     }
+  };
+  auto combine = [&](const double (&v0)[VEC], const double (&v1)[VEC], const double (&v2)[VEC],
+                     bool ok, double (&out)[VEC]) {
 #pragma unroll
     for (int c = 0; c < VEC; ++c) {
+      double v;
+      if constexpr (MODE == M_PCG_J) v = fma(beta[c], v1[c], v0[c] / v2[c]);
+      else if constexpr (MODE == M_PCG_Z) v = fma(beta[c], v1[c], v0[c]);
+      else v = v0[c];
+      out[c] = ok ? v : 0.0;
+    }
+  };
+  // Ring values: the own point of ring line jj (`own` marks a line of this
+  // tile, whose new direction is also stored) and, for the halo lanes, the
+  // halo point.  The halo branch is entered only after every load of the
+  // line has been issued, so its wait is the line's one round trip.
+  auto put_own = [&](int jj, bool own, const double (&o0)[VEC], const double (&o1)[VEC],
+                     const double (&o2)[VEC], double (&rp)[VEC], double (&rv4)[VEC],
+                     double (&rval)[VEC]) {
+    double* line = ring[(jj - j0 + 4) & 3];
+    const bool ok = jj >= 0 && jj < n && own_i;
+    double val[VEC];
+    combine(o0, o1, o2, ok, val);
+#pragma unroll
+    for (int c = 0; c < VEC; ++c) {
+      rp[c] = PCG ? o1[c] : 0.0;
+      rv4[c] = (MODE == M_PCG_J) ? o2[c] : 0.0;
       line[(lp + 1) * sw + cl + c] = val[c];
       rval[c] = val[c];
     }
-    // one-point halo on both sides of the chunk
-    if (t < 2 * tpp) {
-      const int hp = (t < tpp) ? -1 : a.tx;
-      const int hi = i0 + hp;
-      double hv[VEC];
-      if (in_line && hi >= 0 && hi < n) {
-        const size_t he = ((size_t)jj * n + hi) * S + sv;
-        if constexpr (MODE == M_SPMV || MODE == M_CHEB) {
-          ld<VEC>(hv, a.src + he);
-        } else if constexpr (MODE == M_PCG_J) {
-          double rr[VEC], pp[VEC], dd[VEC];
-          ld<VEC>(rr, a.r + he);
-          ld<VEC>(pp, a.pold + he);
-          ld<VEC>(dd, a.V + 4 * slot_stride + he);
-#pragma unroll
-          for (int c = 0; c < VEC; ++c) hv[c] = fma(beta[c], pp[c], rr[c] / dd[c]);
-        } else {
-          double zz[VEC], pp[VEC];
-          ld<VEC>(zz, a.src + he);
-          ld<VEC>(pp, a.pold + he);
-#pragma unroll
-          for (int c = 0; c < VEC; ++c) hv[c] = fma(beta[c], pp[c], zz[c]);
-        }
-      } else {
-#pragma unroll
-        for (int c = 0; c < VEC; ++c) hv[c] = 0.0;
-      }
-#pragma unroll
-      for (int c = 0; c < VEC; ++c) line[(hp + 1) * sw + cl + c] = hv[c];
+    if constexpr (PCG) {
+      if (ok && own) st<VEC>(a.pnew + row(jj) + col, val);
     }
+  };
+  auto put_halo = [&](int jj, const double (&h0)[VEC], const double (&h1)[VEC],
+                      const double (&h2)[VEC]) {
+    double hv[VEC];
+    combine(h0, h1, h2, jj >= 0 && jj < n && halo_i, hv);
+#pragma unroll
+    for (int c = 0; c < VEC; ++c) ring[(jj - j0 + 4) & 3][(hpt + 1) * sw + cl + c] = hv[c];
   };
 
   // symmetric sweep: per line slot (j - j0) & 1, LDS lines of E (line j),
   // NE and NW (line j - 1), each with the one-point halo
   auto symL = [&](int jj, int w) { return sym + (((jj - j0) & 1) * 3 + w) * kRing; };
-  const bool left_halo = t < tpp, halo = t < 2 * tpp;
-  const int hi = i0 + (left_halo ? -1 : a.tx);   // halo point of this thread
   double prevN[VEC], prevNE[VEC], prevNW[VEC];   // own point, line j - 1
-#pragma unroll
-  for (int c = 0; c < VEC; ++c) prevN[c] = prevNE[c] = prevNW[c] = 0.0;
 
   __syncthreads();  // the previous tile's readers are done with the ring
   {
-    double d0[VEC], d1[VEC], d2v[VEC];
-    fill(j0 - 1, false, d0, d1, d2v);
-  }
-  if constexpr (SYM) {
-    if (j0 > 0 && own_i) {
-      const size_t ep = ((size_t)(j0 - 1) * n + i) * S + sv;
+    if constexpr (SYM) {
+      const size_t ep = row(j0 - 1) + col;
       ld_stream<VEC>(prevN, a.V + 7 * slot_stride + ep);
       ld_stream<VEC>(prevNE, a.V + 8 * slot_stride + ep);
       ld_stream<VEC>(prevNW, a.V + 6 * slot_stride + ep);
     }
-  }
-  fill(j0, true, cur_pold, cur_v4, cur_val);
-  for (int j = j0; j < j1; ++j) {
-    // Issue this line's matrix values (and x, or the Chebyshev r and d)
-    // before forming the next ring line: both sets of loads are then in
-    // flight together and the line costs one memory round trip.
-    const size_t e = ((size_t)j * n + i) * S + sv;
-    double vk[9][VEC], xv[VEC], rr[VEC], dd[VEC], hE[VEC], hX[VEC];
-    if constexpr (SYM) {
-#pragma unroll
-      for (int k = 0; k < 9; ++k)
-#pragma unroll
-        for (int c = 0; c < VEC; ++c) vk[k][c] = 0.0;
-#pragma unroll
-      for (int c = 0; c < VEC; ++c) hE[c] = hX[c] = 0.0;
+    double a0[VEC], a1[VEC], a2[VEC], b0[VEC], b1[VEC], b2[VEC];
+    fill_load(row(j0 - 1) + col, a0, a1, a2);
+    fill_load(row(j0) + col, b0, b1, b2);
+    if (halo) {
+      double h0[VEC], h1[VEC], h2[VEC], g0[VEC], g1[VEC], g2[VEC];
+      fill_load(row(j0 - 1) + hcol, h0, h1, h2);
+      fill_load(row(j0) + hcol, g0, g1, g2);
+      put_halo(j0 - 1, h0, h1, h2);
+      put_halo(j0, g0, g1, g2);
     }
-    if (own_i) {
-#pragma unroll
-      for (int k = 0; k < 9; ++k) {
-        if (SYM && k < 4) continue;   // lower coefficients: from neighbours
-        if (k == 4 && MODE == M_PCG_J) {
-#pragma unroll
-          for (int c = 0; c < VEC; ++c) vk[4][c] = cur_v4[c];
-        } else {
-          ld_stream<VEC>(vk[k], a.V + (size_t)k * slot_stride + e);
-        }
-      }
-      if constexpr (MODE == M_PCG_J || MODE == M_PCG_Z) ld<VEC>(xv, a.x + e);
-      if constexpr (MODE == M_CHEB) {
-        ld<VEC>(rr, a.r + e);
-        ld<VEC>(dd, a.d + e);
-      }
-    }
+    double d0[VEC], d1[VEC], d2v[VEC];
+    put_own(j0 - 1, false, a0, a1, a2, d0, d1, d2v);
+    put_own(j0, true, b0, b1, b2, cur_pold, cur_v4, cur_val);
     if constexpr (SYM) {
-      // halo: E(i0 - 1, j) and NE(i0 - 1, j - 1) left of the chunk,
-      // NW(i0 + tx, j - 1) right of it
-      if (halo && hi >= 0 && hi < n) {
-        const size_t he = ((size_t)j * n + hi) * S + sv;
-        if (left_halo) {
-          ld_stream<VEC>(hE, a.V + 5 * slot_stride + he);
-          if (j > 0) ld_stream<VEC>(hX, a.V + 8 * slot_stride + he - (size_t)n * S);
-        } else if (j > 0) {
-          ld_stream<VEC>(hX, a.V + 6 * slot_stride + he - (size_t)n * S);
-        }
-      }
-    }
-    fill(j + 1, j + 1 < j1, nxt_pold, nxt_v4, nxt_val);
-    if constexpr (SYM) {
-      double* lE = symL(j, 0);
-      double* lNE = symL(j, 1);
-      double* lNW = symL(j, 2);
+      const bool okp = j0 > 0 && own_i;
 #pragma unroll
       for (int c = 0; c < VEC; ++c) {
-        lE[(lp + 1) * sw + cl + c] = vk[5][c];
-        lNE[(lp + 1) * sw + cl + c] = prevNE[c];
-        lNW[(lp + 1) * sw + cl + c] = prevNW[c];
-        if (halo) {
+        prevN[c] = okp ? prevN[c] : 0.0;
+        prevNE[c] = okp ? prevNE[c] : 0.0;
+        prevNW[c] = okp ? prevNW[c] : 0.0;
+      }
+    }
+  }
+  for (int j = j0; j < j1; ++j) {
+    // This line's matrix values (and x, or the Chebyshev r and d), the next
+    // ring line's inputs and the halo values are all issued before any is
+    // used: the line costs one memory round trip.
+    const size_t rj = (size_t)j * line_stride;
+    const size_t e = rj + col;
+    double vk[9][VEC], xv[VEC], rr[VEC], dd[VEC];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      if (SYM && k < 4) continue;                 // lower coefficients: from neighbours
+      if (k == 4 && MODE == M_PCG_J) continue;    // the diagonal came with the ring line
+      ld_stream<VEC>(vk[k], a.V + (size_t)k * slot_stride + e);
+    }
+    if constexpr (PCG) ld<VEC>(xv, a.x + e);
+    if constexpr (MODE == M_CHEB) {
+      ld<VEC>(rr, a.r + e);
+      ld<VEC>(dd, a.d + e);
+    }
+    double o0[VEC], o1[VEC], o2[VEC];
+    fill_load(row(j + 1) + col, o0, o1, o2);
+    if (halo) {
+      double h0[VEC], h1[VEC], h2[VEC], hE[VEC], hX[VEC];
+      fill_load(row(j + 1) + hcol, h0, h1, h2);
+      if constexpr (SYM) {
+        // E(i0 - 1, j) and NE(i0 - 1, j - 1) left of the chunk,
+        // NW(i0 + tx, j - 1) right of it
+        ld_stream<VEC>(hE, a.V + 5 * slot_stride + rj + hcol);
+        ld_stream<VEC>(hX, a.V + (left_halo ? 8 : 6) * slot_stride + row(j - 1) + hcol);
+      }
+      put_halo(j + 1, h0, h1, h2);
+      if constexpr (SYM) {
+        const bool okE = halo_i && left_halo, okX = halo_i && j > 0;
+#pragma unroll
+        for (int c = 0; c < VEC; ++c) {
           if (left_halo) {
-            lE[cl + c] = hE[c];
-            lNE[cl + c] = hX[c];
+            symL(j, 0)[cl + c] = okE ? hE[c] : 0.0;
+            symL(j, 1)[cl + c] = okX ? hX[c] : 0.0;
           } else {
-            lNW[(a.tx + 1) * sw + cl + c] = hX[c];
+            symL(j, 2)[(a.tx + 1) * sw + cl + c] = okX ? hX[c] : 0.0;
           }
         }
       }
     }
+    put_own(j + 1, j + 1 < j1, o0, o1, o2, nxt_pold, nxt_v4, nxt_val);
+    if constexpr (MODE == M_PCG_J) {
+#pragma unroll
+      for (int c = 0; c < VEC; ++c) vk[4][c] = cur_v4[c];
+    }
+    if constexpr (SYM) {
+#pragma unroll
+      for (int c = 0; c < VEC; ++c) {
+        symL(j, 0)[(lp + 1) * sw + cl + c] = own_i ? vk[5][c] : 0.0;
+        symL(j, 1)[(lp + 1) * sw + cl + c] = prevNE[c];
+        symL(j, 2)[(lp + 1) * sw + cl + c] = prevNW[c];
+      }
+    }
     __syncthreads();
-    if (own_i) {
-      if constexpr (SYM) {
-        // lower coefficients of row (i, j): SW = NE(i-1, j-1), S = N(i, j-1),
-        // SE = NW(i+1, j-1), W = E(i-1, j)
-        const double* pSW = symL(j, 1) + lp * sw + cl;
-        const double* pSE = symL(j, 2) + (lp + 2) * sw + cl;
-        const double* pW = symL(j, 0) + lp * sw + cl;
+    if constexpr (SYM) {
+      // lower coefficients of row (i, j): SW = NE(i-1, j-1), S = N(i, j-1),
+      // SE = NW(i+1, j-1), W = E(i-1, j)
+      const double* pSW = symL(j, 1) + lp * sw + cl;
+      const double* pSE = symL(j, 2) + (lp + 2) * sw + cl;
+      const double* pW = symL(j, 0) + lp * sw + cl;
 #pragma unroll
-        for (int c = 0; c < VEC; ++c) {
-          vk[0][c] = pSW[c];
-          vk[1][c] = prevN[c];
-          vk[2][c] = pSE[c];
-          vk[3][c] = pW[c];
-          prevN[c] = vk[7][c];
-          prevNE[c] = vk[8][c];
-          prevNW[c] = vk[6][c];
-        }
+      for (int c = 0; c < VEC; ++c) {
+        vk[0][c] = pSW[c];
+        vk[1][c] = prevN[c];
+        vk[2][c] = pSE[c];
+        vk[3][c] = pW[c];
+        prevN[c] = own_i ? vk[7][c] : 0.0;
+        prevNE[c] = own_i ? vk[8][c] : 0.0;
+        prevNW[c] = own_i ? vk[6][c] : 0.0;
       }
-      double q[VEC];
+    }
+    double q[VEC];
 #pragma unroll
-      for (int k = 0; k < 9; ++k) {
-        const int dj = k / 3 - 1, di = k % 3 - 1;
-        const double* rp = &ring[(j + dj - j0 + 4) & 3][(lp + 1 + di) * sw + cl];
-        double pv[VEC];
-        if constexpr (VEC == 2) {
-          const d2 tt = *reinterpret_cast<const d2*>(rp);
-          pv[0] = tt.x;
-          pv[1] = tt.y;
-        } else {
-          pv[0] = rp[0];
-        }
-#pragma unroll
-        for (int c = 0; c < VEC; ++c) q[c] = (k == 0) ? vk[0][c] * pv[c] : fma(vk[k][c], pv[c], q[c]);
+    for (int k = 0; k < 9; ++k) {
+      const int dj = k / 3 - 1, di = k % 3 - 1;
+      const double* rp = &ring[(j + dj - j0 + 4) & 3][(lp + 1 + di) * sw + cl];
+      double pv[VEC];
+      if constexpr (VEC == 2) {
+        const d2 tt = *reinterpret_cast<const d2*>(rp);
+        pv[0] = tt.x;
+        pv[1] = tt.y;
+      } else {
+        pv[0] = rp[0];
       }
-      if constexpr (MODE == M_SPMV) {
-        st<VEC>(a.q + e, q);
-      } else if constexpr (MODE == M_PCG_J || MODE == M_PCG_Z) {
-        st<VEC>(a.q + e, q);
 #pragma unroll
-        for (int c = 0; c < VEC; ++c) {
-          acc[c] = fma(cur_val[c], q[c], acc[c]);
-          if (aprev[c] != 0.0) xv[c] = fma(aprev[c], cur_pold[c], xv[c]);
-        }
+      for (int c = 0; c < VEC; ++c) q[c] = (k == 0) ? vk[0][c] * pv[c] : fma(vk[k][c], pv[c], q[c]);
+    }
+    // lanes without a point (the last chunk of a line) store nothing and
+    // add nothing
+    if constexpr (MODE == M_SPMV) {
+      if (own_i) st<VEC>(a.q + e, q);
+    } else if constexpr (PCG) {
+#pragma unroll
+      for (int c = 0; c < VEC; ++c) {
+        acc[c] = own_i ? fma(cur_val[c], q[c], acc[c]) : acc[c];
+        if (aprev[c] != 0.0) xv[c] = fma(aprev[c], cur_pold[c], xv[c]);
+      }
+      if (own_i) {
+        st<VEC>(a.q + e, q);
         st<VEC>(a.x + e, xv);
-      } else {  // M_CHEB
-        double zn[VEC];
+      }
+    } else {  // M_CHEB
+      double zn[VEC];
 #pragma unroll
-        for (int c = 0; c < VEC; ++c) {
-          dd[c] = c1[c] * dd[c] + c2[c] * ((rr[c] - q[c]) / vk[4][c]);
-          zn[c] = cur_val[c] + dd[c];
-          if (a.cheb_last) acc[c] = fma(rr[c], zn[c], acc[c]);
-        }
+      for (int c = 0; c < VEC; ++c) {
+        dd[c] = c1[c] * dd[c] + c2[c] * ((rr[c] - q[c]) / vk[4][c]);
+        zn[c] = cur_val[c] + dd[c];
+        if (a.cheb_last) acc[c] = own_i ? fma(rr[c], zn[c], acc[c]) : acc[c];
+      }
+      if (own_i) {
         st<VEC>(a.d + e, dd);
         st<VEC>(a.zout + e, zn);
       }
@@ -500,97 +530,114 @@ __device__ __forceinline__ void stencil_tile(const TileView& a, int tile, double
 }
 
 // Reduce a producer's per-workgroup partials in a fixed order and apply the
-// per-member scalar logic of the step (one workgroup).  `fin` holds
-// 2 * kNT * 2 doubles.  Returns 1 when this call retired the ensemble.
+// per-member scalar logic of the step (one workgroup of kFinNT threads).
+// `fin` holds 2 * kFinNT * 2 doubles.  Returns 1 when this call retired the
+// ensemble.
 template <int VEC>
 __device__ __forceinline__ int finish_body(const FinishArgs& a, double* fin, int& live) {
   const int S = a.g.S, t = threadIdx.x;
   const Members& m = a.m;
   const size_t ps = (size_t)a.G * S;
-  if (a.kind != F_INIT && a.kind != F_DOT && a.kind != F_SUMS) {
-    if (m.ctl[CTL_DONE]) return 0;
-  }
   switch (a.kind) {
-    case F_ALPHA: {
-      // p^T A p per member -> alpha, or freeze the member (the guard)
-      const double sig = final_sum<VEC>(a.partial, a.G, S, fin);
-      if (t < S) {
-        double al = 0.0;
-        if (m.active[t]) {
-          if (isfinite(sig) && sig > 0.0) {
-            al = m.rho[t] / sig;
-          } else {
-            m.active[t] = 0;
-            m.status[t] = ENS_BREAKDOWN;
-            m.iters[t] = m.ctl[CTL_K] + 1;
-          }
-        }
-        m.alpha[t] = al;
-      }
-      return 0;
-    }
-    case F_CHEB: {
-      // r^T z of a fresh preconditioner application -> rho (and beta)
-      const double rz = final_sum<VEC>(a.partial, a.G, S, fin);
-      if (t < S) {
-        if (a.cheb_init) {
-          m.rho[t] = rz;
-          m.beta[t] = 0.0;
-        } else if (m.active[t]) {
-          m.beta[t] = rz / m.rho[t];
-          m.rho[t] = rz;
-        } else {
-          m.beta[t] = 0.0;
-        }
-      }
-      return 0;
-    }
+    case F_ALPHA:
+    case F_CHEB:
     case F_UPDATE_J:
     case F_UPDATE_C: {
-      // convergence test ||r_k|| <= rtol ||b||, iteration count, beta
-      double rrs, rzs = 0.0;
+      // A step of a running solve.  The control words and this member's
+      // state are loaded before the partials are reduced and before any
+      // store, so their latency overlaps the reduction's loads.
+      const int done = gload(&m.ctl[CTL_DONE]);
+      const int kprev = gload(&m.ctl[CTL_K]);
+      const int maxit = gload(&m.ctl[CTL_MAXIT]);
+      const bool mine = t < S;
+      int act = 0;
+      double rho = 0.0, alpha = 0.0, bn = 0.0;
+      if (mine) {
+        act = gload(&m.active[t]);
+        rho = gload(&m.rho[t]);
+        alpha = gload(&m.alpha[t]);
+        bn = gload(&m.bnorm[t]);
+      }
+      double s0, s1 = 0.0;
       if (a.kind == F_UPDATE_J) {
+        // r^T r and r^T z
         const double* const P[2] = {a.partial + ps, a.partial};
         double o2[2];
         final_sums<VEC, 2>(P, a.G, S, fin, o2);
-        rrs = o2[0];
-        rzs = o2[1];
+        s0 = o2[0];
+        s1 = o2[1];
       } else {
-        rrs = final_sum<VEC>(a.partial + ps, a.G, S, fin);
+        // p^T A p (F_ALPHA), r^T z (F_CHEB) or r^T r (F_UPDATE_C)
+        s0 = final_sum<VEC>(a.partial + (a.kind == F_UPDATE_C ? ps : 0), a.G, S, fin);
       }
-      const int k = m.ctl[CTL_K] + 1;
-      if (t == 0) live = 0;
-      __syncthreads();
-      if (t < S) {
-        if (m.active[t]) {
-          const double rn = sqrt(rrs);
-          m.relres[t] = rn / m.bnorm[t];
-          if (rn <= a.rtol * m.bnorm[t]) {
-            m.active[t] = 0;
-            m.status[t] = ENS_CONVERGED;
-            m.iters[t] = k;
-          } else if (k >= m.ctl[CTL_MAXIT]) {
-            m.active[t] = 0;
-            m.status[t] = ENS_MAX_ITER;
-            m.iters[t] = k;
+      if (done) return 0;
+      if (a.kind == F_ALPHA) {
+        // p^T A p per member -> alpha, or freeze the member (the guard)
+        if (mine) {
+          double al = 0.0;
+          if (act) {
+            if (isfinite(s0) && s0 > 0.0) {
+              al = rho / s0;
+            } else {
+              gstore(&m.active[t], 0);
+              gstore(&m.status[t], ENS_BREAKDOWN);
+              gstore(&m.iters[t], kprev + 1);
+            }
+          }
+          gstore(&m.alpha[t], al);
+        }
+        return 0;
+      }
+      if (a.kind == F_CHEB) {
+        // r^T z of a fresh preconditioner application -> rho (and beta)
+        if (mine) {
+          if (a.cheb_init) {
+            gstore(&m.rho[t], s0);
+            gstore(&m.beta[t], 0.0);
+          } else if (act) {
+            gstore(&m.beta[t], s0 / rho);
+            gstore(&m.rho[t], s0);
+          } else {
+            gstore(&m.beta[t], 0.0);
           }
         }
-        m.alpha_prev[t] = m.alpha[t];
-        if (m.active[t]) {
+        return 0;
+      }
+      // convergence test ||r_k|| <= rtol ||b||, iteration count, beta
+      const int k = kprev + 1;
+      if (t == 0) live = 0;
+      __syncthreads();
+      if (mine) {
+        if (act) {
+          const double rn = sqrt(s0);
+          gstore(&m.relres[t], rn / bn);
+          if (rn <= a.rtol * bn) {
+            act = 0;
+            gstore(&m.status[t], ENS_CONVERGED);
+            gstore(&m.iters[t], k);
+          } else if (k >= maxit) {
+            act = 0;
+            gstore(&m.status[t], ENS_MAX_ITER);
+            gstore(&m.iters[t], k);
+          }
+          if (!act) gstore(&m.active[t], 0);
+        }
+        gstore(&m.alpha_prev[t], alpha);
+        if (act) {
           if (a.kind == F_UPDATE_J) {
-            m.beta[t] = rzs / m.rho[t];
-            m.rho[t] = rzs;
+            gstore(&m.beta[t], s1 / rho);
+            gstore(&m.rho[t], s1);
           }
           atomicAdd(&live, 1);
         } else {
-          m.beta[t] = 0.0;
+          gstore(&m.beta[t], 0.0);
         }
       }
       __syncthreads();
       const int retired = (live == 0) ? 1 : 0;
       if (t == 0) {
-        m.ctl[CTL_K] = k;
-        m.ctl[CTL_DONE] = retired;
+        gstore(&m.ctl[CTL_K], k);
+        gstore(&m.ctl[CTL_DONE], retired);
       }
       return retired;
     }
@@ -603,47 +650,47 @@ __device__ __forceinline__ int finish_body(const FinishArgs& a, double* fin, int
       __syncthreads();
       if (t < S) {
         const double bn = sqrt(bbs);
-        m.bnorm[t] = bn;
-        m.alpha[t] = 0.0;
-        m.alpha_prev[t] = 0.0;
-        m.beta[t] = 0.0;
-        m.rho[t] = rzs;
-        m.iters[t] = 0;
+        gstore(&m.bnorm[t], bn);
+        gstore(&m.alpha[t], 0.0);
+        gstore(&m.alpha_prev[t], 0.0);
+        gstore(&m.beta[t], 0.0);
+        gstore(&m.rho[t], rzs);
+        gstore(&m.iters[t], 0);
         if (bn == 0.0) {
-          m.active[t] = 0;
-          m.status[t] = ENS_ZERO_RHS;
-          m.relres[t] = 0.0;
+          gstore(&m.active[t], 0);
+          gstore(&m.status[t], ENS_ZERO_RHS);
+          gstore(&m.relres[t], 0.0);
         } else {
-          m.active[t] = 1;
-          m.status[t] = ENS_MAX_ITER;
-          m.relres[t] = 1.0;
+          gstore(&m.active[t], 1);
+          gstore(&m.status[t], ENS_MAX_ITER);
+          gstore(&m.relres[t], 1.0);
           atomicAdd(&live, 1);
         }
         if (a.cheb) {
           // Chebyshev semi-iteration on [lmax / ratio, lmax]: theta, delta the
           // centre and half-width; step k uses c1 = rho_k rho_{k-1},
           // c2 = 2 rho_k / delta with rho_k = 1 / (2 sigma1 - rho_{k-1}).
-          m.lmax[t] = lmax;
+          gstore(&m.lmax[t], lmax);
           const double lmin = lmax / a.cheb_ratio;
           const double theta = (lmax + lmin) / 2.0;
           const double delta = (lmax - lmin) / 2.0;
           const double sigma1 = theta / delta;
           double rho0 = 1.0 / sigma1;
           double* cf = m.cheb + (size_t)t * kChebCoef;
-          cf[0] = theta;
+          gstore(&cf[0], theta);
           for (int k = 1; k < a.cheb_degree; ++k) {
             const double rho1 = 1.0 / (2.0 * sigma1 - rho0);
-            cf[2 * k - 1] = rho1 * rho0;
-            cf[2 * k] = 2.0 * rho1 / delta;
+            gstore(&cf[2 * k - 1], rho1 * rho0);
+            gstore(&cf[2 * k], 2.0 * rho1 / delta);
             rho0 = rho1;
           }
         }
       }
       __syncthreads();
       if (t == 0) {
-        m.ctl[CTL_K] = 0;
-        m.ctl[CTL_MAXIT] = a.max_iter;
-        m.ctl[CTL_DONE] = (live == 0) ? 1 : 0;
+        gstore(&m.ctl[CTL_K], 0);
+        gstore(&m.ctl[CTL_MAXIT], a.max_iter);
+        gstore(&m.ctl[CTL_DONE], (live == 0) ? 1 : 0);
       }
       return 0;
     }
@@ -652,7 +699,7 @@ __device__ __forceinline__ int finish_body(const FinishArgs& a, double* fin, int
       // nsum member sums, scaled, into result[s][q]
       for (int q = 0; q < a.nsum; ++q) {
         const double v = final_sum<VEC>(a.partial + q * ps, a.G, S, fin);
-        if (t < S) m.result[(size_t)t * 16 + q] = a.scale * v;
+        if (t < S) gstore(&m.result[(size_t)t * 16 + q], a.scale * v);
       }
       return 0;
     }

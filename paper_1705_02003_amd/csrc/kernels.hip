@@ -373,8 +373,8 @@ __global__ __launch_bounds__(kNT) void dot_kernel(const double* x, const double*
 // producer's per-workgroup partials in a fixed order and applies the
 // per-member scalar logic of the step.
 template <int VEC>
-__global__ __launch_bounds__(kNT) void finish_kernel(FinishArgs a) {
-  __shared__ double fin[2 * kNT * 2];
+__global__ __launch_bounds__(kFinNT) void finish_kernel(FinishArgs a) {
+  __shared__ double fin[2 * kFinNT * 2];
   __shared__ int live;
   (void)finish_body<VEC>(a, fin, live);
 }
@@ -432,7 +432,8 @@ void launch_final(double* x, const double* p0, const double* p1, const Members& 
 }
 
 void launch_finish(const FinishArgs& a, hipStream_t s) {
-  ENS_LAUNCH_VEC(a.g.vec, finish_kernel, dim3(1), s, a);
+  if (a.g.vec == 2) hipLaunchKernelGGL(finish_kernel<2>, dim3(1), dim3(kFinNT), 0, s, a);
+  else hipLaunchKernelGGL(finish_kernel<1>, dim3(1), dim3(kFinNT), 0, s, a);
 }
 
 void launch_dot(const double* x, const double* y, int y_bcast, double* partial, const Geometry& g,
