@@ -18,7 +18,11 @@
  *  - Ensemble layout (member index innermost, the commuted Kronecker ordering
  *    of eq. (discrete-comm-kron-sys)):
  *        vector X      : X[r * S + s]                      ([N_r][S])
- *        matrix values : V[(k * N_r + r) * S + s]          ([9][N_r][S])
+ *        matrix values : V[k * L + r * S + s]              ([9][L], L >= N_r S)
+ *    with L = ens_matrix_slot_stride(prob, S): each slot holds its N_r * S
+ *    values at its start and is followed by a few KiB of padding, so that
+ *    the nine slots do not sit a large power of two apart (they stream
+ *    together; see ens_matrix_slot_stride).  A V buffer has 9 * L doubles.
  *    Stencil slot k = 3 (dj + 1) + (di + 1) couples row (i, j) to column
  *    (i + di, j + dj): k = 0 SW, 1 S, 2 SE, 3 W, 4 C (diagonal), 5 E, 6 NW,
  *    7 N, 8 NE -- the column order of a CSR row.  Slots that would couple to
@@ -120,7 +124,8 @@ typedef struct {
 /* Assemble the ensemble matrix and right-hand side for S members.
  * Paper: Section 2.3 (each nonzero stored as a length-S array; mesh and graph
  * are sample independent and shared).  y_dev: [S][d] parameters (device).
- * Outputs V_dev [9][N_r][S] (A, with the 1/h^2 included) and b_dev [N_r][S]
+ * Outputs V_dev [9][L] (A, with the 1/h^2 included; L the slot stride, the
+ * padding is not written) and b_dev [N_r][S]
  * (f = 1).  Asynchronous on `stream`.
  * Errors: ENS_EINVAL for a NULL pointer, n < 2, d outside [2,16], eps_model
  * outside {0,1}, S not a power of two in [1,64], or non-finite amp.  The
@@ -128,6 +133,13 @@ typedef struct {
  * non-finite matrix values for that member only (reject them on the host). */
 int ens_assemble_ensemble(const ens_problem* prob, int32_t S, const double* y_dev,
                           double* V_dev, double* b_dev, void* stream);
+
+/* Elements L from the start of one matrix slot to the next in every V_dev
+ * argument: N_r * S rounded up to a multiple of 32, plus 512 (4 KiB).  When
+ * N_r * S * 8 bytes is a large power of two, unpadded slots would stream at
+ * about 80 % of the bandwidth of padded ones on MI355X.  0 if the arguments
+ * are invalid. */
+size_t ens_matrix_slot_stride(const ens_problem* prob, int32_t S);
 
 /* ------------------------------------------------------------- solver */
 /* Bytes of device workspace ens_pcg_solve / ens_adjoint_grad need, or 0 if
@@ -144,7 +156,7 @@ size_t ens_pcg_workspace_bytes(const ens_problem* prob, const ens_opts* opts, in
  * Jacobi (diagonal = slot 4 of V) or a Chebyshev polynomial in D^-1 A over
  * [lambda_max / cheb_ratio, lambda_max], lambda_max the member's Gershgorin
  * bound max_i sum_j |a_ij| / a_ii.
- * In:  V_dev [9][N_r][S] (symmetric positive definite per member),
+ * In:  V_dev [9][L] (symmetric positive definite per member),
  *      b_dev [N_r][S].
  * Out: x_dev [N_r][S] (overwritten); iters_host[S], status_host[S],
  *      relres_host[S] (= ||r|| / ||b|| of the recurrence residual at exit, 0
@@ -160,13 +172,13 @@ int ens_pcg_solve(const ens_problem* prob, const ens_opts* opts, int32_t S,
 
 /* One ensemble matrix-vector product q = A p (the operation the solver's fused
  * kernel performs each iteration, without the fused updates).
- * In: V_dev [9][N_r][S], p_dev [N_r][S]; out: q_dev [N_r][S].  Asynchronous. */
+ * In: V_dev [9][L], p_dev [N_r][S]; out: q_dev [N_r][S].  Asynchronous. */
 int ens_spmv(const ens_problem* prob, int32_t S, const double* V_dev,
              const double* p_dev, double* q_dev, void* stream);
 
 /* Apply the Chebyshev preconditioner once: z = M^-1 r per member, with the
  * polynomial of ens_pcg_solve (degree opts->cheb_degree, ratio opts->cheb_ratio).
- * In: V_dev, r_dev [N_r][S]; out: z_dev [N_r][S]; lmax_host[S] (may be NULL)
+ * In: V_dev [9][L], r_dev [N_r][S]; out: z_dev [N_r][S]; lmax_host[S] (may be NULL)
  * receives each member's Gershgorin bound.  Blocking (reads back lmax). */
 int ens_cheb_apply(const ens_problem* prob, const ens_opts* opts, int32_t S,
                    const double* V_dev, const double* r_dev, double* z_dev,
@@ -209,7 +221,7 @@ typedef struct {
   ens_problem prob;        /* grid size n (the coefficient model is not used here) */
   int32_t S;               /* ensemble width, a power of two in [2, 64]            */
   int32_t tile_lines;      /* stencil tile height, 0 = heuristic                   */
-  const double* V_dev;     /* [9][N_r][S]                                          */
+  const double* V_dev;     /* [9][L], L = ens_matrix_slot_stride(&prob, S)         */
   const double* b_dev;     /* [N_r][S]                                             */
   double* x_dev;           /* [N_r][S], overwritten                                */
   void* ws_dev;            /* >= ens_pcg_workspace_bytes(&prob, Jacobi, S) bytes   */

@@ -54,6 +54,7 @@ SP = C.POINTER(ens_stats)
 # name -> (restype, argtypes); every symbol declared in include/ens.h
 SIGNATURES = {
     "ens_assemble_ensemble": (C.c_int, [PP, i32, vp, vp, vp, vp]),
+    "ens_matrix_slot_stride": (sz, [PP, i32]),
     "ens_pcg_workspace_bytes": (sz, [PP, OP, i32]),
     "ens_pcg_solve": (C.c_int, [PP, OP, i32, vp, vp, vp, i32p, i32p, f64p, i32p, SP, vp, sz, vp]),
     "ens_spmv": (C.c_int, [PP, i32, vp, vp, vp, vp]),

@@ -41,9 +41,11 @@ static size_t header_bytes() {
 
 static int n_vectors(bool cheb) { return cheb ? 8 : 5; }
 
+// bytes from one workspace vector to the next (see slot_stride)
+static size_t vector_bytes(int n, int S) { return sizeof(double) * slot_stride((size_t)n * n * S); }
+
 size_t workspace_bytes(int n, int S, bool cheb) {
-  const size_t vec = align256(sizeof(double) * (size_t)n * n * S);
-  return header_bytes() + vec * n_vectors(cheb);
+  return header_bytes() + vector_bytes(n, S) * n_vectors(cheb);
 }
 
 Workspace carve_workspace(void* base, int n, int S, bool cheb) {
@@ -73,7 +75,7 @@ Workspace carve_workspace(void* base, int n, int S, bool cheb) {
   w.m.ctl = reinterpret_cast<int*>(p);
   p += align256(sizeof(int) * CTL_COUNT);
   if (n > 0) {
-    const size_t vec = align256(sizeof(double) * (size_t)n * n * S);
+    const size_t vec = vector_bytes(n, S);
     double** slots[8] = {&w.p[0], &w.p[1], &w.q, &w.r, &w.aux, &w.z[0], &w.z[1], &w.d};
     for (int k = 0; k < n_vectors(cheb); ++k) {
       *slots[k] = reinterpret_cast<double*>(p);
@@ -115,6 +117,7 @@ Geometry make_geometry(int n, int S, int tile_lines, int max_groups, int member_
   g.groups = std::max(G, 1);
   g.nr = (size_t)n * n;
   g.nelem = g.nr * S;
+  g.vstride = slot_stride(g.nelem);
   g.full = 0;
   return g;
 }
@@ -417,9 +420,15 @@ int ens_assemble_ensemble(const ens_problem* prob, int32_t S, const double* y_de
   a.eps_model = prob->eps_model;
   a.amp = prob->amp;
   a.nelem = (size_t)prob->n * prob->n * S;
+  a.vstride = slot_stride(a.nelem);
   launch_assemble(a, (hipStream_t)stream);
   HIPCHECK(hipGetLastError());
   return ENS_OK;
+}
+
+size_t ens_matrix_slot_stride(const ens_problem* prob, int32_t S) {
+  if (check_problem(prob) || !valid_S(S)) return 0;
+  return slot_stride((size_t)prob->n * prob->n * S);
 }
 
 size_t ens_pcg_workspace_bytes(const ens_problem* prob, const ens_opts* opts, int32_t S) {

@@ -43,7 +43,7 @@ struct BatchEns {
   int n, S, tpp;          // tpp: threads per point of the element-wise kernel (S / 2)
   int sw, stpp;           // member tile width and its threads per point (sw / 2)
   int tx, ty, nchunk, ntiles;   // ntiles: spatial tiles per member tile
-  size_t nelem;
+  size_t nelem, vstride;
   int unit0;    // first stencil unit; units are (member tile, spatial tile)
   int eunit0;   // first update unit
   int neunits;  // update units
@@ -166,6 +166,7 @@ __global__ __launch_bounds__(kNT) void batch_stencil_kernel(BatchArgs a) {
       tv.ty = uni(E.ty);
       tv.nchunk = uni(E.nchunk);
       tv.nelem = uni(E.nelem);
+      tv.vstride = uni(E.vstride);
       const double* mb = uni(E.m.beta);
       const double* ma = uni(E.m.alpha_prev);
 #pragma unroll
@@ -239,7 +240,7 @@ __global__ __launch_bounds__(kNT) void batch_update_kernel(BatchArgs a) {
       r_in = uni(E.r);
       r_out = uni(E.r);
       q_in = uni(E.q);
-      d_in = uni(E.V) + 4 * nelem;
+      d_in = uni(E.V) + 4 * uni(E.vstride);
       const int sv = (t % tpp) * 2;
       const int* ma = uni(E.m.active);
       const double* mal = uni(E.m.alpha);
@@ -454,6 +455,7 @@ int ens_batch_solve(const ens_opts* opts, int32_t n_items, ens_batch_item* items
     E.nchunk = g.nchunk;
     E.ntiles = g.ntiles;
     E.nelem = g.nelem;
+    E.vstride = g.vstride;
     E.unit0 = u0[k];
     E.eunit0 = e0[k];
     E.neunits = (int)((g.nelem + kUpdateChunk - 1) / kUpdateChunk);

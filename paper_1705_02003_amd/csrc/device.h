@@ -250,7 +250,7 @@ struct TileView {
   int sw, s0;      // members this tile covers: s0 .. s0 + sw - 1
   int tpp;         // threads per grid point = sw / VEC
   int tx, ty, nchunk;
-  size_t nelem;
+  size_t nelem, vstride;   // elements per vector; from one matrix slot to the next
   int cheb_last;
 };
 
@@ -286,7 +286,7 @@ __device__ __forceinline__ void stencil_tile(const TileView& a, int tile, double
   const int lp = t / tpp;
   const int cl = (t % tpp) * VEC;   // first member of this thread within the tile
   const int sv = a.s0 + cl;         // ... within the ensemble
-  const size_t slot_stride = a.nelem;
+  const size_t slot_stride = a.vstride;
   const size_t line_stride = (size_t)n * S;
   const int chunk = tile % a.nchunk, band = tile / a.nchunk;
   const int i0 = chunk * a.tx, j0 = band * a.ty;

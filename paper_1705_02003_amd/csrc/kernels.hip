@@ -84,7 +84,7 @@ __global__ __launch_bounds__(kNT) void assemble_kernel(AsmArgs a) {
   if (j == n - 1) h2[6] = h2[7] = h2[8] = 0.0;
   const double inv_h2 = (double)(n + 1) * (double)(n + 1);
 #pragma unroll
-  for (int k = 0; k < 9; ++k) a.V[(size_t)k * a.nelem + e] = h2[k] * inv_h2;
+  for (int k = 0; k < 9; ++k) a.V[(size_t)k * a.vstride + e] = h2[k] * inv_h2;
   a.b[e] = 1.0;
 }
 
@@ -131,6 +131,7 @@ __global__ __launch_bounds__(kNT) void stencil_kernel(StencilArgs a) {
   tv.ty = g.ty;
   tv.nchunk = g.nchunk;
   tv.nelem = g.nelem;
+  tv.vstride = g.vstride;
   tv.cheb_last = a.cheb_last;
   // Every workgroup sweeps the same spatial tiles for each member tile, so
   // each member's partial sums follow the same tree.
@@ -203,7 +204,7 @@ __global__ __launch_bounds__(kNT) void update_kernel(UpdateArgs a) {
       if (e < g.nelem) {
         ld<VEC>(rv[u], a.r + e);
         ld<VEC>(qv[u], a.q + e);
-        ld<VEC>(dv[u], a.V + 4 * g.nelem + e);
+        ld<VEC>(dv[u], a.V + 4 * g.vstride + e);
       }
     }
 #pragma unroll
@@ -258,7 +259,7 @@ __global__ __launch_bounds__(kNT) void init_kernel(InitArgs a) {
     } else {
       ld<VEC>(bv, a.b + e);
     }
-    ld<VEC>(dv, a.V + 4 * g.nelem + e);
+    ld<VEC>(dv, a.V + 4 * g.vstride + e);
 #pragma unroll
     for (int c = 0; c < VEC; ++c) {
       zero[c] = 0.0;
@@ -275,7 +276,7 @@ __global__ __launch_bounds__(kNT) void init_kernel(InitArgs a) {
 #pragma unroll
       for (int k = 0; k < 9; ++k) {
         double vk[VEC];
-        ld<VEC>(vk, a.V + (size_t)k * g.nelem + e);
+        ld<VEC>(vk, a.V + (size_t)k * g.vstride + e);
 #pragma unroll
         for (int c = 0; c < VEC; ++c) rs[c] = rs[c] + fabs(vk[c]);
       }
@@ -307,7 +308,7 @@ __global__ __launch_bounds__(kNT) void cheb_start_kernel(const double* V, const 
   for (size_t e = ((size_t)blockIdx.x * kNT + t) * VEC; e < g.nelem; e += stride) {
     double rv[VEC], dv[VEC], zz[VEC];
     ld<VEC>(rv, r + e);
-    ld<VEC>(dv, V + 4 * g.nelem + e);
+    ld<VEC>(dv, V + 4 * g.vstride + e);
 #pragma unroll
     for (int c = 0; c < VEC; ++c) zz[c] = (rv[c] / dv[c]) / ith[c];
     st<VEC>(d + e, zz);

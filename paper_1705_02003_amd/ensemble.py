@@ -105,13 +105,40 @@ def workspace(prob: Problem, S: int, opts: Optional[SolverOptions] = None,
     return torch.empty(nb, dtype=torch.uint8, device=device or "cuda")
 
 
+def matrix_slot_stride(prob: Problem, S: int) -> int:
+    """Elements from one matrix slot to the next (ens_matrix_slot_stride)."""
+    pc = prob.c()
+    L_ = int(L.lib().ens_matrix_slot_stride(C.byref(pc), S))
+    if L_ == 0:
+        raise ValueError("invalid problem / ensemble width")
+    return L_
+
+
+def empty_matrix(prob: Problem, S: int, device=None) -> torch.Tensor:
+    """An uninitialised ensemble matrix: a (9, N_r, S) view with the library's
+    slot stride (slot k starts at element k * matrix_slot_stride)."""
+    Ls = matrix_slot_stride(prob, S)
+    buf = torch.empty(9 * Ls, dtype=torch.float64, device=device or "cuda")
+    return buf.as_strided((9, prob.rows, S), (Ls, S, 1))
+
+
+def _require_matrix(V: torch.Tensor, prob: Problem, S: int):
+    if not isinstance(V, torch.Tensor) or not V.is_cuda or V.dtype != torch.float64:
+        raise ValueError("V must be a float64 CUDA (HIP) tensor")
+    if tuple(V.shape) != (9, prob.rows, S):
+        raise ValueError(f"V has shape {tuple(V.shape)}, expected {(9, prob.rows, S)}")
+    if V.stride() != (matrix_slot_stride(prob, S), S, 1):
+        raise ValueError("V must have the library's slot stride (use assemble or empty_matrix)")
+
+
 def assemble(prob: Problem, y: torch.Tensor):
-    """Ensemble matrix V (9, N_r, S) and right-hand side b (N_r, S) for y (S, d)."""
+    """Ensemble matrix V (9, N_r, S; slot stride matrix_slot_stride) and
+    right-hand side b (N_r, S) for y (S, d)."""
     _require_cuda(y, "y")
     S = int(y.shape[0])
     if y.dim() != 2 or y.shape[1] != prob.d:
         raise ValueError(f"y must have shape (S, {prob.d})")
-    V = torch.empty((9, prob.rows, S), dtype=torch.float64, device=y.device)
+    V = empty_matrix(prob, S, y.device)
     b = torch.empty((prob.rows, S), dtype=torch.float64, device=y.device)
     pc = prob.c()
     L.check(L.lib().ens_assemble_ensemble(C.byref(pc), S, _p(y), _p(V), _p(b), _stream(y.device)),
@@ -124,7 +151,7 @@ def solve(prob: Problem, V: torch.Tensor, b: torch.Tensor, opts: Optional[Solver
     """Ensemble PCG for every member; blocks until the counts are known."""
     opts = opts or SolverOptions()
     S = _ensemble_width(b)
-    _require_cuda(V, "V", (9, prob.rows, S))
+    _require_matrix(V, prob, S)
     _require_cuda(b, "b", (prob.rows, S))
     if x is None:
         x = torch.empty_like(b)
@@ -151,7 +178,7 @@ def solve(prob: Problem, V: torch.Tensor, b: torch.Tensor, opts: Optional[Solver
 
 def spmv(prob: Problem, V: torch.Tensor, p: torch.Tensor) -> torch.Tensor:
     S = _ensemble_width(p)
-    _require_cuda(V, "V", (9, prob.rows, S))
+    _require_matrix(V, prob, S)
     _require_cuda(p, "p", (prob.rows, S))
     q = torch.empty_like(p)
     pc = prob.c()
@@ -164,7 +191,7 @@ def cheb_apply(prob: Problem, V: torch.Tensor, r: torch.Tensor,
     """z = M^-1 r for the Chebyshev preconditioner; returns (z, lambda_max per member)."""
     opts = opts or SolverOptions(precond="chebyshev")
     S = _ensemble_width(r)
-    _require_cuda(V, "V", (9, prob.rows, S))
+    _require_matrix(V, prob, S)
     _require_cuda(r, "r", (prob.rows, S))
     if ws is None:
         ws = workspace(prob, S, SolverOptions(precond="chebyshev"), r.device)
@@ -216,7 +243,7 @@ def adjoint_grad(prob: Problem, y: torch.Tensor, V: torch.Tensor, u: torch.Tenso
     opts = opts or SolverOptions()
     S = int(y.shape[0])
     _require_cuda(y, "y", (S, prob.d))
-    _require_cuda(V, "V", (9, prob.rows, S))
+    _require_matrix(V, prob, S)
     _require_cuda(u, "u", (prob.rows, S))
     _require_cuda(w, "w", (prob.rows,))
     if ws is None:
@@ -269,7 +296,7 @@ def batch_solve(items, opts: Optional[SolverOptions] = None, batch_ws: Optional[
     for k, it in enumerate(items):
         prob, V, b = it["prob"], it["V"], it["b"]
         S = _ensemble_width(b)
-        _require_cuda(V, "V", (9, prob.rows, S))
+        _require_matrix(V, prob, S)
         _require_cuda(b, "b", (prob.rows, S))
         x = it.get("x")
         if x is None:
