@@ -29,6 +29,7 @@
 namespace ens {
 
 constexpr int kUpdateChunk = kNT * 2 * 4;  // elements per update unit (VEC 2, 4 strides)
+constexpr int kGraphSteps = 16;            // CG steps per graph launch (at most)
 constexpr int kMaxBatch = 1024;             // ensembles per batch (tables staged in LDS)
 
 struct BatchEns {
@@ -171,8 +172,13 @@ __global__ __launch_bounds__(kNT) void batch_stencil_kernel(BatchArgs a) {
       const double* ma = uni(E.m.alpha_prev);
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
-        beta[c] = gload(&mb[sv + c]);
-        aprev[c] = gload(&ma[sv + c]);
+        // consumed here (the select), once per member tile: a load still
+        // pending at the unit loop's head would make each tile wait for the
+        // previous tile's stores
+        const double bt = gload(&mb[sv + c]);
+        const double ap = gload(&ma[sv + c]);
+        beta[c] = (sv + c < S) ? bt : 0.0;
+        aprev[c] = (sv + c < S) ? ap : 0.0;
         acc[c] = 0.0;
       }
     }
@@ -181,14 +187,14 @@ __global__ __launch_bounds__(kNT) void batch_stencil_kernel(BatchArgs a) {
   if (cur >= 0) flush();
 }
 
-// r -= alpha q for active members, then the partial sums r^T r and r^T z
-// (z = r / diag) of two members
+// r -= alpha q for members with a step (step[c] = alpha if the member is
+// active, else 0), then the partial sums r^T r and r^T z (z = r / diag) of
+// two members
 __device__ __forceinline__ void update_pair(double (&rv)[2], const double (&qv)[2], const double (&dv)[2],
-                                            const double (&act)[2], const double (&alpha)[2],
-                                            double (&rr)[2], double (&rz)[2]) {
+                                            const double (&step)[2], double (&rr)[2], double (&rz)[2]) {
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
-    if (act[c] != 0.0 && alpha[c] != 0.0) rv[c] = fma(-alpha[c], qv[c], rv[c]);
+    if (step[c] != 0.0) rv[c] = fma(-step[c], qv[c], rv[c]);
     rr[c] = fma(rv[c], rv[c], rr[c]);
     rz[c] = fma(rv[c], rv[c] / dv[c], rz[c]);
   }
@@ -202,7 +208,7 @@ __global__ __launch_bounds__(kNT) void batch_update_kernel(BatchArgs a) {
   const int t = threadIdx.x;
   const int L = logical_group(blockIdx.x, a.G);
   int cur = -1, tpp = 1, S = 2;
-  double alpha[2] = {0.0, 0.0}, act[2] = {0.0, 0.0}, rz[2] = {0.0, 0.0}, rr[2] = {0.0, 0.0};
+  double step[2] = {0.0, 0.0}, rz[2] = {0.0, 0.0}, rr[2] = {0.0, 0.0};
   int e = 0;
   const double* r_in = nullptr;
   double* r_out = nullptr;
@@ -246,8 +252,12 @@ __global__ __launch_bounds__(kNT) void batch_update_kernel(BatchArgs a) {
       const double* mal = uni(E.m.alpha);
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
-        act[c] = gload(&ma[sv + c]) ? 1.0 : 0.0;
-        alpha[c] = gload(&mal[sv + c]);
+        // consumed here, once per ensemble: a load still pending at the
+        // unit loop's head would make every unit wait for the previous
+        // unit's stores
+        const int on = gload(&ma[sv + c]);
+        const double al = gload(&mal[sv + c]);
+        step[c] = on ? al : 0.0;
         rz[c] = 0.0;
         rr[c] = 0.0;
       }
@@ -263,9 +273,12 @@ __global__ __launch_bounds__(kNT) void batch_update_kernel(BatchArgs a) {
         ld<2>(qv[k], q_in + el);
         ld<2>(dv[k], d_in + el);
       }
+      // keep the scheduler from starting the arithmetic (and its waits)
+      // before all twelve loads are issued
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        update_pair(rv[k], qv[k], dv[k], act, alpha, rr, rz);
+        update_pair(rv[k], qv[k], dv[k], step, rr, rz);
         st<2>(r_out + base + ((size_t)k * kNT + t) * 2, rv[k]);
       }
     } else {
@@ -277,7 +290,7 @@ __global__ __launch_bounds__(kNT) void batch_update_kernel(BatchArgs a) {
           ld<2>(rv, r_in + el);
           ld<2>(qv, q_in + el);
           ld<2>(dv, d_in + el);
-          update_pair(rv, qv, dv, act, alpha, rr, rz);
+          update_pair(rv, qv, dv, step, rr, rz);
           st<2>(r_out + el, rv);
         }
       }
@@ -483,7 +496,11 @@ int ens_batch_solve(const ens_opts* opts, int32_t n_items, ens_batch_item* items
   ba.G = G;
   ba.rtol = rtol;
 
-  // one CG step for every ensemble: a graph of four kernel nodes
+  // CG steps for every ensemble: a graph of `steps` x four kernel nodes.
+  // Several steps per graph launch amortise the few microseconds between
+  // consecutive graph executions; steps after an ensemble retires find its
+  // done flag and return at once.
+  const int steps = std::min(poll, kGraphSteps);
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   he = hipGraphCreate(&graph, 0);
@@ -499,12 +516,13 @@ int ens_batch_solve(const ens_opts* opts, int32_t n_items, ens_batch_item* items
                 {reinterpret_cast<const void*>(&batch_finish_kernel<0>), (unsigned)n_items, (unsigned)kFinNT},
                 {reinterpret_cast<const void*>(&batch_update_kernel), (unsigned)G, (unsigned)kNT},
                 {reinterpret_cast<const void*>(&batch_finish_kernel<1>), (unsigned)n_items, (unsigned)kFinNT}};
-  for (int k = 0; k < 4 && he == hipSuccess; ++k) {
+  for (int k = 0; k < 4 * steps && he == hipSuccess; ++k) {
+    const NodeSpec& sp = specs[k % 4];
     hipKernelNodeParams kp;
     std::memset(&kp, 0, sizeof(kp));
-    kp.func = const_cast<void*>(specs[k].fn);
-    kp.gridDim = dim3(specs[k].grid);
-    kp.blockDim = dim3(specs[k].block);
+    kp.func = const_cast<void*>(sp.fn);
+    kp.gridDim = dim3(sp.grid);
+    kp.blockDim = dim3(sp.block);
     kp.sharedMemBytes = 0;
     kp.kernelParams = args;
     kp.extra = nullptr;
@@ -525,7 +543,7 @@ int ens_batch_solve(const ens_opts* opts, int32_t n_items, ens_batch_item* items
   bool have_prev = false;
   while (he == hipSuccess && launched < max_iter) {
     const int chunk = std::min(poll, max_iter - launched);
-    for (int c = 0; c < chunk && he == hipSuccess; ++c) he = hipGraphLaunch(exec, s);
+    for (int c = 0; c < chunk && he == hipSuccess; c += steps) he = hipGraphLaunch(exec, s);
     launched += chunk;
     if (he != hipSuccess) break;
     int32_t* f = flags + slot * n_items;
