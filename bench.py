@@ -160,6 +160,108 @@ def s1_comparison(res, S, opts, n_groups=2):
             "iters_S1": [int(min(its1)), int(max(its1))]}
 
 
+def measure_triad(gib: int = 4, reps: int = 5) -> dict:
+    """Achievable HBM bandwidth: the library's STREAM triad (c = a + s b) on
+    three `gib`-GiB FP64 arrays, best of `reps` timed launches."""
+    import torch
+    from paper_1705_02003_amd import ensemble as E
+    n = (gib << 30) // 8
+    a = torch.full((n,), 1.0, dtype=torch.float64, device="cuda")
+    b = torch.full((n,), 2.0, dtype=torch.float64, device="cuda")
+    c = torch.empty_like(a)
+    E.stream_triad(a, b, c, 0.5)
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        E.stream_triad(a, b, c, 0.5)
+        e1.record()
+        torch.cuda.synchronize()
+        dt = e0.elapsed_time(e1) * 1e-3
+        best = dt if best is None else min(best, dt)
+    del a, b, c
+    torch.cuda.empty_cache()
+    return {"GBs": round(3 * n * 8 / best / 1e9, 1), "array_GiB": gib, "kernel": "ens_stream_triad"}
+
+
+def device_info() -> dict:
+    import subprocess
+    import torch
+    props = torch.cuda.get_device_properties(0)
+    info = {"name": torch.cuda.get_device_name(0), "arch": getattr(props, "gcnArchName", ""),
+            "compute_units": props.multi_processor_count,
+            "memory_GiB": round(props.total_memory / 2**30, 1)}
+    try:
+        out = subprocess.run(["rocm-smi", "--showclocks"], capture_output=True, text=True,
+                             timeout=20).stdout
+        clocks = [l.strip() for l in out.splitlines() if "sclk" in l or "mclk" in l]
+        info["clocks"] = clocks[:4]
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return info
+
+
+def su_mode(args) -> int:
+    """Perfect grouping (the MI355X analogue of the paper's Fig. 1): S copies
+    of one sample y = (-1, 0, 0, 0) (isotropic, a = 1) at 512x512, Jacobi-PCG,
+    rtol 1e-8, for S = 1, 2, ..., 64.  SU(S) = S t(1) / t(S), t the median of
+    three solves (assembly excluded).  At S = 1 the working set (~30 MB)
+    fits the 256 MB Infinity Cache, so its bandwidth is not an HBM figure."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_1705_02003_amd import ensemble as E
+    torch.cuda.set_device(0)
+    prob = E.Problem(N_GRID, D, 0, AMP)
+    y0 = np.array([-1.0, 0.0, 0.0, 0.0])
+    opts = E.SolverOptions(rtol=RTOL, full_stencil=FULL_STENCIL)
+    rows, t1 = [], None
+    for S in (1, 2, 4, 8, 16, 32, 64):
+        y = torch.tensor(workloads.identical_samples(y0, S), dtype=torch.float64, device="cuda")
+        V, b = E.assemble(prob, y)
+        ws = E.workspace(prob, S, opts)
+        E.solve(prob, V, b, opts, ws=ws)
+        ts = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            r = E.solve(prob, V, b, opts, ws=ws)
+            ts.append(time.perf_counter() - t)
+        t = float(np.median(ts))
+        t1 = t if S == 1 else t1
+        rows.append({"S": S, "seconds": round(t, 5), "iters": int(r.ens_iters),
+                     "sample_solves_per_s": round(S / t, 2), "SU": round(S * t1 / t, 3),
+                     "iteration_alg_GBs": round(r.ens_iters * prob.rows * S * ITER_BYTES / t / 1e9, 1)})
+        print(json.dumps(rows[-1]), flush=True)
+        del V, b, ws
+    print(json.dumps({"mode": "su", "workload": "identical-samples-512x512", "y": y0.tolist(),
+                      "rows": rows}), flush=True)
+    return 0
+
+
+def grouping_mode(args) -> int:
+    """GPU time of each grouping strategy on the samples of one adaptive run
+    of the benchmark workload (the surrogate run itself is untimed here)."""
+    import torch
+    from paper_1705_02003_amd import ensemble as E
+    from paper_1705_02003_amd import uq
+    torch.cuda.set_device(0)
+    prob = E.Problem(N_GRID, D, 0, AMP)
+    opts = E.SolverOptions(rtol=RTOL, max_iter=20000, full_stencil=FULL_STENCIL)
+    res = uq.adaptive(prob, args.S, budget=args.budget, max_level=5, tau_rel=1e-3,
+                      strategy="surrogate", opts=opts, perm_seed=1)
+    print(f"[bench] adaptive run: {len(res.y)} samples", flush=True)
+    out = {"mode": "grouping", "workload": "adaptive-sg-512x512-d4", "samples": len(res.y)}
+    for S in (args.S, 16) if args.S != 16 else (16,):
+        costs = uq.grouping_costs(res, S)
+        times = uq.time_groupings(prob, res, S, opts)
+        out[f"S{S}"] = {k: {**times[k], "R": round(costs[k]["R"], 4)} for k in times}
+        print(json.dumps({f"S{S}": out[f"S{S}"]}), flush=True)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def kernel_mode(args) -> int:
     """One S-wide ensemble of the workload's coefficient model, solved for a
     fixed number of iterations (rtol 0) in the default launch configuration,
@@ -185,8 +287,7 @@ def kernel_mode(args) -> int:
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
-    # STREAM-style calibration of achievable HBM bandwidth (1 GiB arrays)
-    other = torch.empty_like(src).fill_(2.0)
+    # achievable bandwidth: a plain device copy and the library's triad
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     reps = 10
     e0.record()
@@ -194,13 +295,10 @@ def kernel_mode(args) -> int:
         dst.copy_(src)
     e1.record()
     torch.cuda.synchronize()
-    copy_gbs = 2 * src.numel() * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    e0.record()
-    for _ in range(reps):
-        torch.add(src, other, alpha=2.0, out=dst)
-    e1.record()
-    torch.cuda.synchronize()
-    triad_gbs = 3 * src.numel() * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    copy_bytes = src.numel() * 8
+    copy_gbs = 2 * copy_bytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    triad_gbs = measure_triad()["GBs"]
     us = 1e3 * r.stats["spmv_ms"] / max(1, r.stats["spmv_timed"])
     rows = prob.rows * args.S
     print(json.dumps({"mode": "kernel", "S": args.S, "iterations": args.iters,
@@ -209,7 +307,7 @@ def kernel_mode(args) -> int:
                       "iteration_us": round(1e6 * dt / args.iters, 2),
                       "iteration_alg_GBs": round(rows * ITER_BYTES * args.iters / dt / 1e9, 1),
                       "fused_alg_bytes": rows * FUSED_BYTES,
-                      "copy_bytes_each_way": src.numel() * 8,
+                      "copy_bytes_each_way": copy_bytes,
                       "stream_copy_GBs": round(copy_gbs, 1), "stream_triad_GBs": round(triad_gbs, 1),
                       "tile_lines": r.stats["tile_lines"], "groups": r.stats["spmv_groups"]}),
           flush=True)
@@ -384,7 +482,8 @@ def main() -> int:
     ap.add_argument("--cpu-procs", type=int, default=0, help="0: min(16, cpu count)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-s1", action="store_true")
-    ap.add_argument("--mode", choices=["full", "kernel", "adjoint", "cheb", "batch"], default="full",
+    ap.add_argument("--mode", choices=["full", "kernel", "adjoint", "cheb", "batch", "su", "grouping"],
+                    default="full",
                     help="kernel: a fixed-iteration solve of one ensemble plus a 1 GiB "
                          "copy, for hardware-counter runs")
     ap.add_argument("--iters", type=int, default=100, help="iterations in --mode kernel")
@@ -410,6 +509,10 @@ def main() -> int:
         return cheb_mode(args)
     if args.mode == "batch":
         return batch_mode(args)
+    if args.mode == "su":
+        return su_mode(args)
+    if args.mode == "grouping":
+        return grouping_mode(args)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -458,6 +561,8 @@ def main() -> int:
     member_iter_rows = res.total_ensemble_iters * args.S * prob.rows
     useful_rows = int(res.iters.sum()) * prob.rows
     costs = uq.grouping_costs(res, args.S)
+    costs16 = uq.grouping_costs(res, 16) if args.S != 16 else None
+    asm_s = res.assemble_ms / 1e3
 
     out = {
         "metric": "sample-solves/s + HBM GB/s, ensemble PCG S=32 vs S=1, 512² grid, rtol 1e-8",
@@ -488,11 +593,19 @@ def main() -> int:
         "gbps_iteration_alg": round(member_iter_rows * ITER_BYTES / solve_s / 1e9, 1),
         "gbps_iteration_useful": round(useful_rows * ITER_BYTES / solve_s / 1e9, 1),
         "ensemble_iterations": res.total_ensemble_iters,
+        "sample_solves_per_s_without_assembly": round(n_samples / (times[-1] - asm_s), 3),
+        "assembly_seconds": round(asm_s, 3),
         "grouping": costs,
+        "grouping_S16": costs16,
         "cpu_baseline": cpu,
     }
     if not args.no_s1:
         out["s1_comparison"] = s1_comparison(res, args.S, E.SolverOptions(rtol=RTOL))
+    triad = measure_triad()
+    out["roofline"]["stream_triad_GBs"] = triad["GBs"]
+    if achieved:
+        out["roofline"]["frac_of_stream_triad"] = round(achieved / triad["GBs"], 4)
+    out["device"] = device_info()
     print(json.dumps(out), flush=True)
     return 0
 

@@ -309,6 +309,16 @@ const char* ens_strerror(int code);
 int ens_last_hip_error(void);   /* hipError_t of the last ENS_EHIP, 0 if none */
 int ens_version(void);          /* library ABI version (major * 100 + minor)  */
 
+/* ------------------------------------------------------- calibration */
+/* STREAM triad c = a + scalar * b over n doubles (two reads and one write
+ * per element): the achievable-HBM-bandwidth reference that the solver's
+ * kernels are reported against beside the 8 TB/s peak.  Buffers are device
+ * memory, 16-byte aligned, and must not overlap.  Asynchronous on `stream`.
+ * Errors: ENS_EINVAL for a NULL or misaligned pointer, n = 0 or a
+ * non-finite scalar. */
+int ens_stream_triad(const double* a_dev, const double* b_dev, double* c_dev, double scalar,
+                     size_t n, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -71,6 +71,7 @@ SIGNATURES = {
     "ens_strerror": (C.c_char_p, [C.c_int]),
     "ens_last_hip_error": (C.c_int, []),
     "ens_version": (C.c_int, []),
+    "ens_stream_triad": (C.c_int, [vp, vp, vp, f64, sz, vp]),
 }
 
 _lib = None

@@ -391,6 +391,16 @@ extern "C" {
 
 int ens_version(void) { return 100; }
 
+int ens_stream_triad(const double* a_dev, const double* b_dev, double* c_dev, double scalar, size_t n,
+                     void* stream) {
+  if (!a_dev || !b_dev || !c_dev || n == 0 || !std::isfinite(scalar)) return ENS_EINVAL;
+  const uintptr_t mis = ((uintptr_t)a_dev | (uintptr_t)b_dev | (uintptr_t)c_dev) & 15;
+  if (mis) return ENS_EINVAL;
+  launch_triad(a_dev, b_dev, c_dev, scalar, n, (hipStream_t)stream);
+  HIPCHECK(hipGetLastError());
+  return ENS_OK;
+}
+
 int ens_last_hip_error(void) { return g_last_hip_error; }
 
 const char* ens_strerror(int code) {

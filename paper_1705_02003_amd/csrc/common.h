@@ -166,6 +166,7 @@ void launch_cheb_start(const double* V, const double* r, double* d, double* z, c
                        const Geometry& g, int groups, hipStream_t s);
 void launch_final(double* x, const double* p0, const double* p1, const Members& m,
                   const Geometry& g, int groups, hipStream_t s);
+void launch_triad(const double* a, const double* b, double* c, double s, size_t n, hipStream_t st);
 void launch_dot(const double* x, const double* y, int y_bcast, double* partial, const Geometry& g,
                 int groups, hipStream_t s);
 void launch_finish(const FinishArgs& a, hipStream_t s);

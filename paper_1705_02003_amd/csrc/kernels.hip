@@ -18,6 +18,7 @@
 // not depend on the member index, so results are deterministic and
 // permuting members permutes results bit for bit.  No floating-point
 // atomics are used.
+#include <algorithm>
 #include <cmath>
 
 #include "device.h"

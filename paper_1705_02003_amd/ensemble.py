@@ -330,3 +330,13 @@ def batch_solve(items, opts: Optional[SolverOptions] = None, batch_ws: Optional[
                                     _stream(dev)), "ens_batch_solve")
     return [BatchResult(x, it_, st_, rr_, int(c_items[k].ens_iters), float(c_items[k].seconds))
             for k, (x, it_, st_, rr_) in enumerate(outs)]
+
+
+def stream_triad(a: torch.Tensor, b: torch.Tensor, c: torch.Tensor, scalar: float) -> None:
+    """c = a + scalar * b on the device (ens_stream_triad); asynchronous."""
+    for t, name in ((a, "a"), (b, "b"), (c, "c")):
+        _require_cuda(t, name)
+    if not (a.numel() == b.numel() == c.numel()):
+        raise ValueError("a, b, c must have the same number of elements")
+    L.check(L.lib().ens_stream_triad(_p(a), _p(b), _p(c), float(scalar), a.numel(),
+                                     _stream(a.device)), "ens_stream_triad")

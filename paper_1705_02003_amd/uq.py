@@ -52,6 +52,7 @@ class UQResult:
     spmv_ms: float = 0.0
     spmv_launches: int = 0
     spmv_member_rows: float = 0.0   # sum over timed launches of N_r * S
+    assemble_ms: float = 0.0        # device time of the ensemble assemblies
 
     @property
     def total_ensemble_iters(self) -> int:
@@ -64,8 +65,12 @@ def _solve_groups(prob, S, y_level, groups, opts, ws, device, spmv_acc):
     ens_iters = []
     for g in groups:
         y = torch.tensor(y_level[g], dtype=torch.float64, device=device)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         V, b = E.assemble(prob, y)
-        res = E.solve(prob, V, b, opts, ws=ws)
+        e1.record()
+        res = E.solve(prob, V, b, opts, ws=ws)     # blocks: both events have completed
+        spmv_acc[3] += e0.elapsed_time(e1)
         if np.any(res.status != 0):
             raise RuntimeError(f"ensemble did not converge: status {res.status.tolist()}")
         gval = E.member_dot(res.x, res.x, ws=ws)
@@ -92,7 +97,7 @@ def adaptive(prob: E.Problem, S: int, budget: int = 1024, max_level: int = 5,
     lv, ix = G.initial_grid(prob.d)
     out = UQResult(level=np.zeros((0, prob.d), np.int32), index=np.zeros((0, prob.d), np.int32),
                    y=np.zeros((0, prob.d)), iters=np.zeros(0, np.int64), qoi=np.zeros(0))
-    spmv_acc = [0.0, 0, 0.0]
+    spmv_acc = [0.0, 0, 0.0, 0.0]
     level = 1
     while True:
         y_level = G.coords(lv, ix)
@@ -124,32 +129,77 @@ def adaptive(prob: E.Problem, S: int, budget: int = 1024, max_level: int = 5,
             break
         level += 1
     out.spmv_ms, out.spmv_launches, out.spmv_member_rows = spmv_acc[0], int(spmv_acc[1]), spmv_acc[2]
+    out.assemble_ms = spmv_acc[3]
     return out
 
 
-def grouping_costs(res: UQResult, S: int, perm_seed: int = 1) -> dict:
-    """Total ensemble iterations and R of each grouping strategy applied to the
-    same samples, level by level (the first level is grouped in generation
-    order for all but the ideal strategy)."""
+def strategy_groups(res: UQResult, S: int, perm_seed: int = 1) -> dict:
+    """Per-level ensembles of S for each grouping strategy applied to the
+    samples of an adaptive run (S may differ from the run's width: the
+    surrogate grouping is then recomputed from the same data).  Strategies:
+    "surrogate" (Section 3.1), "natural" (generation order), "random" (one
+    seeded permutation per level), "param" (Section 3.2: ascending
+    max_x lambda_max / lambda_min of a(x) K(y) = 1 / eps(y_1), i.e. ascending
+    y_1, ties in generation order) and "its" (ascending true counts, the
+    ideal).  On the first level "surrogate" and "random" use generation
+    order: there is nothing to go on yet."""
     rng = np.random.default_rng(perm_seed)
-    out = {}
+    per = {"surrogate": [], "natural": [], "random": [], "param": [], "its": []}
     start = 0
-    per = {"surrogate": [], "natural": [], "random": [], "its": []}
     for r in res.levels:
         its = r.iters
         m = len(its)
+        y = res.y[start:start + m]
         nat = G.chunk(list(range(m)), S)
-        per["natural"].append((nat, its))
-        per["random"].append((G.chunk(list(rng.permutation(m)), S) if r.level > 1 else nat, its))
-        order = sorted(range(m), key=lambda i: (its[i], i))
-        per["its"].append((G.chunk(order, S), its))
-        per["surrogate"].append((r.groups, its))
+        per["natural"].append(nat)
+        per["random"].append(G.chunk(list(rng.permutation(m)), S) if r.level > 1 else nat)
+        per["param"].append(G.chunk(sorted(range(m), key=lambda i: (y[i, 0], i)), S))
+        per["its"].append(G.chunk(sorted(range(m), key=lambda i: (its[i], i)), S))
+        if r.level == 1:
+            sur = nat
+        elif r.groups.shape[1] == S:
+            sur = r.groups
+        else:
+            sur, _ = G.group_samples(res.level[:start], res.index[:start], res.iters[:start], y, S)
+        per["surrogate"].append(sur)
         start += m
-    for k, lst in per.items():
+    return per
+
+
+def grouping_costs(res: UQResult, S: int, perm_seed: int = 1) -> dict:
+    """Total ensemble iterations and R (eqs. (Rl), (R)) of each grouping
+    strategy on the same samples.  Each member's count does not depend on
+    its companions, so these follow exactly from the recorded counts."""
+    out = {}
+    for k, groups in strategy_groups(res, S, perm_seed).items():
+        lst = list(zip(groups, (r.iters for r in res.levels)))
         num = sum(G.ensemble_iteration_total(g, it) for g, it in lst)
         den = sum(int(it.sum()) for _, it in lst)
         out[k] = {"sum_ensemble_iters": int(num), "R": S * num / den,
                   "R_levels": [round(G.cost_ratio(g, it, S), 4) for g, it in lst]}
+    return out
+
+
+def time_groupings(prob: E.Problem, res: UQResult, S: int, opts: Optional[E.SolverOptions] = None,
+                   strategies=("natural", "random", "param", "its", "surrogate"),
+                   perm_seed: int = 1, device="cuda") -> dict:
+    """GPU seconds to solve every sample of an adaptive run grouped by each
+    strategy (assembly included), and the ensemble iterations it took."""
+    opts = opts or E.SolverOptions()
+    ws = E.workspace(prob, S, opts, device)
+    per = strategy_groups(res, S, perm_seed)
+    out = {}
+    for k in strategies:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        total, start = 0, 0
+        for r, groups in zip(res.levels, per[k]):
+            y = res.y[start:start + r.n_samples]
+            _, _, ens_iters = _solve_groups(prob, S, y, groups, opts, ws, device, [0.0, 0, 0.0, 0.0])
+            total += sum(ens_iters)
+            start += r.n_samples
+        torch.cuda.synchronize()
+        out[k] = {"seconds": round(time.perf_counter() - t0, 3), "sum_ensemble_iters": int(total)}
     return out
 
 
@@ -181,11 +231,11 @@ def nonadaptive(prob: E.Problem, S: int, y: np.ndarray, train_level: int,
     ws = E.workspace(prob, S, opts, device)
     lv, ix = G.full_grid(prob.d, train_level)
     yt = G.coords(lv, ix)
-    acc = [0.0, 0, 0.0]
+    acc = [0.0, 0, 0.0, 0.0]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     it_train, _, _ = _solve_groups(prob, S, yt, G.chunk(list(range(len(yt))), S), opts, ws,
-                                   device, [0.0, 0, 0.0])
+                                   device, [0.0, 0, 0.0, 0.0])
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     groups, pred = G.group_samples(lv, ix, it_train, y, S)

@@ -161,3 +161,42 @@ def test_argument_validation_without_gpu(L):
     rc = lib.ens_pcg_solve(C.byref(prob), C.byref(opts), 8, C.c_void_p(256), C.c_void_p(256),
                            C.c_void_p(256), None, None, None, None, None, C.c_void_p(256), 1024, None)
     assert rc == L.ENS_ENOMEM
+
+
+def test_grouping_strategies_on_recorded_counts(L):
+    """The strategy comparison of the benchmark works from recorded counts:
+    'its' is optimal (no grouping has fewer ensemble iterations), 'param'
+    orders by y_1, every strategy covers every sample, and regrouping at
+    another width reproduces the host surrogate grouping (Section 3.1)."""
+    from paper_1705_02003_amd import grouping, uq
+    rng = np.random.default_rng(11)
+    res = uq.UQResult()
+    lv1, ix1 = grouping.initial_grid(4)
+    y1 = grouping.coords(lv1, ix1)
+    # later levels: any distinct dyadic nodes will do for the bookkeeping
+    lv2, ix2 = grouping.full_grid(4, 2)
+    keep = np.array([i for i in range(len(lv2)) if lv2[i].sum() == 2])
+    lv2, ix2 = lv2[keep], ix2[keep]
+    y2 = grouping.coords(lv2, ix2)
+    it1 = rng.integers(100, 900, len(y1))
+    it2 = rng.integers(100, 900, len(y2))
+    res.level = np.vstack([lv1, lv2]).astype(np.int32)
+    res.index = np.vstack([ix1, ix2]).astype(np.int32)
+    res.y = np.vstack([y1, y2])
+    res.iters = np.concatenate([it1, it2])
+    g32, _ = grouping.group_samples(lv1, ix1, it1, y2, 32)
+    res.levels = [uq.LevelRecord(1, len(y1), grouping.chunk(list(range(len(y1))), 32), [], it1,
+                                 np.zeros(len(y1)), np.zeros(len(y1)), 0.0),
+                  uq.LevelRecord(2, len(y2), g32, [], it2, np.zeros(len(y2)), np.zeros(len(y2)), 0.0)]
+    for S in (32, 8):
+        per = uq.strategy_groups(res, S)
+        costs = uq.grouping_costs(res, S)
+        for k, lst in per.items():
+            for r, g in zip(res.levels, lst):
+                assert g.shape[1] == S
+                assert sorted(set(g.reshape(-1).tolist())) == list(range(r.n_samples))
+            assert costs["its"]["sum_ensemble_iters"] <= costs[k]["sum_ensemble_iters"]
+        order = per["param"][1].reshape(-1)
+        assert np.all(np.diff(y2[order[:len(y2)], 0]) >= 0)
+        expect, _ = grouping.group_samples(lv1, ix1, it1, y2, S)
+        assert np.array_equal(per["surrogate"][1], expect)

@@ -368,3 +368,28 @@ def test_symmetric_sweep_bitwise(n, S, kw):
         z2, l2 = ens.cheb_apply(prob, V, R, ens.SolverOptions(precond="chebyshev",
                                                              full_stencil=True, **kc))
         assert torch.equal(z1, z2) and np.array_equal(l1, l2)
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 4096, 1000003])
+def test_stream_triad(n):
+    """c = a + s b exactly (s a power of two makes s b exact, so the fused
+    multiply-add rounds like the separate expression)."""
+    ens = E()
+    g = torch.Generator(device="cpu").manual_seed(n)
+    a = torch.randn(n, generator=g, dtype=torch.float64).cuda()
+    b = torch.randn(n, generator=g, dtype=torch.float64).cuda()
+    c = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+    for s in (0.5, -2.0):
+        ens.stream_triad(a, b, c, s)
+        torch.cuda.synchronize()
+        assert torch.equal(c, a + s * b)
+
+
+def test_stream_triad_rejects_bad_arguments():
+    from paper_1705_02003_amd import _lib as L
+    ens = E()
+    a = torch.zeros(16, dtype=torch.float64, device="cuda")
+    with pytest.raises(L.EnsError):
+        ens.stream_triad(a[1:], a[1:], a[1:], 1.0)        # 8-byte aligned only
+    with pytest.raises(L.EnsError):
+        ens.stream_triad(a, a, a, float("inf"))
