@@ -200,3 +200,46 @@ def test_grouping_strategies_on_recorded_counts(L):
         assert np.all(np.diff(y2[order[:len(y2)], 0]) >= 0)
         expect, _ = grouping.group_samples(lv1, ix1, it1, y2, S)
         assert np.array_equal(per["surrogate"][1], expect)
+
+
+def test_layout_and_new_entry_points_without_gpu(L):
+    """Slot stride, batch sizing and triad / batch argument checks (no device
+    work: every call below fails validation first)."""
+    lib = L.lib()
+    prob = L.ens_problem(512, 4, 0, 0, 0.4)
+    # the slot stride pads N_r S to a multiple of 32 plus 512 elements
+    for n, S in ((512, 32), (1024, 32), (64, 8), (33, 1), (27, 2)):
+        p = L.ens_problem(n, 4, 0, 0, 0.4)
+        Ls = lib.ens_matrix_slot_stride(C.byref(p), S)
+        nr_s = n * n * S
+        assert Ls == ((nr_s + 31) // 32) * 32 + 512
+        assert Ls % 32 == 0 and Ls - nr_s >= 512
+    assert lib.ens_matrix_slot_stride(C.byref(prob), 48) == 0
+    assert lib.ens_batch_workspace_bytes(0) == 0
+    assert lib.ens_batch_workspace_bytes(1025) == 0
+    assert lib.ens_batch_workspace_bytes(64) > 0
+    # triad: null, misaligned, empty, non-finite scalar
+    a = C.c_void_p(4096)
+    assert lib.ens_stream_triad(None, a, a, 1.0, 8, None) == L.ENS_EINVAL
+    assert lib.ens_stream_triad(a, C.c_void_p(4104), a, 1.0, 8, None) == L.ENS_EINVAL
+    assert lib.ens_stream_triad(a, a, a, 1.0, 0, None) == L.ENS_EINVAL
+    assert lib.ens_stream_triad(a, a, a, float("nan"), 8, None) == L.ENS_EINVAL
+    # batch: no items, too many items, a bad width, a too-small item workspace
+    bws = C.c_void_p(4096)
+    nb = lib.ens_batch_workspace_bytes(1)
+    items = (L.ens_batch_item * 1)()
+    assert lib.ens_batch_solve(None, 0, items, bws, nb, None) == L.ENS_EINVAL
+    assert lib.ens_batch_solve(None, 1, items, bws, nb - 1, None) == L.ENS_ENOMEM
+    it = items[0]
+    it.prob = prob
+    it.S = 24
+    it.V_dev = it.b_dev = it.x_dev = it.ws_dev = 4096
+    it.ws_bytes = 1 << 40
+    assert lib.ens_batch_solve(None, 1, items, bws, nb, None) == L.ENS_EINVAL
+    it.S = 32
+    it.ws_bytes = 1024
+    assert lib.ens_batch_solve(None, 1, items, bws, nb, None) == L.ENS_ENOMEM
+    opts = L.ens_opts()
+    opts.precond = L.PRECOND_CHEBYSHEV
+    it.ws_bytes = 1 << 40
+    assert lib.ens_batch_solve(C.byref(opts), 1, items, bws, nb, None) == L.ENS_ENOTSUP
