@@ -601,6 +601,10 @@ def main() -> int:
     }
     if not args.no_s1:
         out["s1_comparison"] = s1_comparison(res, args.S, E.SolverOptions(rtol=RTOL))
+    traffic = out["roofline"]["traffic"]
+    if traffic and spmv_ms > 0:
+        # measured HBM bytes per launch over the same launches' average time
+        out["roofline"]["measured_GBs"] = round(traffic / 1e9 / (spmv_ms / launches / 1e3), 1)
     triad = measure_triad()
     out["roofline"]["stream_triad_GBs"] = triad["GBs"]
     if achieved:
