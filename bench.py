@@ -210,14 +210,25 @@ def su_mode(args) -> int:
     fits the 256 MB Infinity Cache, so its bandwidth is not an HBM figure."""
     import numpy as np
     import torch
+    torch.cuda.set_device(0)
+    y0 = np.array([-1.0, 0.0, 0.0, 0.0])
+    rows = su_rows((1, 2, 4, 8, 16, 32, 64), y0, verbose=True)
+    print(json.dumps({"mode": "su", "workload": "identical-samples-512x512", "y": y0.tolist(),
+                      "rows": rows}), flush=True)
+    return 0
+
+
+def su_rows(S_list, y0, verbose=False) -> list:
+    """Median solve time of S identical samples y0 for each S in S_list (the
+    first entry must be 1) and SU(S) = S t(1) / t(S)."""
+    import numpy as np
+    import torch
     import workloads
     from paper_1705_02003_amd import ensemble as E
-    torch.cuda.set_device(0)
     prob = E.Problem(N_GRID, D, 0, AMP)
-    y0 = np.array([-1.0, 0.0, 0.0, 0.0])
     opts = E.SolverOptions(rtol=RTOL, full_stencil=FULL_STENCIL)
     rows, t1 = [], None
-    for S in (1, 2, 4, 8, 16, 32, 64):
+    for S in S_list:
         y = torch.tensor(workloads.identical_samples(y0, S), dtype=torch.float64, device="cuda")
         V, b = E.assemble(prob, y)
         ws = E.workspace(prob, S, opts)
@@ -233,10 +244,56 @@ def su_mode(args) -> int:
         rows.append({"S": S, "seconds": round(t, 5), "iters": int(r.ens_iters),
                      "sample_solves_per_s": round(S / t, 2), "SU": round(S * t1 / t, 3),
                      "iteration_alg_GBs": round(r.ens_iters * prob.rows * S * ITER_BYTES / t / 1e9, 1)})
-        print(json.dumps(rows[-1]), flush=True)
+        if verbose:
+            print(json.dumps(rows[-1]), flush=True)
         del V, b, ws
-    print(json.dumps({"mode": "su", "workload": "identical-samples-512x512", "y": y0.tolist(),
-                      "rows": rows}), flush=True)
+    return rows
+
+
+def table_mode(args) -> int:
+    """The MI355X analogue of the paper's Tables 2-3 (Section 4) on the
+    benchmark's adaptive sample set: for each S and the groupings "its"
+    (ascending true counts, hypothetical), "sur" (surrogate), "par"
+    (parameter-based) and "nat" (generation order), the per-level cost ratios
+    R_l, the total R, the measured speed-up (time of every linear solve done
+    alone, S = 1, over the time of the ensemble solves; the assemblies'
+    device time excluded from both) and the predicted speed-up SU(S) / R from
+    the identical-sample curve.  Also the quantity of interest E[G^] after
+    each level."""
+    import numpy as np
+    import torch
+    from paper_1705_02003_amd import ensemble as E
+    from paper_1705_02003_amd import uq
+    torch.cuda.set_device(0)
+    S_list = tuple(int(v) for v in args.S_list.split(","))
+    prob = E.Problem(N_GRID, D, 0, AMP)
+    opts = E.SolverOptions(rtol=RTOL, max_iter=20000, full_stencil=FULL_STENCIL)
+    res = uq.adaptive(prob, args.S, budget=args.budget, max_level=5, tau_rel=1e-3,
+                      strategy="surrogate", opts=opts, perm_seed=1)
+    print(f"[bench] adaptive run: levels {[l.n_samples for l in res.levels]}, "
+          f"E[G] by level {[l.qoi_mean for l in res.levels]}", flush=True)
+    su = {r["S"]: r["SU"] for r in su_rows((1,) + S_list, np.array([-1.0, 0.0, 0.0, 0.0]))}
+    print(f"[bench] SU(S): {su}", flush=True)
+    seq = uq.time_groupings(prob, res, 1, opts, strategies=("natural",))["natural"]
+    print(f"[bench] every sample alone: {seq}", flush=True)
+    rows = []
+    names = (("its", "its"), ("surrogate", "sur"), ("param", "par"), ("natural", "nat"))
+    for S in S_list:
+        costs = uq.grouping_costs(res, S)
+        times = uq.time_groupings(prob, res, S, opts, strategies=("surrogate", "param", "natural"))
+        for key, name in names:
+            t = times.get(key)
+            row = {"I": name, "S": S, "R_levels": costs[key]["R_levels"],
+                   "R": round(costs[key]["R"], 3),
+                   "speedup": round(seq["solve_seconds"] / t["solve_seconds"], 2) if t else None,
+                   "predicted": round(su[S] / costs[key]["R"], 2),
+                   "solve_seconds": t["solve_seconds"] if t else None}
+            rows.append(row)
+            print(json.dumps(row), flush=True)
+    print(json.dumps({"mode": "table", "workload": "adaptive-sg-512x512-d4",
+                      "samples": len(res.y), "levels": [l.n_samples for l in res.levels],
+                      "qoi_mean_levels": [l.qoi_mean for l in res.levels],
+                      "SU": su, "sequential": seq, "rows": rows}), flush=True)
     return 0
 
 
@@ -482,11 +539,13 @@ def main() -> int:
     ap.add_argument("--cpu-procs", type=int, default=0, help="0: min(16, cpu count)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-s1", action="store_true")
-    ap.add_argument("--mode", choices=["full", "kernel", "adjoint", "cheb", "batch", "su", "grouping"],
+    ap.add_argument("--mode", choices=["full", "kernel", "adjoint", "cheb", "batch", "su", "grouping",
+                                       "table"],
                     default="full",
                     help="kernel: a fixed-iteration solve of one ensemble plus a 1 GiB "
                          "copy, for hardware-counter runs")
     ap.add_argument("--iters", type=int, default=100, help="iterations in --mode kernel")
+    ap.add_argument("--S-list", default="4,8,16,32,64", help="ensemble widths in --mode table")
     ap.add_argument("--full-stencil", action="store_true",
                     help="read all nine matrix values per row (no symmetric reuse)")
     ap.add_argument("--sequential", action="store_true",
@@ -513,6 +572,8 @@ def main() -> int:
         return su_mode(args)
     if args.mode == "grouping":
         return grouping_mode(args)
+    if args.mode == "table":
+        return table_mode(args)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -595,6 +656,7 @@ def main() -> int:
         "ensemble_iterations": res.total_ensemble_iters,
         "sample_solves_per_s_without_assembly": round(n_samples / (times[-1] - asm_s), 3),
         "assembly_seconds": round(asm_s, 3),
+        "qoi_mean_levels": [l.qoi_mean for l in res.levels],
         "grouping": costs,
         "grouping_S16": costs16,
         "cpu_baseline": cpu,

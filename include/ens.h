@@ -286,6 +286,19 @@ int ens_sg_surpluses(int32_t d, int32_t M, const int32_t* node_level,
                      const int32_t* node_index, const double* node_value,
                      double* surplus_out);
 
+/* Mean of the sparse-grid interpolant of node_value under the uniform density
+ * 2^-d on [-1,1]^d (paper, Section 2.1: the quantity of interest is the
+ * expectation of G(y); Section 2.2: the interpolant sum_m c_m psi_m integrates
+ * term by term).  A 1-D basis function of level l integrates to 1 (l = 0),
+ * 1/4 (l = 1) or 2^-l (l >= 2) against the density 1/2; the sum runs over the
+ * nodes in canonical order, each term c_m times the d weights in dimension
+ * order.  Host only and synchronous.  Out: *mean_out.
+ * Errors: ENS_EINVAL for M = 0, a NULL pointer, an invalid or duplicate node,
+ * or a non-finite value. */
+int ens_sg_expectation(int32_t d, int32_t M, const int32_t* node_level,
+                       const int32_t* node_index, const double* node_value,
+                       double* mean_out);
+
 /* Coordinates of nodes: y_out [M][d]. */
 int ens_sg_coords(int32_t d, int32_t M, const int32_t* node_level,
                   const int32_t* node_index, double* y_out);

@@ -141,6 +141,16 @@ void surpluses(const Grid& g, const double* value, std::vector<double>& c) {
   }
 }
 
+// Integral of a 1-D hierarchical basis function against the uniform density
+// 1/2 on [-1, 1]: 1 at level 0 (the constant), 1/4 at level 1 (half a hat of
+// unit base at the end points), 2^-l at level l >= 2 (a whole hat of
+// half-width 2^(1-l)).
+double weight_1d(int32_t l) {
+  if (l == 0) return 1.0;
+  if (l == 1) return 0.25;
+  return std::ldexp(1.0, -l);
+}
+
 bool finite_all(const double* v, size_t n) {
   for (size_t i = 0; i < n; ++i)
     if (!std::isfinite(v[i])) return false;
@@ -171,6 +181,26 @@ int ens_sg_surpluses(int32_t d, int32_t M, const int32_t* node_level, const int3
   std::vector<double> c;
   surpluses(g, node_value, c);
   std::copy(c.begin(), c.end(), surplus_out);
+  return ENS_OK;
+}
+
+int ens_sg_expectation(int32_t d, int32_t M, const int32_t* node_level, const int32_t* node_index,
+                       const double* node_value, double* mean_out) {
+  Grid g;
+  int rc = load_grid(d, M, node_level, node_index, g);
+  if (rc) return rc;
+  if (M == 0 || !node_value || !mean_out) return ENS_EINVAL;
+  if (!finite_all(node_value, (size_t)M)) return ENS_EINVAL;
+  std::vector<double> c;
+  surpluses(g, node_value, c);
+  // the interpolant integrates term by term: sum_m c_m prod_n w(l_mn)
+  double acc = 0.0;
+  for (int m : canonical_order(g)) {
+    double t = c[m];
+    for (int n = 0; n < d; ++n) t = t * weight_1d(g.L(m)[n]);
+    acc = acc + t;
+  }
+  *mean_out = acc;
   return ENS_OK;
 }
 

@@ -58,6 +58,19 @@ def surpluses(level, index, values) -> np.ndarray:
     return out
 
 
+def expectation(level, index, values) -> float:
+    """Mean of the sparse-grid interpolant of ``values`` under the uniform
+    density on [-1, 1]^d: the quantity of interest E[G^] (Section 2.1)."""
+    lv, ix = _i32(level), _i32(index)
+    M, d = lv.shape
+    vv = _f64(values, (M,))
+    out = np.zeros(1, np.float64)
+    L.check(L.lib().ens_sg_expectation(d, M, lv.ctypes.data_as(L.i32p), ix.ctypes.data_as(L.i32p),
+                                       vv.ctypes.data_as(L.f64p), out.ctypes.data_as(L.f64p)),
+            "ens_sg_expectation")
+    return float(out[0])
+
+
 def coords(level, index) -> np.ndarray:
     lv, ix = _i32(level), _i32(index)
     M, d = lv.shape

@@ -243,3 +243,28 @@ def test_layout_and_new_entry_points_without_gpu(L):
     opts.precond = L.PRECOND_CHEBYSHEV
     it.ws_bytes = 1 << 40
     assert lib.ens_batch_solve(C.byref(opts), 1, items, bws, nb, None) == L.ENS_ENOTSUP
+
+
+@pytest.mark.parametrize("d,Lv,seed", [(2, 5, 0), (4, 5, 1), (8, 2, 2), (1, 6, 3)])
+def test_expectation_bit_exact_with_oracle(L, d, Lv, seed):
+    from paper_1705_02003_amd import grouping
+    rng = np.random.default_rng(seed)
+    nodes = adaptive_like_grid(d, Lv, 0.6, seed)
+    nodes = [nodes[i] for i in rng.permutation(len(nodes))]
+    lv, ix = nodes_to_arrays(nodes)
+    for vals in (rng.integers(50, 3000, len(nodes)).astype(float), rng.standard_normal(len(nodes))):
+        assert grouping.expectation(lv, ix, vals) == sg.expectation(sg.surpluses(nodes, vals))
+
+
+def test_expectation_rejects_bad_arguments(L):
+    lib = L.lib()
+    lv = np.zeros((1, 2), np.int32)
+    out = np.zeros(1)
+    v = np.array([np.nan])
+    args = (lv.ctypes.data_as(L.i32p), lv.ctypes.data_as(L.i32p))
+    assert lib.ens_sg_expectation(2, 1, *args, v.ctypes.data_as(L.f64p), out.ctypes.data_as(L.f64p)) < 0
+    v[0] = 2.0
+    assert lib.ens_sg_expectation(2, 0, *args, v.ctypes.data_as(L.f64p), out.ctypes.data_as(L.f64p)) < 0
+    assert lib.ens_sg_expectation(2, 1, *args, v.ctypes.data_as(L.f64p), None) < 0
+    assert lib.ens_sg_expectation(2, 1, *args, v.ctypes.data_as(L.f64p), out.ctypes.data_as(L.f64p)) == 0
+    assert out[0] == 2.0

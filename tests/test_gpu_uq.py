@@ -1,0 +1,80 @@
+"""The adaptive loop (Section 3.1, Fig. 2) end to end on the GPU against the
+oracle, on a small grid.
+
+Per sample: the iteration count within +-1 of the oracle's PCG and
+G(y) = ||u||^2 within 1e-9 relative (two PCG solves stopped at rtol 1e-8,
+even one iteration apart, differ in G by about 1e-11 here).  The host steps
+are exact functions of the recorded numbers, so they are compared bit for bit
+with the oracle fed the same numbers: each level's new nodes (refinement on
+the GPU's G values), each level's ensembles (surrogate of the GPU's
+iteration counts), and E[G^] after each level.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import pcg as opcg
+from oracle import problem as oprob
+from oracle import sparse_grid as sg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible: the gpu tests must run on an MI355X")
+    yield
+
+
+def nodes_of(level, index):
+    return [tuple((int(l), int(k)) for l, k in zip(lr, kr)) for lr, kr in zip(level, index)]
+
+
+@pytest.mark.parametrize("n,S,budget,max_level,tau", [(24, 8, 70, 3, 1e-3), (17, 4, 45, 4, 5e-3)])
+def test_adaptive_loop_matches_oracle(n, S, budget, max_level, tau):
+    from paper_1705_02003_amd import ensemble as E
+    from paper_1705_02003_amd import uq
+    print(f"CASE adaptive n={n} S={S} budget={budget}", flush=True)
+    d, rtol = 4, 1e-8
+    prob = E.Problem(n, d, 0, 0.4)
+    res = uq.adaptive(prob, S, budget=budget, max_level=max_level, tau_rel=tau,
+                      strategy="surrogate", opts=E.SolverOptions(rtol=rtol))
+    nodes = nodes_of(res.level, res.index)
+    assert len(nodes) == len(set(nodes)) == len(res.y) <= budget
+    assert len(res.levels) >= 2
+
+    # per sample: the solve
+    for m, nd in enumerate(nodes):
+        y = sg.coords(nd)
+        assert np.array_equal(y, res.y[m])
+        A, b, dg = oprob.assemble(y, n, 0, 0.4)
+        x, it, _, _ = opcg.pcg(A, b, dg, rtol, 20000)
+        assert abs(int(res.iters[m]) - it) <= 1, (m, res.iters[m], it)
+        g = float(x @ x)
+        assert abs(res.qoi[m] - g) <= 1e-9 * g, (m, res.qoi[m], g)
+
+    # per level: refinement, grouping and E[G^] from the recorded numbers
+    start = 0
+    for li, rec in enumerate(res.levels):
+        here = nodes[start:start + rec.n_samples]
+        before = nodes[:start]
+        if li == 0:
+            assert here == sg.full_grid(d, 1)
+            assert rec.groups.tolist() == sg.chunk(list(range(rec.n_samples)), S)
+        else:
+            new = sg.refine(before, res.qoi[:start], rec.level - 1, tau, budget)
+            assert here == new
+            groups, pred = sg.group_samples(before, res.iters[:start].astype(float),
+                                            res.y[start:start + rec.n_samples], S)
+            assert rec.groups.tolist() == groups
+            assert np.array_equal(rec.pred, pred)
+        upto = nodes[:start + rec.n_samples]
+        c = sg.surpluses(upto, res.qoi[:start + rec.n_samples])
+        assert rec.qoi_mean == sg.expectation(c)
+        start += rec.n_samples
+    assert res.qoi_mean == res.levels[-1].qoi_mean
+    # the ensemble counts are the max over their members
+    for rec in res.levels:
+        for g, k in zip(rec.groups, rec.ens_iters):
+            assert k == int(rec.iters[g].max())

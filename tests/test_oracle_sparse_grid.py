@@ -175,3 +175,75 @@ def test_R_level1_matches_paper_ratio():
     pad16 = 16 * 900 / (sum(its) + 7 * 900)
     pad32 = 32 * 900 / (sum(its) + 23 * 900)
     assert abs(pad32 / pad16 - 2) > 0.1
+
+
+# ------------------------------------------------ mean of the interpolant
+def trapezoid_weights(h):
+    n = int(round(2 / h)) + 1
+    w = np.full(n, h)
+    w[0] = w[-1] = h / 2
+    return np.linspace(-1.0, 1.0, n), w
+
+
+def test_mean_1d_is_the_hat_integral():
+    # phi_1d is piecewise linear with breakpoints on multiples of 2^(1-l):
+    # the trapezoid rule on a finer dyadic grid integrates it exactly.
+    xs, w = trapezoid_weights(2.0 ** -8)
+    for l in range(7):
+        for k in range({0: 1, 1: 2}.get(l, 2 ** max(l - 1, 0))):
+            f = np.array([sg.phi_1d(l, k, x) for x in xs])
+            assert sg.mean_1d(l, k) == pytest.approx(float(w @ f) / 2, abs=1e-15)
+
+
+def test_mean_one_d_is_the_trapezoid_rule_on_the_nodes():
+    g = sg.full_grid(1, 5)
+    xs = np.array([sg.coords(nd)[0] for nd in g])
+    v = np.random.default_rng(3).standard_normal(len(g))
+    order = np.argsort(xs)
+    ref = np.trapezoid(v[order], xs[order]) / 2
+    assert sg.expectation(sg.surpluses(g, v)) == pytest.approx(ref, rel=1e-14, abs=1e-15)
+
+
+def test_mean_of_affine_function_is_its_centre_value():
+    g = sg.full_grid(3, 3)
+    a0, a = -1.75, np.array([0.5, 2.0, -3.25])
+    v = [a0 + a @ sg.coords(nd) for nd in g]
+    assert sg.expectation(sg.surpluses(g, v)) == pytest.approx(a0, abs=1e-14)
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 4, 5])
+def test_mean_of_quadratic_closed_form(L):
+    # y^2 interpolated linearly on nodes spaced h = 2^(1-L) over [-1, 1]
+    # overshoots by h^2 / 6 per unit length: E = 1/3 + h^2 / 6 per dimension.
+    # An additive function has zero surpluses at mixed nodes, so the 2-D
+    # sparse grid of total level L holds the 1-D level-L interpolants.
+    g = sg.full_grid(2, L)
+    v = [sg.coords(nd)[0] ** 2 + 3 * sg.coords(nd)[1] ** 2 for nd in g]
+    h = 2.0 ** (1 - L)
+    assert sg.expectation(sg.surpluses(g, v)) == pytest.approx(4 * (1 / 3 + h * h / 6), rel=1e-14)
+
+
+@pytest.mark.parametrize("d,L,seed", [(2, 5, 0), (3, 3, 1), (2, 4, 2)])
+def test_mean_is_exact_quadrature_of_the_interpolant(d, L, seed):
+    # The interpolant is multilinear on every cell of the grid spaced
+    # 2^(1-L): the tensor trapezoid rule on that grid is exact for it.
+    rng = np.random.default_rng(seed)
+    g = [nd for nd in sg.full_grid(d, L) if sg.total_level(nd) <= 1 or rng.random() < 0.7]
+    c = sg.surpluses(g, rng.standard_normal(len(g)))
+    xs, w = trapezoid_weights(2.0 ** (1 - L))
+    Y = np.array(list(itertools.product(xs, repeat=d)))
+    W = np.array([math.prod(t) for t in itertools.product(w, repeat=d)])
+    ref = float(W @ sg.evaluate_many(c, Y)) / 2 ** d
+    assert sg.expectation(c) == pytest.approx(ref, rel=1e-12, abs=1e-14)
+
+
+def test_mean_converges_to_the_integral_of_a_smooth_function():
+    # E[exp(y1 + y2 / 2)] = sinh(1) * 2 sinh(1/2) for uniform y on [-1, 1]^2
+    exact = math.sinh(1.0) * 2 * math.sinh(0.5)
+    errs = []
+    for L in range(3, 8):
+        g = sg.full_grid(2, L)
+        v = [math.exp(sg.coords(nd)[0] + sg.coords(nd)[1] / 2) for nd in g]
+        errs.append(abs(sg.expectation(sg.surpluses(g, v)) - exact))
+    assert errs[-1] < 2e-5
+    assert all(b < a / 3 for a, b in zip(errs, errs[1:]))
