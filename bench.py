@@ -272,8 +272,12 @@ def table_mode(args) -> int:
                       strategy="surrogate", opts=opts, perm_seed=1)
     print(f"[bench] adaptive run: levels {[l.n_samples for l in res.levels]}, "
           f"E[G] by level {[l.qoi_mean for l in res.levels]}", flush=True)
-    su = {r["S"]: r["SU"] for r in su_rows((1,) + S_list, np.array([-1.0, 0.0, 0.0, 0.0]))}
+    curve = su_rows((1, 2, 4, 8, 16, 32, 64), np.array([-1.0, 0.0, 0.0, 0.0]))
+    su = {r["S"]: r["SU"] for r in curve}
     print(f"[bench] SU(S): {su}", flush=True)
+    # seconds per ensemble iteration at each width, from the same curve
+    widths = [r["S"] for r in curve]
+    iter_s = [r["seconds"] / r["iters"] for r in curve]
     seq = uq.time_groupings(prob, res, 1, opts, strategies=("natural",))["natural"]
     print(f"[bench] every sample alone: {seq}", flush=True)
     rows = []
@@ -290,6 +294,21 @@ def table_mode(args) -> int:
                    "solve_seconds": t["solve_seconds"] if t else None}
             rows.append(row)
             print(json.dumps(row), flush=True)
+    # ensembles of varying width (Section 5): least predicted time per level
+    per = uq.variable_groups(res, widths, iter_s)
+    vc = uq.variable_costs(res, per)
+    t = uq.time_groupings(prob, res, 64, opts, strategies=("variable",),
+                          extra={"variable": per})["variable"]
+    its = res.iters
+    pred_t = iter_s[0] * float(its.sum())
+    var_t = sum(sum(iter_s[widths.index(len(g))] * int(it[np.asarray(g)].max()) for g in gs)
+                for gs, it in zip(per, (r.iters for r in res.levels)))
+    row = {"I": "var", "S": "1-64", "R_levels": vc["R_levels"], "R": round(vc["R"], 3),
+           "speedup": round(seq["solve_seconds"] / t["solve_seconds"], 2),
+           "predicted": round(pred_t / var_t, 2), "solve_seconds": t["solve_seconds"],
+           "widths": vc["widths"]}
+    rows.append(row)
+    print(json.dumps(row), flush=True)
     print(json.dumps({"mode": "table", "workload": "adaptive-sg-512x512-d4",
                       "samples": len(res.y), "levels": [l.n_samples for l in res.levels],
                       "qoi_mean_levels": [l.qoi_mean for l in res.levels],

@@ -299,6 +299,32 @@ int ens_sg_expectation(int32_t d, int32_t M, const int32_t* node_level,
                        const int32_t* node_index, const double* node_value,
                        double* mean_out);
 
+/* Ensembles of varying width (paper, Section 5: choose ensemble sizes by a
+ * combinatorial optimisation from a per-size performance model and the cost
+ * surrogate).  Input: pred [M], the predicted iteration count of each sample
+ * (a prediction below 1 counts as 1); the allowed widths [n_widths]
+ * (ascending, distinct powers of two in [1, 64], n_widths <= 7) and
+ * iter_seconds [n_widths], the time of one ensemble iteration at each width.
+ * The samples are ordered by ascending (pred, id) and the order is cut into
+ * consecutive groups; group g has a width w_g and holds 1..w_g real samples
+ * (padded to w_g by repeating its last one) and costs
+ * iter_seconds[w_g] * (its largest prediction).  The cut with the least total
+ * cost is found exactly (dynamic programming over the order; ties keep the
+ * smaller width, then the fewer samples in the last group).  Ordering first
+ * loses nothing: exchanging samples between two groups so that the one with
+ * the smaller maximum holds the smaller samples never raises a group's
+ * maximum.  Host only and synchronous.
+ * Out: order_out [M] sample ids; group_width_out, group_count_out [M]
+ * (the first *n_groups_out entries are used; group g takes the next
+ * group_count_out[g] ids of the order); *cost_out, the least total cost.
+ * Errors: ENS_EINVAL for M < 1, a NULL pointer, a bad width list, a
+ * non-positive or non-finite iter_seconds, or a non-finite prediction. */
+int ens_group_variable(int32_t M, const double* pred, int32_t n_widths,
+                       const int32_t* widths, const double* iter_seconds,
+                       int32_t* order_out, int32_t* group_width_out,
+                       int32_t* group_count_out, int32_t* n_groups_out,
+                       double* cost_out);
+
 /* Coordinates of nodes: y_out [M][d]. */
 int ens_sg_coords(int32_t d, int32_t M, const int32_t* node_level,
                   const int32_t* node_index, double* y_out);

@@ -337,4 +337,63 @@ int ens_sg_refine(int32_t d, int32_t M, const int32_t* node_level, const int32_t
   return ENS_OK;
 }
 
+int ens_group_variable(int32_t M, const double* pred, int32_t n_widths, const int32_t* widths,
+                       const double* iter_seconds, int32_t* order_out, int32_t* group_width_out,
+                       int32_t* group_count_out, int32_t* n_groups_out, double* cost_out) {
+  if (M < 1 || !pred || !widths || !iter_seconds || !order_out || !group_width_out ||
+      !group_count_out || !n_groups_out || !cost_out)
+    return ENS_EINVAL;
+  if (n_widths < 1 || n_widths > 7) return ENS_EINVAL;
+  for (int w = 0; w < n_widths; ++w) {
+    const int32_t s = widths[w];
+    if (s < 1 || s > 64 || (s & (s - 1)) != 0) return ENS_EINVAL;
+    if (w > 0 && s <= widths[w - 1]) return ENS_EINVAL;
+    if (!std::isfinite(iter_seconds[w]) || !(iter_seconds[w] > 0.0)) return ENS_EINVAL;
+  }
+  if (!finite_all(pred, (size_t)M)) return ENS_EINVAL;
+
+  std::vector<int32_t> order(M);
+  for (int i = 0; i < M; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    if (pred[a] != pred[b]) return pred[a] < pred[b];
+    return a < b;
+  });
+  // best[i]: least predicted time of the first i samples of the order; the
+  // last group ends at sample i - 1, whose prediction is the group's maximum
+  std::vector<double> best(M + 1, 0.0);
+  std::vector<int32_t> pick_w(M + 1, 0), pick_m(M + 1, 0);
+  for (int i = 1; i <= M; ++i) {
+    const double p = std::max(pred[order[i - 1]], 1.0);
+    bool have = false;
+    for (int w = 0; w < n_widths; ++w) {
+      const double term = iter_seconds[w] * p;
+      const int mmax = std::min(widths[w], i);
+      for (int m = 1; m <= mmax; ++m) {
+        const double v = best[i - m] + term;
+        if (!have || v < best[i]) {
+          best[i] = v;
+          pick_w[i] = w;
+          pick_m[i] = m;
+          have = true;
+        }
+      }
+    }
+  }
+  // walk back from the end, then emit the groups in ascending order
+  std::vector<int32_t> gw, gc;
+  for (int i = M; i > 0; i -= pick_m[i]) {
+    gw.push_back(widths[pick_w[i]]);
+    gc.push_back(pick_m[i]);
+  }
+  const int G = (int)gw.size();
+  for (int g = 0; g < G; ++g) {
+    group_width_out[g] = gw[G - 1 - g];
+    group_count_out[g] = gc[G - 1 - g];
+  }
+  std::copy(order.begin(), order.end(), order_out);
+  *n_groups_out = G;
+  *cost_out = best[M];
+  return ENS_OK;
+}
+
 }  // extern "C"

@@ -47,6 +47,33 @@ def group_samples(level, index, values, y_new, S: int) -> Tuple[np.ndarray, np.n
     return groups, pred
 
 
+def group_variable(pred, widths, iter_seconds):
+    """Ensembles of varying width with the least predicted time (Section 5):
+    returns (groups, cost), groups a list of id arrays, each padded to its
+    width by repeating its last sample, in ascending order of prediction."""
+    pred = _f64(pred)
+    M = len(pred)
+    wd = _i32(widths)
+    ts = _f64(iter_seconds, (len(wd),))
+    order = np.zeros(M, np.int32)
+    gw = np.zeros(max(M, 1), np.int32)
+    gc = np.zeros(max(M, 1), np.int32)
+    ng = L.i32(0)
+    cost = L.f64(0.0)
+    import ctypes as C
+    L.check(L.lib().ens_group_variable(M, pred.ctypes.data_as(L.f64p), len(wd),
+                                       wd.ctypes.data_as(L.i32p), ts.ctypes.data_as(L.f64p),
+                                       order.ctypes.data_as(L.i32p), gw.ctypes.data_as(L.i32p),
+                                       gc.ctypes.data_as(L.i32p), C.byref(ng), C.byref(cost)),
+            "ens_group_variable")
+    groups, at = [], 0
+    for g in range(int(ng.value)):
+        ids = order[at:at + gc[g]].tolist()
+        at += int(gc[g])
+        groups.append(np.array(ids + [ids[-1]] * (int(gw[g]) - len(ids)), np.int32))
+    return groups, float(cost.value)
+
+
 def surpluses(level, index, values) -> np.ndarray:
     lv, ix = _i32(level), _i32(index)
     M, d = lv.shape
@@ -123,6 +150,15 @@ def cost_ratio(groups: np.ndarray, iters: Sequence[int], S: int) -> float:
     iters = np.asarray(iters)
     num = S * int(sum(int(iters[g].max()) for g in np.asarray(groups)))
     real = np.unique(np.asarray(groups).reshape(-1))
+    return num / float(iters[real].sum())
+
+
+def cost_ratio_variable(groups, iters: Sequence[int]) -> float:
+    """R for ensembles of any widths: sum over ensembles of width times the
+    max member count, over the sum of counts of the real samples."""
+    iters = np.asarray(iters)
+    num = sum(len(g) * int(iters[np.asarray(g)].max()) for g in groups)
+    real = np.unique(np.concatenate([np.asarray(g) for g in groups]))
     return num / float(iters[real].sum())
 
 

@@ -35,7 +35,8 @@ from . import grouping as G
 class LevelRecord:
     level: int
     n_samples: int
-    groups: np.ndarray          # (K_l, S) indices into this level's samples
+    groups: np.ndarray          # (K_l, S) indices into this level's samples (a list of
+                                # id arrays of varying width with strategy "variable")
     ens_iters: List[int]        # K_e per ensemble
     iters: np.ndarray           # per real sample
     qoi: np.ndarray             # G(y) per real sample
@@ -68,11 +69,28 @@ class UQResult:
         return int(sum(sum(r.ens_iters) for r in self.levels))
 
 
-def _solve_groups(prob, S, y_level, groups, opts, ws, device, spmv_acc):
+class _Workspaces:
+    """Solver workspaces by ensemble width, allocated on first use."""
+
+    def __init__(self, prob, opts, device):
+        self.prob, self.opts, self.device, self.by_width = prob, opts, device, {}
+
+    def __call__(self, S: int):
+        if S not in self.by_width:
+            self.by_width[S] = E.workspace(self.prob, S, self.opts, self.device)
+        return self.by_width[S]
+
+
+def _solve_groups(prob, y_level, groups, opts, wss, device, spmv_acc):
+    """Solve each group (an id array; its length is the ensemble width) and
+    record per-sample counts and G(y) = ||u||^2."""
     iters = np.full(len(y_level), -1, np.int64)
     qoi = np.zeros(len(y_level))
     ens_iters = []
     for g in groups:
+        g = np.asarray(g)
+        S = len(g)
+        ws = wss(S)
         y = torch.tensor(y_level[g], dtype=torch.float64, device=device)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -98,11 +116,15 @@ def _solve_groups(prob, S, y_level, groups, opts, ws, device, spmv_acc):
 def adaptive(prob: E.Problem, S: int, budget: int = 1024, max_level: int = 5,
              tau_rel: float = 1e-3, strategy: str = "surrogate",
              opts: Optional[E.SolverOptions] = None, perm_seed: int = 1,
-             device="cuda") -> UQResult:
-    """Run the adaptive loop; every sample is solved on the GPU in ensembles of S."""
+             device="cuda", widths=None, iter_seconds=None) -> UQResult:
+    """Run the adaptive loop; every sample is solved on the GPU in ensembles
+    of S, or, with strategy "variable", in ensembles of the given ``widths``
+    chosen by least predicted time (``iter_seconds`` per ensemble iteration
+    at each width; the surrogate predicts the counts, all counts are taken
+    equal on the first level)."""
     opts = opts or E.SolverOptions()
     rng = np.random.default_rng(perm_seed)
-    ws = E.workspace(prob, S, opts, device)
+    wss = _Workspaces(prob, opts, device)
     lv, ix = G.initial_grid(prob.d)
     out = UQResult(level=np.zeros((0, prob.d), np.int32), index=np.zeros((0, prob.d), np.int32),
                    y=np.zeros((0, prob.d)), iters=np.zeros(0, np.int64), qoi=np.zeros(0))
@@ -110,7 +132,7 @@ def adaptive(prob: E.Problem, S: int, budget: int = 1024, max_level: int = 5,
     level = 1
     while True:
         y_level = G.coords(lv, ix)
-        if level == 1 or strategy == "natural":
+        if strategy != "variable" and (level == 1 or strategy == "natural"):
             groups = G.chunk(list(range(len(y_level))), S)
             pred = np.zeros(len(y_level))
         elif strategy == "surrogate":
@@ -118,11 +140,17 @@ def adaptive(prob: E.Problem, S: int, budget: int = 1024, max_level: int = 5,
         elif strategy == "random":
             groups = G.chunk(list(rng.permutation(len(y_level))), S)
             pred = np.zeros(len(y_level))
+        elif strategy == "variable":
+            if level == 1:
+                pred = np.ones(len(y_level))
+            else:
+                _, pred = G.group_samples(out.level, out.index, out.iters, y_level, 1)
+            groups, _ = G.group_variable(pred, widths, iter_seconds)
         else:
             raise ValueError(strategy)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        iters, qoi, ens_iters = _solve_groups(prob, S, y_level, groups, opts, ws, device, spmv_acc)
+        iters, qoi, ens_iters = _solve_groups(prob, y_level, groups, opts, wss, device, spmv_acc)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         out.level = np.vstack([out.level, lv])
@@ -177,6 +205,35 @@ def strategy_groups(res: UQResult, S: int, perm_seed: int = 1) -> dict:
     return per
 
 
+def variable_groups(res: UQResult, widths, iter_seconds) -> list:
+    """Per-level ensembles of varying width for the samples of an adaptive
+    run (Section 5): least predicted time with the surrogate of the earlier
+    levels' counts (equal counts assumed on the first level)."""
+    per, start = [], 0
+    for r in res.levels:
+        m = r.n_samples
+        if r.level == 1:
+            pred = np.ones(m)
+        else:
+            _, pred = G.group_samples(res.level[:start], res.index[:start], res.iters[:start],
+                                      res.y[start:start + m], 1)
+        groups, _ = G.group_variable(pred, widths, iter_seconds)
+        per.append(groups)
+        start += m
+    return per
+
+
+def variable_costs(res: UQResult, per: list) -> dict:
+    """R (widths weighted) of per-level ensembles of varying width, and the
+    widths used."""
+    lst = list(zip(per, (r.iters for r in res.levels)))
+    num = sum(sum(len(g) * int(it[np.asarray(g)].max()) for g in gs) for gs, it in lst)
+    den = sum(int(it.sum()) for _, it in lst)
+    widths = sorted({len(g) for gs in per for g in gs})
+    return {"R": num / den, "R_levels": [round(G.cost_ratio_variable(gs, it), 4) for gs, it in lst],
+            "widths": {int(w): sum(1 for gs in per for g in gs if len(g) == w) for w in widths}}
+
+
 def grouping_costs(res: UQResult, S: int, perm_seed: int = 1) -> dict:
     """Total ensemble iterations and R (eqs. (Rl), (R)) of each grouping
     strategy on the same samples.  Each member's count does not depend on
@@ -193,13 +250,16 @@ def grouping_costs(res: UQResult, S: int, perm_seed: int = 1) -> dict:
 
 def time_groupings(prob: E.Problem, res: UQResult, S: int, opts: Optional[E.SolverOptions] = None,
                    strategies=("natural", "random", "param", "its", "surrogate"),
-                   perm_seed: int = 1, device="cuda") -> dict:
+                   perm_seed: int = 1, device="cuda", extra: Optional[dict] = None) -> dict:
     """Wall seconds to solve every sample of an adaptive run grouped by each
     strategy, assembly included ("seconds") and without the assemblies'
-    device time ("solve_seconds"), and the ensemble iterations it took."""
+    device time ("solve_seconds"), and the ensemble iterations it took.
+    ``extra`` adds strategies given as per-level group lists."""
     opts = opts or E.SolverOptions()
-    ws = E.workspace(prob, S, opts, device)
+    wss = _Workspaces(prob, opts, device)
     per = strategy_groups(res, S, perm_seed)
+    if extra:
+        per.update(extra)
     out = {}
     for k in strategies:
         acc = [0.0, 0, 0.0, 0.0]
@@ -208,7 +268,7 @@ def time_groupings(prob: E.Problem, res: UQResult, S: int, opts: Optional[E.Solv
         total, start = 0, 0
         for r, groups in zip(res.levels, per[k]):
             y = res.y[start:start + r.n_samples]
-            _, _, ens_iters = _solve_groups(prob, S, y, groups, opts, ws, device, acc)
+            _, _, ens_iters = _solve_groups(prob, y, groups, opts, wss, device, acc)
             total += sum(ens_iters)
             start += r.n_samples
         torch.cuda.synchronize()
@@ -243,13 +303,13 @@ def nonadaptive(prob: E.Problem, S: int, y: np.ndarray, train_level: int,
     the samples ``y`` into ensembles of S.  ``solve_groups`` selects which of
     the resulting ensembles are solved (all by default)."""
     opts = opts or E.SolverOptions()
-    ws = E.workspace(prob, S, opts, device)
+    wss = _Workspaces(prob, opts, device)
     lv, ix = G.full_grid(prob.d, train_level)
     yt = G.coords(lv, ix)
     acc = [0.0, 0, 0.0, 0.0]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    it_train, _, _ = _solve_groups(prob, S, yt, G.chunk(list(range(len(yt))), S), opts, ws,
+    it_train, _, _ = _solve_groups(prob, yt, G.chunk(list(range(len(yt))), S), opts, wss,
                                    device, [0.0, 0, 0.0, 0.0])
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
@@ -258,7 +318,7 @@ def nonadaptive(prob: E.Problem, S: int, y: np.ndarray, train_level: int,
     chosen = np.asarray([groups[k] for k in sel])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    iters, _, ens_iters = _solve_groups(prob, S, y, chosen, opts, ws, device, acc)
+    iters, _, ens_iters = _solve_groups(prob, y, chosen, opts, wss, device, acc)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     return NonAdaptiveResult(it_train, groups, pred, iters, ens_iters, dt, t_train,

@@ -78,3 +78,34 @@ def test_adaptive_loop_matches_oracle(n, S, budget, max_level, tau):
     for rec in res.levels:
         for g, k in zip(rec.groups, rec.ens_iters):
             assert k == int(rec.iters[g].max())
+
+
+def test_adaptive_loop_variable_widths_matches_oracle():
+    from paper_1705_02003_amd import ensemble as E
+    from paper_1705_02003_amd import uq
+    n, d, rtol, tau, budget = 20, 4, 1e-8, 1e-3, 60
+    widths, secs = [1, 2, 4, 8, 16], [1.0, 1.3, 1.7, 2.6, 4.5]
+    print(f"CASE adaptive-variable n={n} widths={widths}", flush=True)
+    prob = E.Problem(n, d, 0, 0.4)
+    res = uq.adaptive(prob, 8, budget=budget, max_level=3, tau_rel=tau, strategy="variable",
+                      opts=E.SolverOptions(rtol=rtol), widths=widths, iter_seconds=secs)
+    nodes = nodes_of(res.level, res.index)
+    start = 0
+    for rec in res.levels:
+        m = rec.n_samples
+        if rec.level == 1:
+            pred = np.ones(m)
+        else:
+            _, pred = sg.group_samples(nodes[:start], res.iters[:start].astype(float),
+                                       res.y[start:start + m], 1)
+        groups, _ = sg.group_variable(pred, widths, secs)
+        assert [list(g) for g in rec.groups] == groups
+        assert sorted(set(sum(groups, []))) == list(range(m))
+        for g, k in zip(rec.groups, rec.ens_iters):
+            assert k == int(rec.iters[np.asarray(g)].max())
+        start += m
+    for mi, nd in enumerate(nodes):
+        A, b, dg = oprob.assemble(sg.coords(nd), n, 0, 0.4)
+        x, it, _, _ = opcg.pcg(A, b, dg, rtol, 20000)
+        assert abs(int(res.iters[mi]) - it) <= 1
+        assert abs(res.qoi[mi] - float(x @ x)) <= 1e-9 * float(x @ x)

@@ -247,3 +247,77 @@ def test_mean_converges_to_the_integral_of_a_smooth_function():
         errs.append(abs(sg.expectation(sg.surpluses(g, v)) - exact))
     assert errs[-1] < 2e-5
     assert all(b < a / 3 for a, b in zip(errs, errs[1:]))
+
+
+# ------------------------------------------- ensembles of varying width
+def set_partitions(items):
+    if not items:
+        yield []
+        return
+    first, rest = items[0], items[1:]
+    for part in set_partitions(rest):
+        for k in range(len(part)):
+            yield part[:k] + [[first] + part[k]] + part[k + 1:]
+        yield [[first]] + part
+
+
+def brute_force_cost(pred, widths, ts):
+    # every partition of the samples into groups, each group at its cheapest
+    # width that holds it; no ordering assumed
+    best = math.inf
+    for part in set_partitions(list(range(len(pred)))):
+        tot = 0.0
+        for g in part:
+            fits = [t for w, t in zip(widths, ts) if w >= len(g)]
+            if not fits:
+                tot = math.inf
+                break
+            tot += min(fits) * max(max(pred[i] for i in g), 1.0)
+        best = min(best, tot)
+    return best
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_variable_groups_are_optimal_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    M = int(rng.integers(1, 8))
+    pred = rng.integers(0, 40, M).astype(float) if seed % 2 else rng.uniform(0.5, 30, M)
+    widths = sorted(rng.choice([1, 2, 4, 8], size=int(rng.integers(1, 4)), replace=False).tolist())
+    ts = rng.uniform(0.5, 3.0, len(widths))
+    groups, cost = sg.group_variable(pred, widths, ts)
+    assert cost == pytest.approx(brute_force_cost(pred, widths, ts), rel=1e-12)
+    # structure: consecutive in (pred, id) order, each padded to its width
+    order = sorted(range(M), key=lambda i: (pred[i], i))
+    real = [list(dict.fromkeys(g)) for g in groups]
+    assert sum(real, []) == order
+    recomputed = 0.0
+    for g, r in zip(groups, real):
+        w = len(g)
+        assert w in widths and 1 <= len(r) <= w and g == r + [r[-1]] * (w - len(r))
+        recomputed += ts[widths.index(w)] * max(max(pred[i] for i in r), 1.0)
+    assert recomputed == pytest.approx(cost, rel=1e-12)
+
+
+def test_variable_groups_without_ensemble_gain_are_single_solves():
+    # one iteration at width w costs w times one at width 1: no grouping pays
+    pred = np.random.default_rng(5).uniform(0, 100, 40)
+    widths = [1, 2, 4, 8, 16, 32, 64]
+    groups, cost = sg.group_variable(pred, widths, [0.25 * w for w in widths])
+    assert all(len(g) == 1 for g in groups)
+    assert cost == pytest.approx(0.25 * float(np.maximum(pred, 1.0).sum()), rel=1e-12)
+
+
+def test_variable_groups_with_perfect_gain_use_the_widest():
+    # every width costs the same per iteration and all predictions agree
+    groups, cost = sg.group_variable([7.0] * 150, [4, 16, 64], [2.0, 2.0, 2.0])
+    assert cost == 2.0 * 7.0 * 3 and len(groups) == 3
+
+
+def test_variable_groups_never_worse_than_fixed_width():
+    rng = np.random.default_rng(9)
+    its = rng.integers(50, 500, 77)
+    for S in (4, 8, 32):
+        groups, cost = sg.group_variable(its.astype(float), [S], [1.0])
+        fixed = sum(int(its[g].max()) for g in np.array(sg.group(list(its.astype(float)), S)))
+        assert cost <= fixed
+        assert len(groups) == -(-77 // S)
