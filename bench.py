@@ -487,6 +487,74 @@ def cheb_mode(args) -> int:
     return 0
 
 
+def fe3d_mode(args) -> int:
+    """The paper's 3-D test problem: 32^3 trilinear cells, d = 4 KL terms,
+    rtol 1e-7.  The level-2 sparse grid (41 nodes) is solved to build the
+    iteration surrogate, the 512 uniform samples (seed 5) are ordered by it
+    into ensembles of S and every ensemble is solved, with Jacobi and with
+    degree-4 Jacobi-Chebyshev; the first ensemble's samples are also solved
+    one at a time (S = 1).  At this size an ensemble's matrix (27 x 8 B per
+    member-row, 206 MB at S = 32) fits the 256 MB Infinity Cache, so the
+    product kernel's rate is partly a cache rate."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_1705_02003_amd import ensemble as E
+    from paper_1705_02003_amd import uq
+    torch.cuda.set_device(0)
+    w = workloads.FE3D_32
+    prob = E.Problem(w.n, w.d, dim=3)
+    ys = workloads.uniform_samples(w.seed, w.n_samples, w.d)
+    S = args.S
+    # bytes per member-row: direction kernel (r, diagonal, p_old, x in;
+    # p, x out) + product (27 matrix values, p in; q out) = 35 words; the
+    # update adds r, q, diagonal in and r out
+    step_bytes, iter_bytes = 35 * 8, 39 * 8
+    out = {"mode": "fe3d", "workload": w.name, "grid": f"{w.n + 1}^3 cells", "S": S,
+           "samples": w.n_samples, "rtol": w.rtol}
+    for pre in ("jacobi", "chebyshev"):
+        opts = E.SolverOptions(precond=pre, rtol=w.rtol, max_iter=w.max_iter, time_spmv=True)
+        uq.nonadaptive(prob, S, ys[:S], 1, opts, solve_groups=[0])       # warm-up
+        res = uq.nonadaptive(prob, S, ys, 2, opts)
+        its = res.iters
+        us = 1e3 * res.spmv_ms / max(1, res.spmv_launches)
+        rows = prob.rows * S
+        r = {"sample_solves_per_s": round(len(ys) / res.solve_seconds, 2),
+             "solve_seconds": round(res.solve_seconds, 3),
+             "iters": [int(its.min()), int(its.max())], "sum_ens_iters": int(sum(res.ens_iters)),
+             "R": round(S * sum(res.ens_iters) / float(its.sum()), 4),
+             "step_avg_us": round(us, 2),
+             "step_alg_GBs": round(rows * step_bytes / (us * 1e-6) / 1e9, 1)}
+        if pre == "jacobi":
+            r["iteration_alg_GBs"] = round(sum(res.ens_iters) * rows * iter_bytes
+                                           / res.solve_seconds / 1e9, 1)
+            # the first ensemble's samples one at a time
+            g0 = [int(i) for i in res.groups[0]]
+            ws1 = E.workspace(prob, 1, opts)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for i in g0:
+                V, b = E.assemble(prob, torch.tensor(ys[i:i + 1], dtype=torch.float64,
+                                                     device="cuda"))
+                E.solve(prob, V, b, opts, ws=ws1)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter() - t
+            wsS = E.workspace(prob, S, opts)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            V, b = E.assemble(prob, torch.tensor(ys[g0], dtype=torch.float64, device="cuda"))
+            E.solve(prob, V, b, opts, ws=wsS)
+            torch.cuda.synchronize()
+            tS = time.perf_counter() - t
+            r["first_ensemble_S1_seconds"] = round(t1, 4)
+            r["first_ensemble_S_seconds"] = round(tS, 4)
+            r["speedup_vs_S1"] = round(t1 / tS, 2)
+        out[pre] = r
+        print(json.dumps({pre: r}), flush=True)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def batch_mode(args) -> int:
     """64 ensembles, widths drawn from {4..64}, grids from {256, 512, 1024}^2,
     d = 8 coefficient model (seed 3), Jacobi-PCG rtol 1e-8, solved together by
@@ -559,7 +627,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-s1", action="store_true")
     ap.add_argument("--mode", choices=["full", "kernel", "adjoint", "cheb", "batch", "su", "grouping",
-                                       "table"],
+                                       "table", "fe3d"],
                     default="full",
                     help="kernel: a fixed-iteration solve of one ensemble plus a 1 GiB "
                          "copy, for hardware-counter runs")
@@ -593,6 +661,8 @@ def main() -> int:
         return grouping_mode(args)
     if args.mode == "table":
         return table_mode(args)
+    if args.mode == "fe3d":
+        return fe3d_mode(args)
 
     cpu = None
     if not args.no_cpu_baseline:

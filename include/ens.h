@@ -69,19 +69,37 @@ extern "C" {
 #define ENS_PRECOND_JACOBI 0
 #define ENS_PRECOND_CHEBYSHEV 1
 
-/* Problem descriptor: -div(a(x) K(y) grad u) = f on the unit square, u = 0 on
- * the boundary, discretised by the conservative nine-point scheme.
+/* Problem descriptor.
+ *
+ * dim = 0 or 2 (the 2-D model): -div(a(x) K(y) grad u) = f on the unit
+ * square, u = 0 on the boundary, discretised by the conservative nine-point
+ * scheme.
  *   K = R(theta) diag(1, eps) R(theta)^T,  theta = (pi/4)(1 + y1'),
  *   eps = 10^-(1 + y0')            (eps_model 0)
  *       = 10^-(1.5 + 1.5 y0')      (eps_model 1)
  *   a(x) = 1 + amp * sum_{k=1}^{d-2} y'_{k+1} sin(k pi x1) sin(k pi x2) / k^2
- * where y' = (y'_0 .. y'_{d-1}) is one member's parameter vector (0-based). */
+ * where y' = (y'_0 .. y'_{d-1}) is one member's parameter vector (0-based).
+ * N_r = n^2 rows, nine matrix slots (SW, S, SE, W, C, E, NW, N, NE).
+ *
+ * dim = 3 (the paper's test problem, Section 2.1, eqs. (elliptic-SPDE) and
+ * (diff-coeff), Section 4): -div(diag(a, a_y, a_z) grad u) = 1 on the unit
+ * cube, u = 0 on the boundary, trilinear finite elements on (n+1)^3 cubes,
+ *   a(x, y) = a_min + a_hat exp(sum_{k<d} sqrt(lambda_k) b_k(x) y'_k),
+ * (lambda_k, b_k) the d largest eigenpairs of the covariance
+ * sigma_0 exp(-|x - x'|_1 / delta), sigma_0 = sqrt(300), delta = 1/4, with
+ * a_min = 0.1, a_hat = 1, a_y = a_z = 1; a is taken at each cube's centre.
+ * The eigenpairs are products of 1-D ones (cos / sin about 1/2, frequencies
+ * from the exponential kernel's transcendental equations), ordered by
+ * decreasing lambda, ties by their 1-D mode indices (x, y, z).
+ * N_r = n^3 rows (x fastest), 27 matrix slots 9 (dz+1) + 3 (dy+1) + (dx+1)
+ * (13 = diagonal); eps_model and amp must be 0, 1 <= d <= 16.  The adjoint
+ * entry points and the batched solver take the 2-D model only. */
 typedef struct {
-  int32_t n;          /* interior points per dimension, n >= 2            */
-  int32_t d;          /* parameters per member, 2 <= d <= 16              */
-  int32_t eps_model;  /* 0 or 1                                            */
-  int32_t reserved;   /* must be 0                                         */
-  double amp;         /* amplitude of the a(x) modes (finite, |amp| < 1)  */
+  int32_t n;          /* interior points per dimension, 2 <= n            */
+  int32_t d;          /* parameters per member, 2 <= d <= 16 (3-D: 1..16) */
+  int32_t eps_model;  /* 0 or 1 (3-D: 0)                                   */
+  int32_t dim;        /* 0 or 2: the 2-D model; 3: the 3-D model          */
+  double amp;         /* amplitude of the a(x) modes (finite, |amp| < 1; 3-D: 0) */
 } ens_problem;
 
 /* Solver options.  Zero-initialise, then set what you need; fields left 0
@@ -126,9 +144,12 @@ typedef struct {
  * are sample independent and shared).  y_dev: [S][d] parameters (device).
  * Outputs V_dev [9][L] (A, with the 1/h^2 included; L the slot stride, the
  * padding is not written) and b_dev [N_r][S]
- * (f = 1).  Asynchronous on `stream`.
+ * (f = 1).  3-D model: V_dev [27][L], the finite-element stiffness matrix
+ * (each cube's matrix integrated exactly with a held at the cube's centre),
+ * b = h^3 (the load of f = 1).  Asynchronous on `stream`.
  * Errors: ENS_EINVAL for a NULL pointer, n < 2, d outside [2,16], eps_model
- * outside {0,1}, S not a power of two in [1,64], or non-finite amp.  The
+ * outside {0,1}, S not a power of two in [1,64], or non-finite amp (3-D: the
+ * limits of the descriptor above; n <= 1024).  The
  * parameter values themselves are read on the device; a non-finite y gives
  * non-finite matrix values for that member only (reject them on the host). */
 int ens_assemble_ensemble(const ens_problem* prob, int32_t S, const double* y_dev,
@@ -153,10 +174,11 @@ size_t ens_pcg_workspace_bytes(const ens_problem* prob, const ens_opts* opts, in
  * is replaced by zero and its x stops changing).  Each member follows the
  * Hestenes-Stiefel PCG recurrence; a member that has converged is frozen (its
  * x and r no longer change) while the others continue.  Preconditioner:
- * Jacobi (diagonal = slot 4 of V) or a Chebyshev polynomial in D^-1 A over
- * [lambda_max / cheb_ratio, lambda_max], lambda_max the member's Gershgorin
- * bound max_i sum_j |a_ij| / a_ii.
- * In:  V_dev [9][L] (symmetric positive definite per member),
+ * Jacobi (diagonal = slot 4 of V; 3-D: slot 13) or a Chebyshev polynomial in
+ * D^-1 A over [lambda_max / cheb_ratio, lambda_max], lambda_max the member's
+ * Gershgorin bound max_i sum_j |a_ij| / a_ii.  Both models; the 3-D model
+ * ignores tile_lines, member_tile and ENS_FLAG_FULL_STENCIL.
+ * In:  V_dev [9][L] (3-D: [27][L]; symmetric positive definite per member),
  *      b_dev [N_r][S].
  * Out: x_dev [N_r][S] (overwritten); iters_host[S], status_host[S],
  *      relres_host[S] (= ||r|| / ||b|| of the recurrence residual at exit, 0
@@ -172,13 +194,14 @@ int ens_pcg_solve(const ens_problem* prob, const ens_opts* opts, int32_t S,
 
 /* One ensemble matrix-vector product q = A p (the operation the solver's fused
  * kernel performs each iteration, without the fused updates).
- * In: V_dev [9][L], p_dev [N_r][S]; out: q_dev [N_r][S].  Asynchronous. */
+ * In: V_dev [9][L] (3-D: [27][L]), p_dev [N_r][S]; out: q_dev [N_r][S].
+ * Asynchronous. */
 int ens_spmv(const ens_problem* prob, int32_t S, const double* V_dev,
              const double* p_dev, double* q_dev, void* stream);
 
 /* Apply the Chebyshev preconditioner once: z = M^-1 r per member, with the
  * polynomial of ens_pcg_solve (degree opts->cheb_degree, ratio opts->cheb_ratio).
- * In: V_dev [9][L], r_dev [N_r][S]; out: z_dev [N_r][S]; lmax_host[S] (may be NULL)
+ * In: V_dev [9][L] (3-D: [27][L]), r_dev [N_r][S]; out: z_dev [N_r][S]; lmax_host[S] (may be NULL)
  * receives each member's Gershgorin bound.  Blocking (reads back lmax). */
 int ens_cheb_apply(const ens_problem* prob, const ens_opts* opts, int32_t S,
                    const double* V_dev, const double* r_dev, double* z_dev,
@@ -201,7 +224,7 @@ int ens_member_dot(int32_t N_r, int32_t S, const double* a_dev, const double* b_
  * In: y_dev [S][d], V_dev (assembled for y), u_dev [N_r][S] (forward
  * solution), w_dev [N_r] (shared QoI weights).  Out: lambda_dev [N_r][S],
  * grad_host [S][d], iters_host[S], status_host[S] of the adjoint solve.
- * Blocking. */
+ * 2-D model only (ENS_ENOTSUP for dim = 3).  Blocking. */
 int ens_adjoint_grad(const ens_problem* prob, const ens_opts* opts, int32_t S,
                      const double* y_dev, const double* V_dev, const double* u_dev,
                      const double* w_dev, double* lambda_dev, double* grad_host,
@@ -209,7 +232,7 @@ int ens_adjoint_grad(const ens_problem* prob, const ens_opts* opts, int32_t S,
                      void* ws_dev, size_t ws_bytes, void* stream);
 
 /* The dQ/dy kernel alone: grad_host[s][j] = -lambda_s^T (dA_s/dy_j) u_s for
- * given u and lambda.  Blocking. */
+ * given u and lambda.  2-D model only (ENS_ENOTSUP for dim = 3).  Blocking. */
 int ens_dqdy(const ens_problem* prob, int32_t S, const double* y_dev,
              const double* u_dev, const double* lambda_dev, double* grad_host,
              void* ws_dev, size_t ws_bytes, void* stream);
@@ -248,7 +271,8 @@ size_t ens_batch_workspace_bytes(int32_t n_items);
  * each ensemble here still runs max over its members iterations (eqs. (Rl),
  * (R)).  opts: Jacobi only (ENS_ENOTSUP otherwise); max_groups sets the grid
  * of the strided kernels (default 512, a multiple of 8).  Blocking.
- * Errors: ENS_EINVAL (bad item), ENS_ENOMEM (a workspace too small). */
+ * Errors: ENS_EINVAL (bad item), ENS_ENOMEM (a workspace too small),
+ * ENS_ENOTSUP (an item of the 3-D model). */
 int ens_batch_solve(const ens_opts* opts, int32_t n_items, ens_batch_item* items,
                     void* batch_ws, size_t batch_ws_bytes, void* stream);
 

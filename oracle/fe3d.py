@@ -1,0 +1,175 @@
+"""3-D model problem of the paper's numerical tests: trilinear finite elements.
+
+Paper, Section 2.1, eqs. (elliptic-SPDE) and (diff-coeff): on D = [0, 1]^3,
+-div(A(x, y) grad u) = f with u = 0 on the boundary and the anisotropic
+diffusivity A = diag(a(x, y), a_y, a_z),
+
+  a(x, y) = a_min + a_hat exp( sum_{n=1}^N sqrt(lambda_n) b_n(x) y_n ),
+
+where (lambda_n, b_n) are the N largest eigenpairs of the covariance
+cov(x, x') = sigma_0 exp(-||x - x'||_1 / delta).  Section 4: sigma_0 =
+sqrt(300), delta = 1/4, 32^3 cells, trilinear elements, N = 4.
+
+Readings (the paper leaves them open):
+  * a_min = 0.1, a_hat = 1, a_y = a_z = 1;
+  * a is evaluated at each element's centroid and held constant on the
+    element; the element matrices are then integrated exactly;
+  * f = 1 (the load vector entry of an interior node is h^3);
+  * the L1-norm covariance is a product of 1-D kernels exp(-|s - t| / delta),
+    so its eigenpairs are products of 1-D ones; the 1-D pairs on [0, 1] are
+    the classical closed forms for the exponential kernel (even: cos, odd:
+    sin about the midpoint, frequencies from transcendental equations); the
+    3-D terms are ordered by decreasing eigenvalue, ties by the 1-D mode
+    indices (x, y, z) lexicographically, with each product formed over the
+    three factors in ascending 1-D mode order so that ties are exact.
+
+Unknowns: the m^3 interior nodes of the (m + 1)^3-cell mesh, h = 1 / (m + 1),
+row r = (k m + j) m + i for node (i + 1, j + 1, k + 1), x fastest.  Stencil
+slot of the neighbour at offset (di, dj, dk): 9 (dk + 1) + 3 (dj + 1) +
+(di + 1), so 13 is the diagonal and slot order is column order.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+from typing import List, Tuple
+
+import numpy as np
+import scipy.sparse as sp
+from scipy.optimize import brentq
+
+SIGMA0 = math.sqrt(300.0)
+DELTA = 0.25
+A_MIN, A_HAT, A_Y, A_Z = 0.1, 1.0, 1.0, 1.0
+CENTER = 13
+SLOT_OFFSETS = [(di, dj, dk) for dk in (-1, 0, 1) for dj in (-1, 0, 1) for di in (-1, 0, 1)]
+
+
+# ------------------------------------------------------------ KL modes
+def kl_1d(count: int, delta: float = DELTA) -> List[Tuple[int, float, float, float]]:
+    """The `count` largest eigenpairs of k(s, t) = exp(-|s - t| / delta) on
+    [0, 1] as (kind, omega, lambda, norm): kind 0 is cos(omega (s - 1/2)),
+    kind 1 is sin(omega (s - 1/2)), each times norm (unit L2 norm), with
+    lambda = 2c / (omega^2 + c^2), c = 1 / delta.  With half-length a = 1/2 the
+    even frequencies solve c cos(omega a) = omega sin(omega a) on
+    (j pi, j pi + pi/2) / a and the odd ones solve omega cos(omega a) +
+    c sin(omega a) = 0 on (j pi + pi/2, (j + 1) pi) / a."""
+    c, a = 1.0 / delta, 0.5
+    out = []
+    for j in range(count):
+        lo, hi = j * math.pi / a, (j * math.pi + math.pi / 2) / a
+        w = brentq(lambda w: c * math.cos(w * a) - w * math.sin(w * a), lo + 1e-12, hi - 1e-12,
+                   xtol=1e-15, rtol=4 * np.finfo(float).eps, maxiter=500)
+        out.append((0, w, 2 * c / (w * w + c * c), 1.0 / math.sqrt(a + math.sin(2 * w * a) / (2 * w))))
+        lo, hi = (j * math.pi + math.pi / 2) / a, (j + 1) * math.pi / a
+        w = brentq(lambda w: w * math.cos(w * a) + c * math.sin(w * a), lo + 1e-12, hi - 1e-12,
+                   xtol=1e-15, rtol=4 * np.finfo(float).eps, maxiter=500)
+        out.append((1, w, 2 * c / (w * w + c * c), 1.0 / math.sqrt(a - math.sin(2 * w * a) / (2 * w))))
+    out.sort(key=lambda t: -t[2])
+    return out[:count]
+
+
+def phi_1d(mode, s):
+    kind, w, _, norm = mode
+    return norm * (np.cos(w * (s - 0.5)) if kind == 0 else np.sin(w * (s - 0.5)))
+
+
+def kl_3d(N: int):
+    """The N largest 3-D terms: (sqrt(lambda), (p, q, r)) with
+    lambda = sigma_0 lambda_p lambda_q lambda_r."""
+    K = 8
+    m1 = kl_1d(K)
+    terms = []
+    for p, q, r in itertools.product(range(K), repeat=3):
+        a_, b_, c_ = sorted((p, q, r))
+        lam = SIGMA0 * (m1[a_][2] * m1[b_][2] * m1[c_][2])
+        terms.append((lam, (p, q, r)))
+    terms.sort(key=lambda t: (-t[0], t[1]))
+    return [(math.sqrt(lam), idx) for lam, idx in terms[:N]], m1
+
+
+def element_coefficients(y, m: int) -> np.ndarray:
+    """a at the centroid of every cell, shape (m+1, m+1, m+1) indexed [ez, ey, ex]."""
+    y = np.asarray(y, dtype=np.float64)
+    terms, m1 = kl_3d(len(y))
+    h = 1.0 / (m + 1)
+    xc = (np.arange(m + 1) + 0.5) * h
+    g = np.zeros((m + 1, m + 1, m + 1))
+    for (sq, (p, q, r)), yn in zip(terms, y):
+        bx, by, bz = phi_1d(m1[p], xc), phi_1d(m1[q], xc), phi_1d(m1[r], xc)
+        g = g + sq * yn * (bz[:, None, None] * by[None, :, None] * bx[None, None, :])
+    return A_MIN + A_HAT * np.exp(g)
+
+
+# ------------------------------------------------------------ assembly
+def element_matrix(ae: float, ay: float, az: float, h: float) -> np.ndarray:
+    """8 x 8 stiffness of diag(ae, ay, az) on one cube cell, exact: with the
+    1-D linear-element stiffness K1 = [[1, -1], [-1, 1]] / h and mass
+    M1 = [[2, 1], [1, 2]] h / 6, the cell matrix is
+    ae Kx My Mz + ay Mx Ky Mz + az Mx My Kz (tensor products).  Local node
+    (lx, ly, lz) in {0, 1}^3 has index lx + 2 ly + 4 lz."""
+    K1 = np.array([[1.0, -1.0], [-1.0, 1.0]]) / h
+    M1 = np.array([[2.0, 1.0], [1.0, 2.0]]) * h / 6.0
+    Ke = np.zeros((8, 8))
+    for a_, b_ in itertools.product(range(8), repeat=2):
+        ax, ay_, az_ = a_ & 1, (a_ >> 1) & 1, a_ >> 2
+        bx, by, bz = b_ & 1, (b_ >> 1) & 1, b_ >> 2
+        Ke[a_, b_] = (ae * K1[ax, bx] * M1[ay_, by] * M1[az_, bz]
+                      + ay * M1[ax, bx] * K1[ay_, by] * M1[az_, bz]
+                      + az * M1[ax, bx] * M1[ay_, by] * K1[az_, bz])
+    return Ke
+
+
+def assemble_from_cells(acell: np.ndarray, m: int, ay: float = A_Y, az: float = A_Z):
+    """Global matrix (CSR, interior nodes only) from per-cell a values
+    acell[ez, ey, ex]: every cell adds its matrix, cells taken in (ez, ey, ex)
+    order with ex fastest, each entry summed in that order (so A[i, j] and
+    A[j, i] are the same sum); rows and columns of boundary nodes are dropped
+    (zero Dirichlet data)."""
+    h = 1.0 / (m + 1)
+    acc = {}
+
+    def idx(i, j, k):   # mesh node -> unknown index, or -1 on the boundary
+        if 1 <= i <= m and 1 <= j <= m and 1 <= k <= m:
+            return ((k - 1) * m + (j - 1)) * m + (i - 1)
+        return -1
+
+    for ez, ey, ex in itertools.product(range(m + 1), repeat=3):
+        Ke = element_matrix(acell[ez, ey, ex], ay, az, h)
+        ids = [idx(ex + (l & 1), ey + ((l >> 1) & 1), ez + (l >> 2)) for l in range(8)]
+        for a_, b_ in itertools.product(range(8), repeat=2):
+            if ids[a_] >= 0 and ids[b_] >= 0:
+                key = (ids[a_], ids[b_])
+                acc[key] = acc[key] + float(Ke[a_, b_]) if key in acc else float(Ke[a_, b_])
+    N = m ** 3
+    rows = np.array([k[0] for k in acc], dtype=np.int64)
+    cols = np.array([k[1] for k in acc], dtype=np.int64)
+    vals = np.array(list(acc.values()))
+    return sp.csr_matrix((vals, (rows, cols)), shape=(N, N))
+
+
+def rhs(m: int) -> np.ndarray:
+    """Load vector of f = 1: each interior hat integrates to h^3."""
+    h = 1.0 / (m + 1)
+    return np.full(m ** 3, h ** 3)
+
+
+def assemble(y, m: int):
+    """(A as CSR, b, diag(A)) for one sample."""
+    A = assemble_from_cells(element_coefficients(y, m), m)
+    return A, rhs(m), A.diagonal().copy()
+
+
+def slot_values(A, m: int) -> np.ndarray:
+    """The 27 stencil values of every row, [27][m^3] (0 where the neighbour
+    is outside the grid)."""
+    N = m ** 3
+    out = np.zeros((27, N))
+    C = A.tocoo()
+    r, c = C.row, C.col
+    di = c % m - r % m
+    dj = (c // m) % m - (r // m) % m
+    dk = c // (m * m) - r // (m * m)
+    assert np.all(np.abs(di) <= 1) and np.all(np.abs(dj) <= 1) and np.all(np.abs(dk) <= 1)
+    out[9 * (dk + 1) + 3 * (dj + 1) + (di + 1), r] = C.data
+    return out

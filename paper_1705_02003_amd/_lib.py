@@ -26,7 +26,7 @@ sz = C.c_size_t
 
 
 class ens_problem(C.Structure):
-    _fields_ = [("n", i32), ("d", i32), ("eps_model", i32), ("reserved", i32), ("amp", f64)]
+    _fields_ = [("n", i32), ("d", i32), ("eps_model", i32), ("dim", i32), ("amp", f64)]
 
 
 class ens_opts(C.Structure):

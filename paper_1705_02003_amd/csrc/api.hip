@@ -42,13 +42,13 @@ static size_t header_bytes() {
 static int n_vectors(bool cheb) { return cheb ? 8 : 5; }
 
 // bytes from one workspace vector to the next (see slot_stride)
-static size_t vector_bytes(int n, int S) { return sizeof(double) * slot_stride((size_t)n * n * S); }
+static size_t vector_bytes(size_t nr, int S) { return sizeof(double) * slot_stride(nr * S); }
 
-size_t workspace_bytes(int n, int S, bool cheb) {
-  return header_bytes() + vector_bytes(n, S) * n_vectors(cheb);
+size_t workspace_bytes(size_t nr, int S, bool cheb) {
+  return header_bytes() + vector_bytes(nr, S) * n_vectors(cheb);
 }
 
-Workspace carve_workspace(void* base, int n, int S, bool cheb) {
+Workspace carve_workspace(void* base, size_t nr, int S, bool cheb) {
   Workspace w;
   std::memset(&w, 0, sizeof(w));
   char* p = static_cast<char*>(base);
@@ -74,8 +74,8 @@ Workspace carve_workspace(void* base, int n, int S, bool cheb) {
   w.m.status = ii + 2 * kMaxS;
   w.m.ctl = reinterpret_cast<int*>(p);
   p += align256(sizeof(int) * CTL_COUNT);
-  if (n > 0) {
-    const size_t vec = vector_bytes(n, S);
+  if (nr > 0) {
+    const size_t vec = vector_bytes(nr, S);
     double** slots[8] = {&w.p[0], &w.p[1], &w.q, &w.r, &w.aux, &w.z[0], &w.z[1], &w.d};
     for (int k = 0; k < n_vectors(cheb); ++k) {
       *slots[k] = reinterpret_cast<double*>(p);
@@ -119,6 +119,34 @@ Geometry make_geometry(int n, int S, int tile_lines, int max_groups, int member_
   g.nelem = g.nr * S;
   g.vstride = slot_stride(g.nelem);
   g.full = 0;
+  g.dim = 2;
+  g.nslot = 9;
+  g.cslot = 4;
+  return g;
+}
+
+// 3-D model: no tiles; the product kernel strides over points, kNT / tpp
+// points per workgroup and pass, with at most 1024 workgroups.
+Geometry make_geometry3(int m, int S) {
+  Geometry g;
+  std::memset(&g, 0, sizeof(g));
+  g.n = m;
+  g.S = S;
+  g.logS = log2i(S);
+  g.vec = (S >= 2) ? 2 : 1;
+  g.tpp = S / g.vec;
+  g.sw = S;
+  g.nstile = 1;
+  g.stpp = g.tpp;
+  g.nr = (size_t)m * m * m;
+  g.nelem = g.nr * S;
+  g.vstride = slot_stride(g.nelem);
+  g.full = 1;
+  g.dim = 3;
+  g.nslot = 27;
+  g.cslot = 13;
+  const size_t ppb = (size_t)(kNT / g.tpp);
+  g.groups = (int)std::min<size_t>((g.nr + ppb - 1) / ppb, 1024);
   return g;
 }
 
@@ -128,14 +156,27 @@ int init_groups(const Geometry& g) {
   return (int)std::min<size_t>(need, 512);
 }
 
+static bool is3d(const ens_problem* p) { return p->dim == 3; }
+
 static int check_problem(const ens_problem* p) {
   if (!p) return ENS_EINVAL;
+  if (is3d(p)) {
+    if (p->n < 2 || p->n > 1024) return ENS_EINVAL;
+    if (p->d < 1 || p->d > kMaxTerms) return ENS_EINVAL;
+    if (p->eps_model != 0 || p->amp != 0.0) return ENS_EINVAL;
+    return ENS_OK;
+  }
+  if (p->dim != 0 && p->dim != 2) return ENS_EINVAL;
   if (p->n < 2 || p->n > 16384) return ENS_EINVAL;
   if (p->d < 2 || p->d > 16) return ENS_EINVAL;
   if (p->eps_model != 0 && p->eps_model != 1) return ENS_EINVAL;
-  if (p->reserved != 0) return ENS_EINVAL;
   if (!std::isfinite(p->amp) || std::fabs(p->amp) >= 1.0) return ENS_EINVAL;
   return ENS_OK;
+}
+
+static size_t rows_of(const ens_problem* p) {
+  const size_t n = (size_t)p->n;
+  return is3d(p) ? n * n * n : n * n;
 }
 
 struct Opts {
@@ -213,6 +254,13 @@ static double* cheb_apply(const double* V, const Workspace& w, const Geometry& g
   return w.z[(degree - 1) & 1];
 }
 
+static Geometry geometry_for(const ens_problem* prob, const Opts& o, int S) {
+  if (is3d(prob)) return make_geometry3(prob->n, S);
+  Geometry g = make_geometry(prob->n, S, o.tile_lines, o.max_groups, o.member_tile);
+  g.full = (o.flags & ENS_FLAG_FULL_STENCIL) ? 1 : 0;
+  return g;
+}
+
 struct SolveOut {
   int32_t* iters;
   int32_t* status;
@@ -223,10 +271,8 @@ struct SolveOut {
 
 static int run_solve(const ens_problem* prob, const Opts& o, int S, const double* V, const double* b,
                      int b_bcast, double* x, const Workspace& w, hipStream_t s, SolveOut out) {
-  const int n = prob->n;
   const bool cheb = (o.precond == ENS_PRECOND_CHEBYSHEV);
-  Geometry g = make_geometry(n, S, o.tile_lines, o.max_groups, o.member_tile);
-  g.full = (o.flags & ENS_FLAG_FULL_STENCIL) ? 1 : 0;
+  const Geometry g = geometry_for(prob, o, S);
   const int ge = init_groups(g);
 
   HIPCHECK(hipMemsetAsync(w.m.ctl, 0, sizeof(int) * CTL_COUNT, s));
@@ -419,6 +465,24 @@ int ens_assemble_ensemble(const ens_problem* prob, int32_t S, const double* y_de
   int rc = check_problem(prob);
   if (rc) return rc;
   if (!valid_S(S) || !y_dev || !V_dev || !b_dev) return ENS_EINVAL;
+  if (is3d(prob)) {
+    Fe3dAsmArgs f;
+    std::memset(&f, 0, sizeof(f));
+    rc = fe3d_setup(prob, f);
+    if (rc) return rc;
+    f.y = y_dev;
+    f.V = V_dev;
+    f.b = b_dev;
+    f.m = prob->n;
+    f.S = S;
+    f.logS = log2i(S);
+    f.d = prob->d;
+    f.nelem = rows_of(prob) * S;
+    f.vstride = slot_stride(f.nelem);
+    launch_fe3d_assemble(f, (hipStream_t)stream);
+    HIPCHECK(hipGetLastError());
+    return ENS_OK;
+  }
   AsmArgs a;
   a.y = y_dev;
   a.V = V_dev;
@@ -438,13 +502,13 @@ int ens_assemble_ensemble(const ens_problem* prob, int32_t S, const double* y_de
 
 size_t ens_matrix_slot_stride(const ens_problem* prob, int32_t S) {
   if (check_problem(prob) || !valid_S(S)) return 0;
-  return slot_stride((size_t)prob->n * prob->n * S);
+  return slot_stride(rows_of(prob) * S);
 }
 
 size_t ens_pcg_workspace_bytes(const ens_problem* prob, const ens_opts* opts, int32_t S) {
   Opts o;
   if (check_problem(prob) || resolve_opts(opts, o) || !valid_S(S)) return 0;
-  return workspace_bytes(prob->n, S, o.precond == ENS_PRECOND_CHEBYSHEV);
+  return workspace_bytes(rows_of(prob), S, o.precond == ENS_PRECOND_CHEBYSHEV);
 }
 
 int ens_pcg_solve(const ens_problem* prob, const ens_opts* opts, int32_t S, const double* V_dev,
@@ -458,8 +522,8 @@ int ens_pcg_solve(const ens_problem* prob, const ens_opts* opts, int32_t S, cons
   if (rc) return rc;
   if (!valid_S(S) || !V_dev || !b_dev || !x_dev || !ws_dev) return ENS_EINVAL;
   const bool cheb = o.precond == ENS_PRECOND_CHEBYSHEV;
-  if (ws_bytes < workspace_bytes(prob->n, S, cheb)) return ENS_ENOMEM;
-  const Workspace w = carve_workspace(ws_dev, prob->n, S, cheb);
+  if (ws_bytes < workspace_bytes(rows_of(prob), S, cheb)) return ENS_ENOMEM;
+  const Workspace w = carve_workspace(ws_dev, rows_of(prob), S, cheb);
   SolveOut out{iters_host, status_host, relres_host, ens_iters_host, stats};
   return run_solve(prob, o, S, V_dev, b_dev, 0, x_dev, w, (hipStream_t)stream, out);
 }
@@ -474,8 +538,12 @@ int ens_spmv(const ens_problem* prob, int32_t S, const double* V_dev, const doub
   a.V = V_dev;
   a.src = p_dev;
   a.q = q_dev;
-  a.g = make_geometry(prob->n, S, 0, 0);
-  a.g.full = 1;   // any stored matrix, symmetric or not
+  if (is3d(prob)) {
+    a.g = make_geometry3(prob->n, S);
+  } else {
+    a.g = make_geometry(prob->n, S, 0, 0);
+    a.g.full = 1;   // any stored matrix, symmetric or not
+  }
   launch_stencil<M_SPMV>(a, (hipStream_t)stream);
   HIPCHECK(hipGetLastError());
   return ENS_OK;
@@ -490,10 +558,9 @@ int ens_cheb_apply(const ens_problem* prob, const ens_opts* opts, int32_t S, con
   rc = resolve_opts(opts, o);
   if (rc) return rc;
   if (!valid_S(S) || !V_dev || !r_dev || !z_dev || !ws_dev) return ENS_EINVAL;
-  if (ws_bytes < workspace_bytes(prob->n, S, true)) return ENS_ENOMEM;
-  const Workspace w = carve_workspace(ws_dev, prob->n, S, true);
-  Geometry g = make_geometry(prob->n, S, o.tile_lines, o.max_groups, o.member_tile);
-  g.full = (o.flags & ENS_FLAG_FULL_STENCIL) ? 1 : 0;
+  if (ws_bytes < workspace_bytes(rows_of(prob), S, true)) return ENS_ENOMEM;
+  const Workspace w = carve_workspace(ws_dev, rows_of(prob), S, true);
+  const Geometry g = geometry_for(prob, o, S);
   hipStream_t s = (hipStream_t)stream;
   HIPCHECK(hipMemsetAsync(w.m.ctl, 0, sizeof(int) * CTL_COUNT, s));
   InitArgs ia;
@@ -576,6 +643,7 @@ int ens_dqdy(const ens_problem* prob, int32_t S, const double* y_dev, const doub
   int rc = check_problem(prob);
   if (rc) return rc;
   if (!valid_S(S) || !y_dev || !u_dev || !lambda_dev || !grad_host || !ws_dev) return ENS_EINVAL;
+  if (is3d(prob)) return ENS_ENOTSUP;
   if (ws_bytes < header_bytes()) return ENS_ENOMEM;
   const Workspace w = carve_workspace(ws_dev, 0, S, false);
   const Geometry g = make_geometry(prob->n, S, 0, 0);
@@ -627,9 +695,10 @@ int ens_adjoint_grad(const ens_problem* prob, const ens_opts* opts, int32_t S, c
   if (rc) return rc;
   if (!valid_S(S) || !y_dev || !V_dev || !u_dev || !w_dev || !lambda_dev || !grad_host || !ws_dev)
     return ENS_EINVAL;
+  if (is3d(prob)) return ENS_ENOTSUP;
   const bool cheb = o.precond == ENS_PRECOND_CHEBYSHEV;
-  if (ws_bytes < workspace_bytes(prob->n, S, cheb)) return ENS_ENOMEM;
-  const Workspace w = carve_workspace(ws_dev, prob->n, S, cheb);
+  if (ws_bytes < workspace_bytes(rows_of(prob), S, cheb)) return ENS_ENOMEM;
+  const Workspace w = carve_workspace(ws_dev, rows_of(prob), S, cheb);
   SolveOut out{iters_host, status_host, nullptr, nullptr, nullptr};
   rc = run_solve(prob, o, S, V_dev, w_dev, 1, lambda_dev, w, (hipStream_t)stream, out);
   if (rc) return rc;

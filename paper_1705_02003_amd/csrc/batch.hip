@@ -403,10 +403,12 @@ int ens_batch_solve(const ens_opts* opts, int32_t n_items, ens_batch_item* items
   for (int k = 0; k < n_items; ++k) {
     const ens_batch_item& it = items[k];
     const int S = it.S;
+    if (it.prob.dim == 3) return ENS_ENOTSUP;
     if (it.prob.n < 2 || it.prob.n > 16384 || S < 2 || !valid_S(S)) return ENS_EINVAL;
     if (!it.V_dev || !it.b_dev || !it.x_dev || !it.ws_dev || it.tile_lines < 0) return ENS_EINVAL;
     if (it.member_tile < 0 || (it.member_tile & (it.member_tile - 1)) != 0) return ENS_EINVAL;
-    if (it.ws_bytes < workspace_bytes(it.prob.n, S, false)) return ENS_ENOMEM;
+    const size_t nr = (size_t)it.prob.n * it.prob.n;
+    if (it.ws_bytes < workspace_bytes(nr, S, false)) return ENS_ENOMEM;
   }
   hipStream_t s = (hipStream_t)stream;
   const BatchLayout lay = batch_layout(batch_ws, n_items);
@@ -422,7 +424,7 @@ int ens_batch_solve(const ens_opts* opts, int32_t n_items, ens_batch_item* items
     geo[k] = g;
     char* base = static_cast<char*>(it.ws_dev);
     // same carve as ens_pcg_solve (Jacobi layout)
-    Workspace w = carve_workspace(base, it.prob.n, it.S, false);
+    Workspace w = carve_workspace(base, (size_t)it.prob.n * it.prob.n, it.S, false);
     hipError_t he = hipMemsetAsync(w.m.ctl, 0, sizeof(int) * CTL_COUNT, s);
     if (he != hipSuccess) return hip_fail(he);
     InitArgs ia;

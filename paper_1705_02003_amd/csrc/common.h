@@ -67,6 +67,8 @@ struct Geometry {
   size_t nr, nelem;          // rows, rows * S
   size_t vstride;            // elements from one matrix slot to the next (slot_stride)
   int full;                  // 1: the sweep reads all nine matrix values per row
+  int dim;                   // 2: nine-point grid n x n; 3: 27-point grid n x n x n
+  int nslot, cslot;          // matrix slots per row and the diagonal's slot
 };
 
 
@@ -81,6 +83,25 @@ struct AsmArgs {
 };
 
 enum Mode { M_SPMV = 0, M_PCG_J = 1, M_PCG_Z = 2, M_CHEB = 3 };
+
+// 3-D model: one term of the log-diffusivity expansion, a product of three
+// 1-D covariance eigenfunctions (kind 0: norm cos(w (s - 1/2)), kind 1:
+// norm sin(w (s - 1/2))) scaled by sqrt(lambda)
+constexpr int kMaxTerms = 16;
+struct Fe3dTerm {
+  double w[3], norm[3];
+  int kind[3];
+  double sq;
+};
+
+struct Fe3dAsmArgs {
+  const double* y;  // [S][d]
+  double* V;        // [27][vstride], slot k holds [N_r][S]
+  double* b;        // [N_r][S]
+  int m, S, logS, d;
+  size_t nelem, vstride;
+  Fe3dTerm term[kMaxTerms];
+};
 
 struct StencilArgs {
   const double* V;
@@ -172,10 +193,18 @@ void launch_dot(const double* x, const double* y, int y_bcast, double* partial, 
 void launch_finish(const FinishArgs& a, hipStream_t s);
 void launch_dqdy(const DqdyArgs& a, int groups, hipStream_t s);
 
-size_t workspace_bytes(int n, int S, bool cheb);
-Workspace carve_workspace(void* base, int n, int S, bool cheb);
+size_t workspace_bytes(size_t nr, int S, bool cheb);
+Workspace carve_workspace(void* base, size_t nr, int S, bool cheb);
 int init_groups(const Geometry& g);   // workgroups of the element-wise kernels
 Geometry make_geometry(int n, int S, int tile_lines, int max_groups, int member_tile = 0);
+Geometry make_geometry3(int m, int S);
+
+// 3-D model (fe3d.hip): assembly, and the stencil step of every mode for
+// dim = 3 geometries (launch_stencil forwards to it)
+int fe3d_setup(const ens_problem* p, Fe3dAsmArgs& a);
+void launch_fe3d_assemble(const Fe3dAsmArgs& a, hipStream_t s);
+template <int MODE>
+void launch_fe3d(const StencilArgs& a, hipStream_t s);
 // Elements from the start of one matrix slot (or workspace vector) to the
 // next: the slot's N_r * S elements plus 4 KiB.  Arrays that stream together
 // must not sit a large power of two apart: at 2^28 bytes eleven such streams

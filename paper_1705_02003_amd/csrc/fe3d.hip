@@ -1,0 +1,323 @@
+// The 3-D model of the paper's numerical tests (Section 2.1, eqs.
+// (elliptic-SPDE) and (diff-coeff); Section 4): -div(diag(a, a_y, a_z) grad u)
+// = 1 on the unit cube, u = 0 on the boundary, trilinear finite elements on a
+// uniform mesh of (m+1)^3 cubes, a log-normal diffusivity
+//   a(x, y) = a_min + a_hat exp(sum_k sqrt(lambda_k) b_k(x) y_k)
+// built from the eigenpairs of the covariance sigma_0 exp(-|x - x'|_1 / delta).
+//
+// Host: the covariance eigenpairs.  The kernel is a product of three 1-D
+// kernels exp(-|s - t| / delta), whose eigenpairs on [0, 1] are the classical
+// closed forms: cos(w (s - 1/2)) with c cos(w/2) = w sin(w/2) and
+// sin(w (s - 1/2)) with w cos(w/2) + c sin(w/2) = 0, c = 1/delta, eigenvalue
+// 2c / (w^2 + c^2); the frequencies are found by bisection.
+//
+// Device: ensemble assembly of the 27-point matrix (member innermost, as in
+// the 2-D model), and one solver step of every mode:
+//   M_PCG_*: a direction kernel (p = D^-1 r + beta p_old or z + beta p_old,
+//            and the deferred x += alpha_prev p_old), then the product
+//            q = A p with the partial sums of p^T q;
+//   M_SPMV:  q = A p;
+//   M_CHEB:  one Chebyshev step d = c1 d + c2 D^-1 (r - A z), z_out = z + d,
+//            on the last step with the partial sums of r^T z_out.
+// The neighbours' values of the product come through the caches (a point's
+// 27 neighbours lie on three planes of the grid, all near in memory); the 27
+// matrix values are streamed.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "device.h"
+
+namespace ens {
+
+namespace {
+
+constexpr double kDelta = 0.25;
+constexpr double kAmin = 0.1, kAhat = 1.0, kAy = 1.0, kAz = 1.0;
+constexpr int kModes1d = 8;   // 1-D modes from which the 3-D products are drawn
+
+struct Mode1 {
+  int kind;
+  double w, lam, norm;
+};
+
+// the root in [lo, hi] of a function that changes sign there, to the last bit
+template <class F>
+double bisect(F f, double lo, double hi) {
+  const bool neg_lo = f(lo) < 0.0;
+  for (int it = 0; it < 2000; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if ((f(mid) < 0.0) == neg_lo) lo = mid;
+    else hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+std::vector<Mode1> kl_1d(int count) {
+  const double c = 1.0 / kDelta, a = 0.5, pi = M_PI;
+  std::vector<Mode1> out;
+  for (int j = 0; j < count; ++j) {
+    double w = bisect([&](double v) { return c * std::cos(v * a) - v * std::sin(v * a); },
+                      j * pi / a + 1e-12, (j * pi + pi / 2) / a - 1e-12);
+    out.push_back({0, w, 2 * c / (w * w + c * c), 1.0 / std::sqrt(a + std::sin(2 * w * a) / (2 * w))});
+    w = bisect([&](double v) { return v * std::cos(v * a) + c * std::sin(v * a); },
+               (j * pi + pi / 2) / a + 1e-12, (j + 1) * pi / a - 1e-12);
+    out.push_back({1, w, 2 * c / (w * w + c * c), 1.0 / std::sqrt(a - std::sin(2 * w * a) / (2 * w))});
+  }
+  std::stable_sort(out.begin(), out.end(), [](const Mode1& x, const Mode1& y) { return x.lam > y.lam; });
+  out.resize(count);
+  return out;
+}
+
+__device__ __forceinline__ double phi1(int kind, double w, double norm, double s) {
+  const double u = w * (s - 0.5);
+  return norm * (kind == 0 ? cos(u) : sin(u));
+}
+
+}  // namespace
+
+int fe3d_setup(const ens_problem* p, Fe3dAsmArgs& a) {
+  if (p->d < 1 || p->d > kMaxTerms) return ENS_EINVAL;
+  const std::vector<Mode1> m1 = kl_1d(kModes1d);
+  struct T {
+    double lam;
+    int idx[3];
+  };
+  std::vector<T> t;
+  const double sigma0 = std::sqrt(300.0);
+  for (int x = 0; x < kModes1d; ++x)
+    for (int y = 0; y < kModes1d; ++y)
+      for (int z = 0; z < kModes1d; ++z) {
+        int s3[3] = {x, y, z};
+        std::sort(s3, s3 + 3);   // the same product for every permutation
+        t.push_back({sigma0 * (m1[s3[0]].lam * m1[s3[1]].lam * m1[s3[2]].lam), {x, y, z}});
+      }
+  // enumeration order is (x, y, z) lexicographic: a stable sort keeps it for ties
+  std::stable_sort(t.begin(), t.end(), [](const T& u, const T& v) { return u.lam > v.lam; });
+  for (int k = 0; k < p->d; ++k) {
+    Fe3dTerm& f = a.term[k];
+    for (int q = 0; q < 3; ++q) {
+      const Mode1& md = m1[t[k].idx[q]];
+      f.w[q] = md.w;
+      f.norm[q] = md.norm;
+      f.kind[q] = md.kind;
+    }
+    f.sq = std::sqrt(t[k].lam);
+  }
+  return ENS_OK;
+}
+
+// ------------------------------------------------------------ assembly
+// One thread per (row, member).  The cube matrices follow from the 1-D
+// linear-element stiffness K1 = [[1, -1], [-1, 1]] / h and mass
+// M1 = [[2, 1], [1, 2]] h / 6: a cube with coefficient a_c adds
+// a_c Kx My Mz + a_y Mx Ky Mz + a_z Mx My Kz between two of its nodes; the
+// value of slot (di, dj, dk) sums the cubes holding both nodes.
+__global__ __launch_bounds__(kNT) void fe3d_assemble_kernel(Fe3dAsmArgs a) {
+#pragma clang fp contract(off)
+  const size_t e = (size_t)blockIdx.x * kNT + threadIdx.x;
+  if (e >= a.nelem) return;
+  const int m = a.m;
+  const int s = (int)(e & (size_t)(a.S - 1));
+  const size_t row = e >> a.logS;
+  const int i = (int)(row % m), j = (int)((row / m) % m), k = (int)(row / ((size_t)m * m));
+  const double* y = a.y + (size_t)s * a.d;
+  const double h = 1.0 / (double)(m + 1);
+
+  // a at the centres of the eight cubes around mesh node (i+1, j+1, k+1):
+  // cube (i + cx, j + cy, k + cz), cx, cy, cz in {0, 1}
+  double ac[2][2][2];
+  for (int cz = 0; cz < 2; ++cz)
+    for (int cy = 0; cy < 2; ++cy)
+      for (int cx = 0; cx < 2; ++cx) {
+        const double xc = ((double)(i + cx) + 0.5) * h;
+        const double yc = ((double)(j + cy) + 0.5) * h;
+        const double zc = ((double)(k + cz) + 0.5) * h;
+        double g = 0.0;
+        for (int n = 0; n < a.d; ++n) {
+          const Fe3dTerm& f = a.term[n];
+          const double bx = phi1(f.kind[0], f.w[0], f.norm[0], xc);
+          const double by = phi1(f.kind[1], f.w[1], f.norm[1], yc);
+          const double bz = phi1(f.kind[2], f.w[2], f.norm[2], zc);
+          g = g + (f.sq * y[n]) * ((bz * by) * bx);
+        }
+        ac[cz][cy][cx] = kAmin + kAhat * exp(g);
+      }
+  const double kd = 1.0 / h, ko = -1.0 / h;               // K1 diagonal / off-diagonal
+  const double md = (2.0 * h) / 6.0, mo = (1.0 * h) / 6.0;  // M1
+  auto K1 = [&](int l, int l2) { return l == l2 ? kd : ko; };
+  auto M1 = [&](int l, int l2) { return l == l2 ? md : mo; };
+  for (int dk = -1; dk <= 1; ++dk)
+    for (int dj = -1; dj <= 1; ++dj)
+      for (int di = -1; di <= 1; ++di) {
+        const int slot = 9 * (dk + 1) + 3 * (dj + 1) + (di + 1);
+        double v = 0.0;
+        const bool inside = i + di >= 0 && i + di < m && j + dj >= 0 && j + dj < m &&
+                            k + dk >= 0 && k + dk < m;
+        if (inside) {
+          for (int cz = 0; cz < 2; ++cz)
+            for (int cy = 0; cy < 2; ++cy)
+              for (int cx = 0; cx < 2; ++cx) {
+                // local coordinates of the node and its neighbour in the cube
+                const int lx = 1 - cx, ly = 1 - cy, lz = 1 - cz;
+                const int nx = lx + di, ny = ly + dj, nz = lz + dk;
+                if (nx < 0 || nx > 1 || ny < 0 || ny > 1 || nz < 0 || nz > 1) continue;
+                const double t = ac[cz][cy][cx] * K1(lx, nx) * M1(ly, ny) * M1(lz, nz) +
+                                 kAy * M1(lx, nx) * K1(ly, ny) * M1(lz, nz) +
+                                 kAz * M1(lx, nx) * M1(ly, ny) * K1(lz, nz);
+                v = v + t;
+              }
+        }
+        a.V[(size_t)slot * a.vstride + e] = v;
+      }
+  a.b[e] = h * h * h;
+}
+
+// ------------------------------------------------------------ solver step
+// p = D^-1 r + beta p_old (M_PCG_J) or z + beta p_old (M_PCG_Z) and the
+// deferred x += alpha_prev p_old, element by element.
+template <int VEC, int MODE>
+__global__ __launch_bounds__(kNT) void fe3d_dir_kernel(StencilArgs a) {
+  if (gload(&a.m.ctl[CTL_DONE])) return;
+  const Geometry& g = a.g;
+  const int t = threadIdx.x, sv = (t % g.tpp) * VEC;
+  double beta[VEC], aprev[VEC];
+#pragma unroll
+  for (int c = 0; c < VEC; ++c) {
+    beta[c] = gload(&a.m.beta[sv + c]);
+    aprev[c] = gload(&a.m.alpha_prev[sv + c]);
+  }
+  const double* diag = a.V + (size_t)g.cslot * g.vstride;
+  const size_t stride = (size_t)gridDim.x * kNT * VEC;
+  for (size_t e = ((size_t)blockIdx.x * kNT + t) * VEC; e < g.nelem; e += stride) {
+    double v0[VEC], dv[VEC], po[VEC], xv[VEC], pv[VEC];
+    if constexpr (MODE == M_PCG_J) {
+      ld<VEC>(v0, a.r + e);
+      ld<VEC>(dv, diag + e);
+    } else {
+      ld<VEC>(v0, a.src + e);
+    }
+    ld<VEC>(po, a.pold + e);
+    ld<VEC>(xv, a.x + e);
+#pragma unroll
+    for (int c = 0; c < VEC; ++c) {
+      if constexpr (MODE == M_PCG_J) pv[c] = fma(beta[c], po[c], v0[c] / dv[c]);
+      else pv[c] = fma(beta[c], po[c], v0[c]);
+      if (aprev[c] != 0.0) xv[c] = fma(aprev[c], po[c], xv[c]);
+    }
+    st<VEC>(a.pnew + e, pv);
+    st<VEC>(a.x + e, xv);
+  }
+}
+
+// The 27-point product for (point, VEC members) per thread, grid-strided
+// over points; the mode's fused work follows (see the top of this file).
+template <int VEC, int MODE>
+__global__ __launch_bounds__(kNT) void fe3d_stencil_kernel(StencilArgs a) {
+  __shared__ double red[kWaves * 64 * 2];
+  constexpr bool PCG = (MODE == M_PCG_J || MODE == M_PCG_Z);
+  const Geometry& g = a.g;
+  if constexpr (MODE != M_SPMV) {
+    if (gload(&a.m.ctl[CTL_DONE])) return;
+  }
+  const int S = g.S, tpp = g.tpp, t = threadIdx.x, m = g.n;
+  const int sv = (t % tpp) * VEC;
+  const int ppb = kNT / tpp;   // points per workgroup and pass
+  const size_t vs = g.vstride, plane = (size_t)m * m;
+  double c1[VEC], c2[VEC], acc[VEC];
+#pragma unroll
+  for (int c = 0; c < VEC; ++c) {
+    acc[c] = 0.0;
+    c1[c] = c2[c] = 0.0;
+    if constexpr (MODE == M_CHEB) {
+      c1[c] = gload(&a.m.cheb[(size_t)(sv + c) * kChebCoef + 2 * a.cheb_step - 1]);
+      c2[c] = gload(&a.m.cheb[(size_t)(sv + c) * kChebCoef + 2 * a.cheb_step]);
+    }
+  }
+  const double* src = PCG ? a.pnew : a.src;
+  for (size_t pt = (size_t)blockIdx.x * ppb + t / tpp; pt < g.nr; pt += (size_t)gridDim.x * ppb) {
+    const int i = (int)(pt % m), j = (int)((pt / m) % m), k = (int)(pt / plane);
+    const size_t e = pt * S + sv;
+    double q[VEC], own[VEC], diag[VEC];
+#pragma unroll
+    for (int dk = -1; dk <= 1; ++dk) {
+#pragma unroll
+      for (int dj = -1; dj <= 1; ++dj) {
+#pragma unroll
+        for (int di = -1; di <= 1; ++di) {
+          const int slot = 9 * (dk + 1) + 3 * (dj + 1) + (di + 1);
+          const bool ok = i + di >= 0 && i + di < m && j + dj >= 0 && j + dj < m &&
+                          k + dk >= 0 && k + dk < m;
+          // neighbours outside the grid read the point itself and count zero
+          const size_t nb = ok ? (size_t)((long long)pt + ((long long)dk * m + dj) * m + di) : pt;
+          double vk[VEC], pv[VEC];
+          ld_stream<VEC>(vk, a.V + (size_t)slot * vs + e);
+          ld<VEC>(pv, src + nb * S + sv);
+#pragma unroll
+          for (int c = 0; c < VEC; ++c) {
+            pv[c] = ok ? pv[c] : 0.0;
+            q[c] = (slot == 0) ? vk[c] * pv[c] : fma(vk[c], pv[c], q[c]);
+            if (slot == 13) {
+              own[c] = pv[c];
+              diag[c] = vk[c];
+            }
+          }
+        }
+      }
+    }
+    if constexpr (MODE == M_SPMV) {
+      st<VEC>(a.q + e, q);
+    } else if constexpr (PCG) {
+#pragma unroll
+      for (int c = 0; c < VEC; ++c) acc[c] = fma(own[c], q[c], acc[c]);
+      st<VEC>(a.q + e, q);
+    } else {  // M_CHEB
+      double rr[VEC], dd[VEC], zn[VEC];
+      ld<VEC>(rr, a.r + e);
+      ld<VEC>(dd, a.d + e);
+#pragma unroll
+      for (int c = 0; c < VEC; ++c) {
+        dd[c] = c1[c] * dd[c] + c2[c] * ((rr[c] - q[c]) / diag[c]);
+        zn[c] = own[c] + dd[c];
+        if (a.cheb_last) acc[c] = fma(rr[c], zn[c], acc[c]);
+      }
+      st<VEC>(a.d + e, dd);
+      st<VEC>(a.zout + e, zn);
+    }
+  }
+  if constexpr (PCG) {
+    group_reduce<VEC>(acc, tpp, red);
+    put_partial<VEC>(a.partial, S, tpp, acc);
+  } else if constexpr (MODE == M_CHEB) {
+    if (a.cheb_last) {
+      group_reduce<VEC>(acc, tpp, red);
+      put_partial<VEC>(a.partial, S, tpp, acc);
+    }
+  }
+}
+
+// ------------------------------------------------------------ launchers
+void launch_fe3d_assemble(const Fe3dAsmArgs& a, hipStream_t s) {
+  const unsigned blocks = (unsigned)((a.nelem + kNT - 1) / kNT);
+  hipLaunchKernelGGL(fe3d_assemble_kernel, dim3(blocks), dim3(kNT), 0, s, a);
+}
+
+template <int VEC, int MODE>
+static void fe3d_step(const StencilArgs& a, hipStream_t s) {
+  if constexpr (MODE == M_PCG_J || MODE == M_PCG_Z)
+    hipLaunchKernelGGL((fe3d_dir_kernel<VEC, MODE>), dim3(init_groups(a.g)), dim3(kNT), 0, s, a);
+  hipLaunchKernelGGL((fe3d_stencil_kernel<VEC, MODE>), dim3(a.g.groups), dim3(kNT), 0, s, a);
+}
+
+template <int MODE>
+void launch_fe3d(const StencilArgs& a, hipStream_t s) {
+  if (a.g.vec == 2) fe3d_step<2, MODE>(a, s);
+  else fe3d_step<1, MODE>(a, s);
+}
+template void launch_fe3d<M_SPMV>(const StencilArgs&, hipStream_t);
+template void launch_fe3d<M_PCG_J>(const StencilArgs&, hipStream_t);
+template void launch_fe3d<M_PCG_Z>(const StencilArgs&, hipStream_t);
+template void launch_fe3d<M_CHEB>(const StencilArgs&, hipStream_t);
+
+}  // namespace ens

@@ -205,7 +205,7 @@ __global__ __launch_bounds__(kNT) void update_kernel(UpdateArgs a) {
       if (e < g.nelem) {
         ld<VEC>(rv[u], a.r + e);
         ld<VEC>(qv[u], a.q + e);
-        ld<VEC>(dv[u], a.V + 4 * g.vstride + e);
+        ld<VEC>(dv[u], a.V + (size_t)g.cslot * g.vstride + e);
       }
     }
 #pragma unroll
@@ -260,7 +260,7 @@ __global__ __launch_bounds__(kNT) void init_kernel(InitArgs a) {
     } else {
       ld<VEC>(bv, a.b + e);
     }
-    ld<VEC>(dv, a.V + 4 * g.vstride + e);
+    ld<VEC>(dv, a.V + (size_t)g.cslot * g.vstride + e);
 #pragma unroll
     for (int c = 0; c < VEC; ++c) {
       zero[c] = 0.0;
@@ -274,8 +274,7 @@ __global__ __launch_bounds__(kNT) void init_kernel(InitArgs a) {
       double rs[VEC];
 #pragma unroll
       for (int c = 0; c < VEC; ++c) rs[c] = 0.0;
-#pragma unroll
-      for (int k = 0; k < 9; ++k) {
+      for (int k = 0; k < g.nslot; ++k) {
         double vk[VEC];
         ld<VEC>(vk, a.V + (size_t)k * g.vstride + e);
 #pragma unroll
@@ -309,7 +308,7 @@ __global__ __launch_bounds__(kNT) void cheb_start_kernel(const double* V, const 
   for (size_t e = ((size_t)blockIdx.x * kNT + t) * VEC; e < g.nelem; e += stride) {
     double rv[VEC], dv[VEC], zz[VEC];
     ld<VEC>(rv, r + e);
-    ld<VEC>(dv, V + 4 * g.vstride + e);
+    ld<VEC>(dv, V + (size_t)g.cslot * g.vstride + e);
 #pragma unroll
     for (int c = 0; c < VEC; ++c) zz[c] = (rv[c] / dv[c]) / ith[c];
     st<VEC>(d + e, zz);
@@ -395,6 +394,10 @@ void launch_assemble(const AsmArgs& a, hipStream_t s) {
 
 template <int MODE>
 void launch_stencil(const StencilArgs& a, hipStream_t s) {
+  if (a.g.dim == 3) {
+    launch_fe3d<MODE>(a, s);
+    return;
+  }
   const dim3 grid(a.g.groups), block(kNT);
   if (a.g.vec == 2) {
     if (a.g.full) hipLaunchKernelGGL((stencil_kernel<2, MODE, false>), grid, block, 0, s, a);

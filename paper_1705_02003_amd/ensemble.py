@@ -19,19 +19,26 @@ from . import _lib as L
 
 @dataclass(frozen=True)
 class Problem:
-    """-div(a(x) K(y) grad u) = 1 on an n x n interior grid; see ens_problem."""
+    """dim 2: -div(a(x) K(y) grad u) = 1 on an n x n interior grid (nine-point
+    scheme); dim 3: the paper's 3-D test problem on an n x n x n interior grid
+    (trilinear finite elements, 27 matrix slots).  See ens_problem."""
 
     n: int
     d: int
     eps_model: int = 0
     amp: float = 0.0
+    dim: int = 2
 
     @property
     def rows(self) -> int:
-        return self.n * self.n
+        return self.n ** self.dim
+
+    @property
+    def slots(self) -> int:
+        return 27 if self.dim == 3 else 9
 
     def c(self) -> L.ens_problem:
-        return L.ens_problem(self.n, self.d, self.eps_model, 0, float(self.amp))
+        return L.ens_problem(self.n, self.d, self.eps_model, self.dim, float(self.amp))
 
 
 @dataclass
@@ -115,24 +122,24 @@ def matrix_slot_stride(prob: Problem, S: int) -> int:
 
 
 def empty_matrix(prob: Problem, S: int, device=None) -> torch.Tensor:
-    """An uninitialised ensemble matrix: a (9, N_r, S) view with the library's
-    slot stride (slot k starts at element k * matrix_slot_stride)."""
+    """An uninitialised ensemble matrix: a (slots, N_r, S) view with the
+    library's slot stride (slot k starts at element k * matrix_slot_stride)."""
     Ls = matrix_slot_stride(prob, S)
-    buf = torch.empty(9 * Ls, dtype=torch.float64, device=device or "cuda")
-    return buf.as_strided((9, prob.rows, S), (Ls, S, 1))
+    buf = torch.empty(prob.slots * Ls, dtype=torch.float64, device=device or "cuda")
+    return buf.as_strided((prob.slots, prob.rows, S), (Ls, S, 1))
 
 
 def _require_matrix(V: torch.Tensor, prob: Problem, S: int):
     if not isinstance(V, torch.Tensor) or not V.is_cuda or V.dtype != torch.float64:
         raise ValueError("V must be a float64 CUDA (HIP) tensor")
-    if tuple(V.shape) != (9, prob.rows, S):
-        raise ValueError(f"V has shape {tuple(V.shape)}, expected {(9, prob.rows, S)}")
+    if tuple(V.shape) != (prob.slots, prob.rows, S):
+        raise ValueError(f"V has shape {tuple(V.shape)}, expected {(prob.slots, prob.rows, S)}")
     if V.stride() != (matrix_slot_stride(prob, S), S, 1):
         raise ValueError("V must have the library's slot stride (use assemble or empty_matrix)")
 
 
 def assemble(prob: Problem, y: torch.Tensor):
-    """Ensemble matrix V (9, N_r, S; slot stride matrix_slot_stride) and
+    """Ensemble matrix V (slots, N_r, S; slot stride matrix_slot_stride) and
     right-hand side b (N_r, S) for y (S, d)."""
     _require_cuda(y, "y")
     S = int(y.shape[0])

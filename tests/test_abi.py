@@ -299,3 +299,46 @@ def test_group_variable_rejects_bad_arguments(L):
         grouping.group_variable(np.array([1.0, np.nan]), [1], [1.0])
     with pytest.raises(RuntimeError):
         grouping.group_variable(np.zeros(0), [1], [1.0])
+
+
+def test_3d_model_descriptor_without_gpu(L):
+    """dim = 3: slot stride and workspace over n^3 rows, descriptor limits,
+    and the entry points that take the 2-D model only (no device work:
+    every call below fails validation first)."""
+    lib = L.lib()
+    o = L.ens_opts()
+    for n, S in ((31, 32), (10, 1), (64, 16)):
+        p = L.ens_problem(n, 4, 0, 3, 0.0)
+        Ls = lib.ens_matrix_slot_stride(C.byref(p), S)
+        assert Ls == ((n ** 3 * S + 31) // 32) * 32 + 512
+        ws = lib.ens_pcg_workspace_bytes(C.byref(p), C.byref(o), S)
+        p2 = L.ens_problem(n, 4, 0, 2, 0.0)
+        ws2 = lib.ens_pcg_workspace_bytes(C.byref(p2), C.byref(o), S)
+        # five vectors of the slot stride beyond the same header
+        assert ws - ws2 == 5 * 8 * (Ls - lib.ens_matrix_slot_stride(C.byref(p2), S))
+    for bad in (L.ens_problem(31, 4, 1, 3, 0.0), L.ens_problem(31, 4, 0, 3, 0.4),
+                L.ens_problem(31, 0, 0, 3, 0.0), L.ens_problem(31, 17, 0, 3, 0.0),
+                L.ens_problem(1, 4, 0, 3, 0.0), L.ens_problem(1025, 4, 0, 3, 0.0),
+                L.ens_problem(31, 4, 0, 4, 0.0), L.ens_problem(31, 4, 0, 1, 0.0)):
+        assert lib.ens_matrix_slot_stride(C.byref(bad), 8) == 0
+        assert lib.ens_pcg_workspace_bytes(C.byref(bad), C.byref(o), 8) == 0
+    # 1 <= d is allowed in 3-D (the 2-D model needs d >= 2)
+    assert lib.ens_matrix_slot_stride(C.byref(L.ens_problem(31, 1, 0, 3, 0.0)), 8) > 0
+    assert lib.ens_matrix_slot_stride(C.byref(L.ens_problem(31, 1, 0, 2, 0.0)), 8) == 0
+    p = L.ens_problem(8, 4, 0, 3, 0.0)
+    a = C.c_void_p(4096)
+    g = np.zeros(64)
+    assert lib.ens_assemble_ensemble(C.byref(p), 8, None, a, a, None) == L.ENS_EINVAL
+    assert lib.ens_dqdy(C.byref(p), 8, a, a, a, g.ctypes.data_as(L.f64p), a, 1 << 30,
+                        None) == L.ENS_ENOTSUP
+    assert lib.ens_adjoint_grad(C.byref(p), C.byref(o), 8, a, a, a, a, a,
+                                g.ctypes.data_as(L.f64p), None, None, a, 1 << 40,
+                                None) == L.ENS_ENOTSUP
+    nb = lib.ens_batch_workspace_bytes(1)
+    items = (L.ens_batch_item * 1)()
+    it = items[0]
+    it.prob = p
+    it.S = 8
+    it.V_dev = it.b_dev = it.x_dev = it.ws_dev = 4096
+    it.ws_bytes = 1 << 40
+    assert lib.ens_batch_solve(None, 1, items, C.c_void_p(4096), nb, None) == L.ENS_ENOTSUP

@@ -1,0 +1,197 @@
+"""GPU parity of the 3-D trilinear finite-element model (the paper's test
+problem, dim = 3) against the oracle, through the C ABI.
+
+Tolerances: matrix entries within 1e-13 of their row's diagonal (the only
+differences are the last bits of cos / sin / exp in the diffusivity); the
+product and the Chebyshev application within 1e-13 relative (summation
+order); PCG iteration counts within +-1 of the oracle, the solution at equal
+iteration count within 1e-9 relative, true residual <= 2 rtol ||b||.
+Reductions are deterministic: permuting members permutes results bit for
+bit and a padded replica equals its original.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import torch
+
+from oracle import CONVERGED
+from oracle import fe3d as ofe
+from oracle import pcg as opcg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible: the gpu tests must run on an MI355X")
+    from paper_1705_02003_amd import _lib
+    _lib.lib()
+    yield
+
+
+def E():
+    from paper_1705_02003_amd import ensemble
+    return ensemble
+
+
+def to_dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def log_case(**kw):
+    print("CASE", " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+def csr_from_slots(Vs, m):
+    """CSR matrix of one member from its 27 stored slots (test helper)."""
+    N = m ** 3
+    r = np.arange(N)
+    i, j, k = r % m, (r // m) % m, r // (m * m)
+    rows, cols, vals = [], [], []
+    for s, (di, dj, dk) in enumerate(ofe.SLOT_OFFSETS):
+        ok = (i + di >= 0) & (i + di < m) & (j + dj >= 0) & (j + dj < m) & (k + dk >= 0) & (k + dk < m)
+        rows.append(r[ok])
+        cols.append(((k + dk) * m + (j + dj)) * m + (i + di))
+        cols[-1] = cols[-1][ok]
+        vals.append(Vs[s][ok])
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(N, N))
+
+
+def assemble(m, ys):
+    ens = E()
+    prob = ens.Problem(m, ys.shape[1], dim=3)
+    V, b = ens.assemble(prob, to_dev(ys))
+    return prob, V, b
+
+
+@pytest.mark.parametrize("m,S,d,seed", [(5, 8, 4, 0), (7, 1, 2, 1), (6, 32, 6, 2), (4, 64, 4, 3),
+                                        (3, 2, 1, 4)])
+def test_assembly_matches_oracle(m, S, d, seed):
+    log_case(test="fe3d-assembly", m=m, S=S, d=d)
+    ys = np.random.default_rng(seed).uniform(-1, 1, (S, d))
+    prob, V, b = assemble(m, ys)
+    Vh, bh = V.cpu().numpy(), b.cpu().numpy()
+    assert Vh.shape == (27, m ** 3, S)
+    h = 1.0 / (m + 1)
+    np.testing.assert_allclose(bh, h ** 3, rtol=1e-15)
+    for s in range(min(S, 8)):
+        A, _, dg = ofe.assemble(ys[s], m)
+        ref = ofe.slot_values(A, m)
+        err = np.abs(Vh[:, :, s] - ref).max(axis=0)
+        assert np.all(err <= 1e-13 * np.abs(dg)), (s, float((err / dg).max()))
+
+
+def test_matrix_bitwise_symmetric():
+    m, S = 6, 4
+    prob, V, _ = assemble(m, np.random.default_rng(5).uniform(-1, 1, (S, 4)))
+    Vh = V.cpu().numpy()
+    for s in range(S):
+        A = csr_from_slots(Vh[:, :, s], m)
+        assert (A != A.T).nnz == 0
+
+
+@pytest.mark.parametrize("m,S", [(9, 4), (7, 32), (5, 1), (11, 16)])
+def test_spmv_matches_oracle(m, S):
+    log_case(test="fe3d-spmv", m=m, S=S)
+    ens = E()
+    rng = np.random.default_rng(m * 100 + S)
+    prob, V, _ = assemble(m, rng.uniform(-1, 1, (S, 4)))
+    P = rng.standard_normal((m ** 3, S))
+    q = ens.spmv(prob, V, to_dev(P)).cpu().numpy()
+    Vh = V.cpu().numpy()
+    for s in range(S):
+        A = csr_from_slots(Vh[:, :, s], m)
+        ref = A @ P[:, s]
+        assert np.max(np.abs(q[:, s] - ref)) <= 1e-13 * np.abs(A).sum(axis=1).max() * np.abs(P[:, s]).max()
+
+
+def check_solution(res, ys, m, rtol, precond, real=None):
+    x = res.x.cpu().numpy()
+    worst = 0.0
+    for s in range(x.shape[1] if real is None else real):
+        A, b, diag = ofe.assemble(ys[s], m)
+        xo, Io, so, _ = opcg.pcg(A, b, diag, rtol, 20000, precond)
+        assert so == CONVERGED and res.status[s] == CONVERGED
+        assert abs(int(res.iters[s]) - Io) <= 1, (s, res.iters[s], Io)
+        xe, _, _, _ = opcg.pcg(A, b, diag, 0.0, int(res.iters[s]), precond)
+        worst = max(worst, np.linalg.norm(x[:, s] - xe) / np.linalg.norm(xe))
+        assert np.linalg.norm(b - A @ x[:, s]) <= 2 * rtol * np.linalg.norm(b)
+    return worst
+
+
+@pytest.mark.parametrize("m,S,d,seed", [(10, 8, 4, 6), (7, 1, 4, 7), (12, 32, 4, 8), (5, 64, 3, 9)])
+def test_jacobi_pcg_matches_oracle(m, S, d, seed):
+    log_case(test="fe3d-jacobi", m=m, S=S, d=d)
+    ens = E()
+    ys = np.random.default_rng(seed).uniform(-1, 1, (S, d))
+    prob, V, b = assemble(m, ys)
+    res = ens.solve(prob, V, b, ens.SolverOptions(rtol=1e-8))
+    worst = check_solution(res, ys, m, 1e-8, "jacobi", real=min(S, 8))
+    print("fe3d jacobi max rel diff", worst)
+    assert worst <= 1e-9
+
+
+def test_chebyshev_apply_matches_oracle():
+    log_case(test="fe3d-cheb-apply")
+    ens = E()
+    m, S = 8, 8
+    rng = np.random.default_rng(10)
+    prob, V, _ = assemble(m, rng.uniform(-1, 1, (S, 4)))
+    R = rng.standard_normal((m ** 3, S))
+    z, lmax = ens.cheb_apply(prob, V, to_dev(R))
+    z = z.cpu().numpy()
+    Vh = V.cpu().numpy()
+    for s in range(S):
+        A = csr_from_slots(Vh[:, :, s], m)
+        diag = Vh[ofe.CENTER, :, s]
+        lm = opcg.gershgorin_lmax(A, diag)
+        assert lmax[s] == pytest.approx(lm, rel=1e-15)
+        ref = opcg.chebyshev_apply(A, diag, R[:, s], lm)
+        assert np.linalg.norm(z[:, s] - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("m,S", [(10, 16), (6, 2)])
+def test_chebyshev_pcg_matches_oracle(m, S):
+    log_case(test="fe3d-chebyshev", m=m, S=S)
+    ens = E()
+    ys = np.random.default_rng(11).uniform(-1, 1, (S, 4))
+    prob, V, b = assemble(m, ys)
+    res = ens.solve(prob, V, b, ens.SolverOptions(precond="chebyshev"))
+    worst = check_solution(res, ys, m, 1e-8, "chebyshev", real=min(S, 8))
+    print("fe3d chebyshev max rel diff", worst)
+    assert worst <= 1e-9
+
+
+def test_permutation_and_padding_bitwise():
+    log_case(test="fe3d-permutation")
+    ens = E()
+    m, S = 9, 16
+    rng = np.random.default_rng(12)
+    ys = rng.uniform(-1, 1, (S, 4))
+    ys[12:] = ys[11]
+    prob, V, b = assemble(m, ys)
+    r0 = ens.solve(prob, V, b)
+    x0 = r0.x.cpu().numpy()
+    for s in range(12, S):
+        assert np.array_equal(x0[:, s], x0[:, 11]) and r0.iters[s] == r0.iters[11]
+    perm = rng.permutation(S)
+    _, V2, b2 = assemble(m, ys[perm])
+    r1 = ens.solve(prob, V2, b2)
+    assert np.array_equal(r1.x.cpu().numpy(), x0[:, perm])
+    assert np.array_equal(r1.iters, r0.iters[perm])
+    r2 = ens.solve(prob, V, b)
+    assert np.array_equal(r2.x.cpu().numpy(), x0)
+
+
+def test_adjoint_and_batch_reject_the_3d_model():
+    from paper_1705_02003_amd import _lib as L
+    ens = E()
+    m, S = 4, 4
+    ys = np.random.default_rng(13).uniform(-1, 1, (S, 4))
+    prob, V, b = assemble(m, ys)
+    u = ens.solve(prob, V, b).x
+    with pytest.raises(RuntimeError):
+        ens.adjoint_grad(prob, to_dev(ys), V, u, to_dev(np.ones(m ** 3)))
+    assert L.ENS_ENOTSUP == -4

@@ -63,7 +63,15 @@ ADJOINT_512 = Workload("adjoint-512x512-d6", 512, 6, EPS_MODEL_MILD, 0.4, (32,),
                        PRECOND_JACOBI, 1e-8, 20000, 4, 512,
                        "QoI = mean of u over [0.4,0.6]^2, gradient by adjoint")
 
-ALL = (SMALL, ADAPTIVE_512, CHEB_1024, BATCHED, ADJOINT_512)
+# The paper's own test problem (Section 4): 3-D, trilinear finite elements
+# on 32^3 cells (n = 31 interior nodes per dimension), N = 4 parameters,
+# solver tolerance 1e-7; 512 uniform samples grouped by a surrogate trained
+# on the level-2 sparse grid.  eps_model and amp do not apply (0).
+FE3D_32 = Workload("fe3d-32cube-d4", 31, 4, EPS_MODEL_MILD, 0.0, (32,),
+                   PRECOND_CHEBYSHEV, 1e-7, 20000, 5, 512,
+                   "3-D trilinear FE, log-normal KL diffusivity, Jacobi and Chebyshev-4")
+
+ALL = (SMALL, ADAPTIVE_512, CHEB_1024, BATCHED, ADJOINT_512, FE3D_32)
 
 
 def uniform_samples(seed: int, M: int, d: int) -> np.ndarray:
