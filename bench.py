@@ -509,11 +509,15 @@ def fe3d_mode(args) -> int:
     # bytes per member-row: direction kernel (r, diagonal, p_old, x in;
     # p, x out) + product (27 matrix values, p in; q out) = 35 words; the
     # update adds r, q, diagonal in and r out
-    step_bytes, iter_bytes = 35 * 8, 39 * 8
+    # (by default the product reads 14 matrix values per row and takes the
+    # other 13 from the neighbours' rows by symmetry: 22 and 26 words)
+    step_bytes, iter_bytes = (35 * 8, 39 * 8) if FULL_STENCIL else (22 * 8, 26 * 8)
     out = {"mode": "fe3d", "workload": w.name, "grid": f"{w.n + 1}^3 cells", "S": S,
-           "samples": w.n_samples, "rtol": w.rtol}
+           "samples": w.n_samples, "rtol": w.rtol, "full_stencil": FULL_STENCIL,
+           "step_bytes_per_member_row": step_bytes}
     for pre in ("jacobi", "chebyshev"):
-        opts = E.SolverOptions(precond=pre, rtol=w.rtol, max_iter=w.max_iter, time_spmv=True)
+        opts = E.SolverOptions(precond=pre, rtol=w.rtol, max_iter=w.max_iter, time_spmv=True,
+                               full_stencil=FULL_STENCIL)
         uq.nonadaptive(prob, S, ys[:S], 1, opts, solve_groups=[0])       # warm-up
         res = uq.nonadaptive(prob, S, ys, 2, opts)
         its = res.iters

@@ -126,7 +126,9 @@ typedef struct {
    from E(i-1, j), N(i, j-1), NE(i-1, j-1), NW(i+1, j-1); both give the same
    bits on the bitwise-symmetric matrices ens_assemble_ensemble writes.  The
    full read is kept for verification and for matrices stored otherwise.
-   ens_spmv always reads all nine values. */
+   ens_spmv always reads all nine values.  3-D model: by default the 14
+   values of slots 13..26 are read per row and slot s < 13 of row P is taken
+   as slot 26 - s of the neighbour row P + offset(s); with the flag all 27. */
 #define ENS_FLAG_FULL_STENCIL 2
 
 /* Optional statistics of one solve. */
@@ -177,7 +179,7 @@ size_t ens_pcg_workspace_bytes(const ens_problem* prob, const ens_opts* opts, in
  * Jacobi (diagonal = slot 4 of V; 3-D: slot 13) or a Chebyshev polynomial in
  * D^-1 A over [lambda_max / cheb_ratio, lambda_max], lambda_max the member's
  * Gershgorin bound max_i sum_j |a_ij| / a_ii.  Both models; the 3-D model
- * ignores tile_lines, member_tile and ENS_FLAG_FULL_STENCIL.
+ * ignores tile_lines and member_tile.
  * In:  V_dev [9][L] (3-D: [27][L]; symmetric positive definite per member),
  *      b_dev [N_r][S].
  * Out: x_dev [N_r][S] (overwritten); iters_host[S], status_host[S],

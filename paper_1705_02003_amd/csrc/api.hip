@@ -255,7 +255,11 @@ static double* cheb_apply(const double* V, const Workspace& w, const Geometry& g
 }
 
 static Geometry geometry_for(const ens_problem* prob, const Opts& o, int S) {
-  if (is3d(prob)) return make_geometry3(prob->n, S);
+  if (is3d(prob)) {
+    Geometry g = make_geometry3(prob->n, S);
+    g.full = (o.flags & ENS_FLAG_FULL_STENCIL) ? 1 : 0;
+    return g;
+  }
   Geometry g = make_geometry(prob->n, S, o.tile_lines, o.max_groups, o.member_tile);
   g.full = (o.flags & ENS_FLAG_FULL_STENCIL) ? 1 : 0;
   return g;

@@ -213,7 +213,14 @@ __global__ __launch_bounds__(kNT) void fe3d_dir_kernel(StencilArgs a) {
 
 // The 27-point product for (point, VEC members) per thread, grid-strided
 // over points; the mode's fused work follows (see the top of this file).
-template <int VEC, int MODE>
+// SYM: the matrix is symmetric, so the thirteen lower values of row P are
+// read as the upper values of the neighbours' rows, A(P, P + o) =
+// A(P + o, P) = slot 26 - s of row P + o; those rows are being read by their
+// own threads at about the same time, so the values come through the caches
+// and the matrix streams from memory about once at 14 words per row.  The
+// products are formed in the same order, so on a bitwise-symmetric matrix
+// both reads give the same bits.
+template <int VEC, int MODE, bool SYM>
 __global__ __launch_bounds__(kNT) void fe3d_stencil_kernel(StencilArgs a) {
   __shared__ double red[kWaves * 64 * 2];
   constexpr bool PCG = (MODE == M_PCG_J || MODE == M_PCG_Z);
@@ -252,11 +259,14 @@ __global__ __launch_bounds__(kNT) void fe3d_stencil_kernel(StencilArgs a) {
           // neighbours outside the grid read the point itself and count zero
           const size_t nb = ok ? (size_t)((long long)pt + ((long long)dk * m + dj) * m + di) : pt;
           double vk[VEC], pv[VEC];
-          ld_stream<VEC>(vk, a.V + (size_t)slot * vs + e);
+          if (SYM && slot < 13) ld<VEC>(vk, a.V + (size_t)(26 - slot) * vs + nb * S + sv);
+          else if (SYM) ld<VEC>(vk, a.V + (size_t)slot * vs + e);
+          else ld_stream<VEC>(vk, a.V + (size_t)slot * vs + e);
           ld<VEC>(pv, src + nb * S + sv);
 #pragma unroll
           for (int c = 0; c < VEC; ++c) {
             pv[c] = ok ? pv[c] : 0.0;
+            if (SYM) vk[c] = ok ? vk[c] : 0.0;
             q[c] = (slot == 0) ? vk[c] * pv[c] : fma(vk[c], pv[c], q[c]);
             if (slot == 13) {
               own[c] = pv[c];
@@ -307,7 +317,10 @@ template <int VEC, int MODE>
 static void fe3d_step(const StencilArgs& a, hipStream_t s) {
   if constexpr (MODE == M_PCG_J || MODE == M_PCG_Z)
     hipLaunchKernelGGL((fe3d_dir_kernel<VEC, MODE>), dim3(init_groups(a.g)), dim3(kNT), 0, s, a);
-  hipLaunchKernelGGL((fe3d_stencil_kernel<VEC, MODE>), dim3(a.g.groups), dim3(kNT), 0, s, a);
+  if (a.g.full)
+    hipLaunchKernelGGL((fe3d_stencil_kernel<VEC, MODE, false>), dim3(a.g.groups), dim3(kNT), 0, s, a);
+  else
+    hipLaunchKernelGGL((fe3d_stencil_kernel<VEC, MODE, true>), dim3(a.g.groups), dim3(kNT), 0, s, a);
 }
 
 template <int MODE>

@@ -195,3 +195,16 @@ def test_adjoint_and_batch_reject_the_3d_model():
     with pytest.raises(RuntimeError):
         ens.adjoint_grad(prob, to_dev(ys), V, u, to_dev(np.ones(m ** 3)))
     assert L.ENS_ENOTSUP == -4
+
+
+@pytest.mark.parametrize("m,S,pre", [(9, 8, "jacobi"), (6, 1, "jacobi"), (8, 32, "chebyshev")])
+def test_symmetric_read_bitwise(m, S, pre):
+    """The 14-value symmetric read and the 27-value read give the same bits."""
+    log_case(test="fe3d-sym", m=m, S=S, pre=pre)
+    ens = E()
+    ys = np.random.default_rng(20 + m).uniform(-1, 1, (S, 4))
+    prob, V, b = assemble(m, ys)
+    r0 = ens.solve(prob, V, b, ens.SolverOptions(precond=pre))
+    r1 = ens.solve(prob, V, b, ens.SolverOptions(precond=pre, full_stencil=True))
+    assert np.array_equal(r0.x.cpu().numpy(), r1.x.cpu().numpy())
+    assert np.array_equal(r0.iters, r1.iters)
