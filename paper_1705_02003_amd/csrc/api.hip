@@ -126,7 +126,9 @@ Geometry make_geometry(int n, int S, int tile_lines, int max_groups, int member_
 }
 
 // 3-D model: no tiles; the product kernel strides over points, kNT / tpp
-// points per workgroup and pass, with at most 1024 workgroups.
+// points per workgroup and pass, with at most 512 workgroups (two per CU;
+// measured on MI355X at 31^3 points, S = 32 and 64: 6 % faster solves than
+// 1024, whose larger partial arrays cost the finishing kernels more).
 Geometry make_geometry3(int m, int S) {
   Geometry g;
   std::memset(&g, 0, sizeof(g));
@@ -146,7 +148,7 @@ Geometry make_geometry3(int m, int S) {
   g.nslot = 27;
   g.cslot = 13;
   const size_t ppb = (size_t)(kNT / g.tpp);
-  g.groups = (int)std::min<size_t>((g.nr + ppb - 1) / ppb, 1024);
+  g.groups = (int)std::min<size_t>((g.nr + ppb - 1) / ppb, 512);
   return g;
 }
 
@@ -258,6 +260,7 @@ static Geometry geometry_for(const ens_problem* prob, const Opts& o, int S) {
   if (is3d(prob)) {
     Geometry g = make_geometry3(prob->n, S);
     g.full = (o.flags & ENS_FLAG_FULL_STENCIL) ? 1 : 0;
+    if (o.max_groups > 0) g.groups = std::min(g.groups, o.max_groups);
     return g;
   }
   Geometry g = make_geometry(prob->n, S, o.tile_lines, o.max_groups, o.member_tile);
