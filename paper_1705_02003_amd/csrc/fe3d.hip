@@ -243,7 +243,22 @@ __global__ __launch_bounds__(kNT) void fe3d_stencil_kernel(StencilArgs a) {
     }
   }
   const double* src = PCG ? a.pnew : a.src;
-  for (size_t pt = (size_t)blockIdx.x * ppb + t / tpp; pt < g.nr; pt += (size_t)gridDim.x * ppb) {
+  // Chunks of ppb consecutive points.  Consecutive workgroup ids are
+  // dispatched round-robin over the eight XCDs, each with its own L2: the
+  // chunks are split into eight contiguous ranges, one per XCD, so that a
+  // point's neighbours (one row and one plane away), whose values this
+  // thread reads, are mostly handled -- and cached -- on the same XCD.
+  const size_t nchunk = (g.nr + ppb - 1) / ppb;
+  size_t c0 = blockIdx.x, cstep = gridDim.x, cend = nchunk;
+  if (gridDim.x >= 8 && (gridDim.x & 7) == 0) {
+    const size_t x = blockIdx.x & 7;
+    c0 = (x * nchunk >> 3) + (blockIdx.x >> 3);
+    cstep = gridDim.x >> 3;
+    cend = (x + 1) * nchunk >> 3;
+  }
+  for (size_t ch = c0; ch < cend; ch += cstep) {
+    const size_t pt = ch * ppb + t / tpp;
+    if (pt >= g.nr) continue;
     const int i = (int)(pt % m), j = (int)((pt / m) % m), k = (int)(pt / plane);
     const size_t e = pt * S + sv;
     double q[VEC], own[VEC], diag[VEC];
