@@ -20,8 +20,10 @@
 //   M_CHEB:  one Chebyshev step d = c1 d + c2 D^-1 (r - A z), z_out = z + d,
 //            on the last step with the partial sums of r^T z_out.
 // The neighbours' values of the product come through the caches (a point's
-// 27 neighbours lie on three planes of the grid, all near in memory); the 27
-// matrix values are streamed.
+// 27 neighbours lie on three planes of the grid, all near in memory); of the
+// 27 matrix values of a row, the 14 of slots 13..26 are read and the other
+// 13 are the neighbours' rows' upper values (symmetry), also through the
+// caches.
 #include <algorithm>
 #include <cmath>
 #include <vector>
