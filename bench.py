@@ -212,21 +212,24 @@ def su_mode(args) -> int:
     import torch
     torch.cuda.set_device(0)
     y0 = np.array([-1.0, 0.0, 0.0, 0.0])
-    rows = su_rows((1, 2, 4, 8, 16, 32, 64), y0, verbose=True)
+    rows = su_rows(None, None, (1, 2, 4, 8, 16, 32, 64), y0, verbose=True)
     print(json.dumps({"mode": "su", "workload": "identical-samples-512x512", "y": y0.tolist(),
                       "rows": rows}), flush=True)
     return 0
 
 
-def su_rows(S_list, y0, verbose=False) -> list:
+def su_rows(prob, opts, S_list, y0, verbose=False) -> list:
     """Median solve time of S identical samples y0 for each S in S_list (the
-    first entry must be 1) and SU(S) = S t(1) / t(S)."""
+    first entry must be 1) and SU(S) = S t(1) / t(S); prob / opts default to
+    the benchmark's 512^2 problem and Jacobi at rtol 1e-8."""
     import numpy as np
     import torch
     import workloads
     from paper_1705_02003_amd import ensemble as E
-    prob = E.Problem(N_GRID, D, 0, AMP)
-    opts = E.SolverOptions(rtol=RTOL, full_stencil=FULL_STENCIL)
+    prob = prob or E.Problem(N_GRID, D, 0, AMP)
+    opts = opts or E.SolverOptions(rtol=RTOL, full_stencil=FULL_STENCIL)
+    # Jacobi iteration bytes per member-row (3-D: 26 words, 39 with all 27 values)
+    it_bytes = ITER_BYTES if prob.dim == 2 else (39 if FULL_STENCIL else 26) * 8
     rows, t1 = [], None
     for S in S_list:
         y = torch.tensor(workloads.identical_samples(y0, S), dtype=torch.float64, device="cuda")
@@ -243,7 +246,7 @@ def su_rows(S_list, y0, verbose=False) -> list:
         t1 = t if S == 1 else t1
         rows.append({"S": S, "seconds": round(t, 5), "iters": int(r.ens_iters),
                      "sample_solves_per_s": round(S / t, 2), "SU": round(S * t1 / t, 3),
-                     "iteration_alg_GBs": round(r.ens_iters * prob.rows * S * ITER_BYTES / t / 1e9, 1)})
+                     "iteration_alg_GBs": round(r.ens_iters * prob.rows * S * it_bytes / t / 1e9, 1)})
         if verbose:
             print(json.dumps(rows[-1]), flush=True)
         del V, b, ws
@@ -259,20 +262,34 @@ def table_mode(args) -> int:
     alone, S = 1, over the time of the ensemble solves; the assemblies'
     device time excluded from both) and the predicted speed-up SU(S) / R from
     the identical-sample curve.  Also the quantity of interest E[G^] after
-    each level."""
+    each level.
+
+    --dim 3: the same for the paper's own 3-D test problem (32^3 trilinear
+    cells, d = 4, the paper's Test 1 settings: tau 1e-3, at most 2000 samples,
+    up to 8 levels, solver tolerance 1e-7), SU(S) from S copies of y = 0."""
     import numpy as np
     import torch
+    import workloads
     from paper_1705_02003_amd import ensemble as E
     from paper_1705_02003_amd import uq
     torch.cuda.set_device(0)
     S_list = tuple(int(v) for v in args.S_list.split(","))
-    prob = E.Problem(N_GRID, D, 0, AMP)
-    opts = E.SolverOptions(rtol=RTOL, max_iter=20000, full_stencil=FULL_STENCIL)
-    res = uq.adaptive(prob, args.S, budget=args.budget, max_level=5, tau_rel=1e-3,
-                      strategy="surrogate", opts=opts, perm_seed=1)
+    if args.dim == 3:
+        w = workloads.FE3D_32
+        prob = E.Problem(w.n, w.d, dim=3)
+        opts = E.SolverOptions(rtol=w.rtol, max_iter=w.max_iter, full_stencil=FULL_STENCIL)
+        res = uq.adaptive(prob, args.S, budget=2000, max_level=8, tau_rel=1e-3,
+                          strategy="surrogate", opts=opts, perm_seed=1)
+        y0, workload = np.zeros(w.d), "adaptive-sg-fe3d-32cube-d4"
+    else:
+        prob = E.Problem(N_GRID, D, 0, AMP)
+        opts = E.SolverOptions(rtol=RTOL, max_iter=20000, full_stencil=FULL_STENCIL)
+        res = uq.adaptive(prob, args.S, budget=args.budget, max_level=5, tau_rel=1e-3,
+                          strategy="surrogate", opts=opts, perm_seed=1)
+        y0, workload = np.array([-1.0, 0.0, 0.0, 0.0]), "adaptive-sg-512x512-d4"
     print(f"[bench] adaptive run: levels {[l.n_samples for l in res.levels]}, "
           f"E[G] by level {[l.qoi_mean for l in res.levels]}", flush=True)
-    curve = su_rows((1, 2, 4, 8, 16, 32, 64), np.array([-1.0, 0.0, 0.0, 0.0]))
+    curve = su_rows(prob, opts, (1, 2, 4, 8, 16, 32, 64), y0)
     su = {r["S"]: r["SU"] for r in curve}
     print(f"[bench] SU(S): {su}", flush=True)
     # seconds per ensemble iteration at each width, from the same curve
@@ -309,7 +326,7 @@ def table_mode(args) -> int:
            "widths": vc["widths"]}
     rows.append(row)
     print(json.dumps(row), flush=True)
-    print(json.dumps({"mode": "table", "workload": "adaptive-sg-512x512-d4",
+    print(json.dumps({"mode": "table", "workload": workload,
                       "samples": len(res.y), "levels": [l.n_samples for l in res.levels],
                       "qoi_mean_levels": [l.qoi_mean for l in res.levels],
                       "SU": su, "sequential": seq, "rows": rows}), flush=True)
@@ -637,6 +654,8 @@ def main() -> int:
                          "copy, for hardware-counter runs")
     ap.add_argument("--iters", type=int, default=100, help="iterations in --mode kernel")
     ap.add_argument("--S-list", default="4,8,16,32,64", help="ensemble widths in --mode table")
+    ap.add_argument("--dim", type=int, default=2, choices=(2, 3),
+                    help="--mode table: the 2-D benchmark problem or the 3-D test problem")
     ap.add_argument("--full-stencil", action="store_true",
                     help="read all nine matrix values per row (no symmetric reuse)")
     ap.add_argument("--sequential", action="store_true",

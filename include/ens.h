@@ -217,6 +217,18 @@ int ens_member_dot(int32_t N_r, int32_t S, const double* a_dev, const double* b_
                    int32_t b_broadcast, double* out_host,
                    void* ws_dev, size_t ws_bytes, void* stream);
 
+/* Parameter-based grouping indicator (paper, Section 3.2, eq.
+ * (pb-indicator)): per member, H = the supremum over the domain of
+ * lambda_max / lambda_min of the diffusion tensor.  2-D model: a(x) K(y) has
+ * eigenvalues a and a eps, so H = 1 / eps(y'_0).  3-D model: diag(a, a_y,
+ * a_z) with a held on each cube, so H = the largest max(a, a_y, a_z) /
+ * min(a, a_y, a_z) over the cubes.  In: y_dev [S][d] (device).  Out:
+ * h_host [S].  Uses the first ens_pcg_workspace_bytes(...) bytes of ws.
+ * Blocking.  Errors: as ens_assemble_ensemble; ENS_ENOMEM for a too-small
+ * workspace. */
+int ens_param_indicator(const ens_problem* prob, int32_t S, const double* y_dev,
+                        double* h_host, void* ws_dev, size_t ws_bytes, void* stream);
+
 /* ----------------------------------------------------------- adjoint */
 /* dQ/dy for Q_s = w^T u_s, with A_s u_s = b (A symmetric, b independent of y):
  *   solve A_s lambda_s = w by the same ensemble PCG, then

@@ -173,3 +173,12 @@ def slot_values(A, m: int) -> np.ndarray:
     assert np.all(np.abs(di) <= 1) and np.all(np.abs(dj) <= 1) and np.all(np.abs(dk) <= 1)
     out[9 * (dk + 1) + 3 * (dj + 1) + (di + 1), r] = C.data
     return out
+
+
+def param_indicator(y, m: int) -> float:
+    """Section 3.2, eq. (pb-indicator): the supremum over the domain of
+    lambda_max / lambda_min of A = diag(a, a_y, a_z), a held on each cube."""
+    ac = element_coefficients(y, m)
+    hi = np.maximum(np.maximum(ac, A_Y), A_Z)
+    lo = np.minimum(np.minimum(ac, A_Y), A_Z)
+    return float(np.max(hi / lo))

@@ -154,3 +154,11 @@ def qoi_weights(n):
     w = np.zeros(n * n)
     w[mask] = 1.0 / float(mask.sum())
     return w
+
+
+def param_indicator(y, eps_model) -> float:
+    """Section 3.2, eq. (pb-indicator): the supremum over the domain of
+    lambda_max / lambda_min of a(x) K(y).  K = R diag(1, eps) R^T and a > 0
+    scales both eigenvalues, so the ratio is 1 / eps at every x."""
+    eps = anisotropy(np.asarray(y), eps_model)[0]
+    return 1.0 / eps

@@ -65,6 +65,7 @@ SIGNATURES = {
     "ens_group_samples": (C.c_int, [i32, i32, i32p, i32p, f64p, i32, f64p, i32, i32p, f64p]),
     "ens_sg_surpluses": (C.c_int, [i32, i32, i32p, i32p, f64p, f64p]),
     "ens_sg_expectation": (C.c_int, [i32, i32, i32p, i32p, f64p, f64p]),
+    "ens_param_indicator": (C.c_int, [PP, i32, vp, f64p, vp, sz, vp]),
     "ens_group_variable": (C.c_int, [i32, f64p, i32, i32p, f64p, i32p, i32p, i32p, i32p, f64p]),
     "ens_sg_coords": (C.c_int, [i32, i32, i32p, i32p, f64p]),
     "ens_sg_refine": (C.c_int, [i32, i32, i32p, i32p, f64p, i32, f64, i32, i32, i32p, i32p, i32p]),

@@ -644,6 +644,54 @@ int ens_member_dot(int32_t N_r, int32_t S, const double* a_dev, const double* b_
   return ENS_OK;
 }
 
+int ens_param_indicator(const ens_problem* prob, int32_t S, const double* y_dev, double* h_host,
+                        void* ws_dev, size_t ws_bytes, void* stream) {
+  int rc = check_problem(prob);
+  if (rc) return rc;
+  if (!valid_S(S) || !y_dev || !h_host || !ws_dev) return ENS_EINVAL;
+  if (ws_bytes < header_bytes()) return ENS_ENOMEM;
+  const Workspace w = carve_workspace(ws_dev, 0, S, false);
+  IndArgs a;
+  std::memset(&a, 0, sizeof(a));
+  if (is3d(prob)) {
+    Fe3dAsmArgs f;
+    std::memset(&f, 0, sizeof(f));
+    rc = fe3d_setup(prob, f);
+    if (rc) return rc;
+    std::memcpy(a.term, f.term, sizeof(a.term));
+    a.dim = 3;
+    a.ncell = (size_t)(prob->n + 1) * (prob->n + 1) * (prob->n + 1);
+  } else {
+    a.dim = 2;
+    a.ncell = 1;
+  }
+  a.y = y_dev;
+  a.partial = w.partial;
+  a.m = prob->n;
+  a.S = S;
+  a.d = prob->d;
+  a.eps_model = prob->eps_model;
+  const int groups = (int)std::min<size_t>((a.ncell * S + kNT - 1) / kNT, 512);
+  hipStream_t s = (hipStream_t)stream;
+  launch_indicator(a, groups, s);
+  {
+    FinishArgs f;
+    std::memset(&f, 0, sizeof(f));
+    f.partial = w.partial;
+    f.G = groups;
+    f.kind = F_MAX;
+    f.m = w.m;
+    f.g = make_geometry(2, S, 0, 0);
+    launch_finish(f, s);
+  }
+  HIPCHECK(hipGetLastError());
+  double res[kMaxS * 16];
+  HIPCHECK(hipMemcpyAsync(res, w.m.result, sizeof(double) * S * 16, hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  for (int k = 0; k < S; ++k) h_host[k] = res[k * 16];
+  return ENS_OK;
+}
+
 int ens_dqdy(const ens_problem* prob, int32_t S, const double* y_dev, const double* u_dev,
              const double* lambda_dev, double* grad_host, void* ws_dev, size_t ws_bytes,
              void* stream) {

@@ -159,7 +159,18 @@ struct DqdyArgs {
   double amp;
 };
 
-enum Finish { F_ALPHA = 0, F_UPDATE_J = 1, F_UPDATE_C = 2, F_CHEB = 3, F_INIT = 4, F_DOT = 5, F_SUMS = 6 };
+enum Finish { F_ALPHA = 0, F_UPDATE_J = 1, F_UPDATE_C = 2, F_CHEB = 3, F_INIT = 4, F_DOT = 5, F_SUMS = 6,
+              F_MAX = 7 };
+
+// Parameter-based grouping indicator (both models): per member the largest
+// ratio lambda_max / lambda_min of the diffusion tensor over the domain.
+struct IndArgs {
+  const double* y;   // [S][d]
+  double* partial;   // [groups][S] per-workgroup maxima
+  int dim, m, S, d, eps_model;
+  size_t ncell;      // 3-D: cubes (m+1)^3; 2-D: 1 (the ratio does not depend on x)
+  Fe3dTerm term[kMaxTerms];
+};
 
 struct FinishArgs {
   const double* partial;  // consecutive arrays of G * S partials
@@ -203,6 +214,7 @@ Geometry make_geometry3(int m, int S);
 // dim = 3 geometries (launch_stencil forwards to it)
 int fe3d_setup(const ens_problem* p, Fe3dAsmArgs& a);
 void launch_fe3d_assemble(const Fe3dAsmArgs& a, hipStream_t s);
+void launch_indicator(const IndArgs& a, int groups, hipStream_t s);
 template <int MODE>
 void launch_fe3d(const StencilArgs& a, hipStream_t s);
 // Elements from the start of one matrix slot (or workspace vector) to the

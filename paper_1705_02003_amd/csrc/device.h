@@ -694,6 +694,12 @@ __device__ __forceinline__ int finish_body(const FinishArgs& a, double* fin, int
       }
       return 0;
     }
+    case F_MAX: {
+      // per-member maximum of one partial array into result[s][0]
+      const double v = final_max(a.partial, a.G, S, fin);
+      if (t < S) gstore(&m.result[(size_t)t * 16], v);
+      return 0;
+    }
     case F_DOT:
     case F_SUMS: {
       // nsum member sums, scaled, into result[s][q]

@@ -176,6 +176,52 @@ __global__ __launch_bounds__(kNT) void fe3d_assemble_kernel(Fe3dAsmArgs a) {
   a.b[e] = h * h * h;
 }
 
+// ------------------------------------------------------------ indicator
+// Paper, Section 3.2, eq. (pb-indicator): H(y) = sup over the domain of
+// lambda_max / lambda_min of the diffusion tensor.  3-D: the tensor is
+// diag(a, a_y, a_z) with a constant on each cube, so H is the largest
+// max(a, a_y, a_z) / min(a, a_y, a_z) over the cubes.  2-D: a(x) K(y) has
+// eigenvalues a(x) and a(x) eps, so H = 1 / eps(y_0) everywhere.  One thread
+// per (cube, member), grid-strided; per-workgroup maxima per member.
+__global__ __launch_bounds__(kNT) void indicator_kernel(IndArgs a) {
+  __shared__ double red[kWaves * 64 * 2];
+  const int S = a.S, t = threadIdx.x, s = t & (S - 1);
+  const double* y = a.y + (size_t)s * a.d;
+  double hv[1] = {0.0};
+  const size_t total = a.ncell * S;
+  const size_t stride = (size_t)gridDim.x * kNT;
+  for (size_t e = (size_t)blockIdx.x * kNT + t; e < total; e += stride) {
+    double r;
+    if (a.dim == 3) {
+      const size_t c = e / S;
+      const int mc = a.m + 1;
+      const int cx = (int)(c % mc), cy = (int)((c / mc) % mc), cz = (int)(c / ((size_t)mc * mc));
+      const double h = 1.0 / (double)(a.m + 1);
+      const double xc = ((double)cx + 0.5) * h, yc = ((double)cy + 0.5) * h, zc = ((double)cz + 0.5) * h;
+      double g = 0.0;
+      for (int n = 0; n < a.d; ++n) {
+        const Fe3dTerm& f = a.term[n];
+        const double bx = phi1(f.kind[0], f.w[0], f.norm[0], xc);
+        const double by = phi1(f.kind[1], f.w[1], f.norm[1], yc);
+        const double bz = phi1(f.kind[2], f.w[2], f.norm[2], zc);
+        g = g + (f.sq * y[n]) * ((bz * by) * bx);
+      }
+      const double ac = kAmin + kAhat * exp(g);
+      r = fmax(fmax(ac, kAy), kAz) / fmin(fmin(ac, kAy), kAz);
+    } else {
+      const double eps = (a.eps_model == 0) ? pow(10.0, -(1.0 + y[0])) : pow(10.0, -(1.5 + 1.5 * y[0]));
+      r = 1.0 / eps;
+    }
+    hv[0] = fmax(hv[0], r);
+  }
+  group_max<1>(hv, S, red);
+  put_partial<1>(a.partial, S, S, hv);
+}
+
+void launch_indicator(const IndArgs& a, int groups, hipStream_t s) {
+  hipLaunchKernelGGL(indicator_kernel, dim3(groups), dim3(kNT), 0, s, a);
+}
+
 // ------------------------------------------------------------ solver step
 // p = D^-1 r + beta p_old (M_PCG_J) or z + beta p_old (M_PCG_Z) and the
 // deferred x += alpha_prev p_old, element by element.

@@ -227,6 +227,32 @@ def member_dot(a: torch.Tensor, b: torch.Tensor, ws: Optional[torch.Tensor] = No
     return out
 
 
+def param_indicator(prob: Problem, y: torch.Tensor, ws: Optional[torch.Tensor] = None) -> np.ndarray:
+    """H(y) per member (S,): the largest eigenvalue ratio of the diffusion
+    tensor over the domain (the parameter-based grouping indicator)."""
+    S = int(y.shape[0])
+    _require_cuda(y, "y", (S, prob.d))
+    if ws is None:
+        ws = workspace(Problem(2, 2), S, None, y.device)
+    h = np.zeros(S, np.float64)
+    pc = prob.c()
+    L.check(L.lib().ens_param_indicator(C.byref(pc), S, _p(y), h.ctypes.data_as(L.f64p), _p(ws),
+                                        ws.numel(), _stream(y.device)), "ens_param_indicator")
+    return h
+
+
+def param_indicator_samples(prob: Problem, ys: np.ndarray, device="cuda") -> np.ndarray:
+    """H for any number of samples (M, d), in member batches of 64."""
+    ys = np.asarray(ys, dtype=np.float64)
+    out = np.zeros(len(ys))
+    ws = workspace(Problem(2, 2), 64, None, device)
+    for a in range(0, len(ys), 64):
+        blk = ys[a:a + 64]
+        pad = np.vstack([blk, np.repeat(blk[-1:], 64 - len(blk), axis=0)])
+        out[a:a + len(blk)] = param_indicator(prob, torch.tensor(pad, device=device), ws)[:len(blk)]
+    return out
+
+
 def dqdy(prob: Problem, y: torch.Tensor, u: torch.Tensor, lam: torch.Tensor,
          ws: Optional[torch.Tensor] = None) -> np.ndarray:
     """-lambda^T (dA/dy_j) u per member, shape (S, d)."""

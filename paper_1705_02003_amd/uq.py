@@ -57,6 +57,7 @@ class UQResult:
     spmv_launches: int = 0
     spmv_member_rows: float = 0.0   # sum over timed launches of N_r * S
     assemble_ms: float = 0.0        # device time of the ensemble assemblies
+    hind: np.ndarray = None         # parameter-based indicator H(y) per sample (Section 3.2)
 
     @property
     def qoi_mean(self) -> float:
@@ -127,12 +128,18 @@ def adaptive(prob: E.Problem, S: int, budget: int = 1024, max_level: int = 5,
     wss = _Workspaces(prob, opts, device)
     lv, ix = G.initial_grid(prob.d)
     out = UQResult(level=np.zeros((0, prob.d), np.int32), index=np.zeros((0, prob.d), np.int32),
-                   y=np.zeros((0, prob.d)), iters=np.zeros(0, np.int64), qoi=np.zeros(0))
+                   y=np.zeros((0, prob.d)), iters=np.zeros(0, np.int64), qoi=np.zeros(0),
+                   hind=np.zeros(0))
     spmv_acc = [0.0, 0, 0.0, 0.0]
     level = 1
     while True:
         y_level = G.coords(lv, ix)
-        if strategy != "variable" and (level == 1 or strategy == "natural"):
+        hind = E.param_indicator_samples(prob, y_level, device)
+        if strategy == "param":
+            # Section 3.2: ascending H, ties in generation order, on every level
+            groups = G.chunk(sorted(range(len(y_level)), key=lambda i: (hind[i], i)), S)
+            pred = np.zeros(len(y_level))
+        elif strategy != "variable" and (level == 1 or strategy == "natural"):
             groups = G.chunk(list(range(len(y_level))), S)
             pred = np.zeros(len(y_level))
         elif strategy == "surrogate":
@@ -158,6 +165,7 @@ def adaptive(prob: E.Problem, S: int, budget: int = 1024, max_level: int = 5,
         out.y = np.vstack([out.y, y_level])
         out.iters = np.concatenate([out.iters, iters])
         out.qoi = np.concatenate([out.qoi, qoi])
+        out.hind = np.concatenate([out.hind, hind])
         mean = G.expectation(out.level, out.index, out.qoi)
         out.levels.append(LevelRecord(level, len(y_level), groups, ens_iters, iters, qoi, pred, dt,
                                       mean))
@@ -178,10 +186,11 @@ def strategy_groups(res: UQResult, S: int, perm_seed: int = 1) -> dict:
     surrogate grouping is then recomputed from the same data).  Strategies:
     "surrogate" (Section 3.1), "natural" (generation order), "random" (one
     seeded permutation per level), "param" (Section 3.2: ascending
-    max_x lambda_max / lambda_min of a(x) K(y) = 1 / eps(y_1), i.e. ascending
-    y_1, ties in generation order) and "its" (ascending true counts, the
-    ideal).  On the first level "surrogate" and "random" use generation
-    order: there is nothing to go on yet."""
+    H(y) = max_x lambda_max / lambda_min of the diffusion tensor, from the
+    library, ties in generation order; for the 2-D model H = 1 / eps(y_1))
+    and "its" (ascending true counts, the ideal).  On the first level
+    "surrogate" and "random" use generation order: there is nothing to go on
+    yet."""
     rng = np.random.default_rng(perm_seed)
     per = {"surrogate": [], "natural": [], "random": [], "param": [], "its": []}
     start = 0
@@ -192,11 +201,12 @@ def strategy_groups(res: UQResult, S: int, perm_seed: int = 1) -> dict:
         nat = G.chunk(list(range(m)), S)
         per["natural"].append(nat)
         per["random"].append(G.chunk(list(rng.permutation(m)), S) if r.level > 1 else nat)
-        per["param"].append(G.chunk(sorted(range(m), key=lambda i: (y[i, 0], i)), S))
+        hv = res.hind[start:start + m]
+        per["param"].append(G.chunk(sorted(range(m), key=lambda i: (hv[i], i)), S))
         per["its"].append(G.chunk(sorted(range(m), key=lambda i: (its[i], i)), S))
         if r.level == 1:
             sur = nat
-        elif r.groups.shape[1] == S:
+        elif isinstance(r.groups, np.ndarray) and r.groups.shape[1] == S:
             sur = r.groups
         else:
             sur, _ = G.group_samples(res.level[:start], res.index[:start], res.iters[:start], y, S)

@@ -166,7 +166,7 @@ def test_argument_validation_without_gpu(L):
 def test_grouping_strategies_on_recorded_counts(L):
     """The strategy comparison of the benchmark works from recorded counts:
     'its' is optimal (no grouping has fewer ensemble iterations), 'param'
-    orders by y_1, every strategy covers every sample, and regrouping at
+    orders by the indicator H, every strategy covers every sample, and regrouping at
     another width reproduces the host surrogate grouping (Section 3.1)."""
     from paper_1705_02003_amd import grouping, uq
     rng = np.random.default_rng(11)
@@ -184,6 +184,7 @@ def test_grouping_strategies_on_recorded_counts(L):
     res.index = np.vstack([ix1, ix2]).astype(np.int32)
     res.y = np.vstack([y1, y2])
     res.iters = np.concatenate([it1, it2])
+    res.hind = 10.0 ** (1.0 + res.y[:, 0])        # the 2-D model's H = 1 / eps(y_1)
     g32, _ = grouping.group_samples(lv1, ix1, it1, y2, 32)
     res.levels = [uq.LevelRecord(1, len(y1), grouping.chunk(list(range(len(y1))), 32), [], it1,
                                  np.zeros(len(y1)), np.zeros(len(y1)), 0.0),
@@ -197,7 +198,8 @@ def test_grouping_strategies_on_recorded_counts(L):
                 assert sorted(set(g.reshape(-1).tolist())) == list(range(r.n_samples))
             assert costs["its"]["sum_ensemble_iters"] <= costs[k]["sum_ensemble_iters"]
         order = per["param"][1].reshape(-1)
-        assert np.all(np.diff(y2[order[:len(y2)], 0]) >= 0)
+        h2 = res.hind[len(y1):]
+        assert np.all(np.diff(h2[order[:len(y2)]]) >= 0)
         expect, _ = grouping.group_samples(lv1, ix1, it1, y2, S)
         assert np.array_equal(per["surrogate"][1], expect)
 

@@ -208,3 +208,23 @@ def test_symmetric_read_bitwise(m, S, pre):
     r1 = ens.solve(prob, V, b, ens.SolverOptions(precond=pre, full_stencil=True))
     assert np.array_equal(r0.x.cpu().numpy(), r1.x.cpu().numpy())
     assert np.array_equal(r0.iters, r1.iters)
+
+
+@pytest.mark.parametrize("dim,m,S,d,eps_model", [(3, 6, 8, 4, 0), (3, 9, 64, 6, 0), (3, 4, 1, 2, 0),
+                                                 (2, 40, 16, 4, 0), (2, 40, 4, 8, 1)])
+def test_param_indicator_matches_oracle(dim, m, S, d, eps_model):
+    from oracle import problem as oprob
+    log_case(test="indicator", dim=dim, m=m, S=S)
+    ens = E()
+    ys = np.random.default_rng(30 + m).uniform(-1, 1, (S, d))
+    amp = 0.4 if dim == 2 else 0.0
+    prob = ens.Problem(m, d, eps_model, amp, dim=dim)
+    h = ens.param_indicator(prob, to_dev(ys))
+    for s in range(S):
+        ref = ofe.param_indicator(ys[s], m) if dim == 3 else oprob.param_indicator(ys[s], eps_model)
+        assert h[s] == pytest.approx(ref, rel=1e-13)
+    many = np.random.default_rng(1).uniform(-1, 1, (150, d))
+    hm = ens.param_indicator_samples(prob, many)
+    assert hm.shape == (150,)
+    assert hm[149] == pytest.approx(ofe.param_indicator(many[149], m) if dim == 3
+                                    else oprob.param_indicator(many[149], eps_model), rel=1e-13)

@@ -123,3 +123,13 @@ def test_manufactured_solution_second_order():
         errs.append(np.max(np.abs(uh - u)))
     r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
     assert 3.3 < r1 < 4.7 and 3.6 < r2 < 4.4
+
+
+def test_param_indicator():
+    m = 5
+    # y = 0: a = a_min + a_hat everywhere
+    assert fe3d.param_indicator(np.zeros(4), m) == pytest.approx(fe3d.A_MIN + fe3d.A_HAT, rel=1e-15)
+    y = np.array([0.9, -0.7, 0.3, 0.5])
+    ac = fe3d.element_coefficients(y, m)
+    ratios = [np.linalg.eigvalsh(np.diag([a, fe3d.A_Y, fe3d.A_Z])) for a in ac.reshape(-1)]
+    assert fe3d.param_indicator(y, m) == pytest.approx(max(r[-1] / r[0] for r in ratios), rel=1e-15)

@@ -177,3 +177,14 @@ def test_tensor_is_rotated_diag(eps_model):
         v2 = np.array([-math.sin(theta), math.cos(theta)])
         np.testing.assert_allclose(K @ v1, v1, atol=1e-15)
         np.testing.assert_allclose(K @ v2, eps * v2, atol=1e-15)
+
+
+def test_param_indicator_is_the_tensor_eigenvalue_ratio():
+    rng = np.random.default_rng(3)
+    for eps_model in (0, 1):
+        for _ in range(5):
+            y = rng.uniform(-1, 1, 4)
+            _, _, k11, k22, k12 = problem.anisotropy(y, eps_model)
+            for a in (0.6, 1.0, 1.7):      # a(x) > 0 scales both eigenvalues
+                ev = np.linalg.eigvalsh(a * np.array([[k11, k12], [k12, k22]]))
+                assert problem.param_indicator(y, eps_model) == pytest.approx(ev[-1] / ev[0], rel=1e-12)
