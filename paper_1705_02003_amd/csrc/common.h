@@ -23,10 +23,6 @@ constexpr int kChebCoef = 2 * kMaxCheb + 2;
 enum Ctl : int {
   CTL_DONE = 0,   // 1 when no member is active
   CTL_K = 1,      // completed iterations
-  CTL_CTR_A = 2,  // last-block counters (one per reducing kernel kind)
-  CTL_CTR_B = 3,
-  CTL_CTR_C = 4,
-  CTL_CTR_D = 5,
   CTL_MAXIT = 6,  // iteration cap (copied from the options)
   CTL_COUNT = 16
 };
