@@ -509,8 +509,9 @@ def fe3d_mode(args) -> int:
     rtol 1e-7.  The level-2 sparse grid (41 nodes) is solved to build the
     iteration surrogate, the 512 uniform samples (seed 5) are ordered by it
     into ensembles of S and every ensemble is solved, with Jacobi and with
-    degree-4 Jacobi-Chebyshev; the first ensemble's samples are also solved
-    one at a time (S = 1).  At this size an ensemble's matrix (27 x 8 B per
+    degree-4 Jacobi-Chebyshev, --streams ensembles at a time (default 2) on
+    separate HIP streams; the first ensemble's samples are also solved one at
+    a time (S = 1).  At this size an ensemble's matrix (27 x 8 B per
     member-row, 206 MB at S = 32) fits the 256 MB Infinity Cache, so the
     product kernel's rate is partly a cache rate."""
     import numpy as np
@@ -529,14 +530,15 @@ def fe3d_mode(args) -> int:
     # (by default the product reads 14 matrix values per row and takes the
     # other 13 from the neighbours' rows by symmetry: 22 and 26 words)
     step_bytes, iter_bytes = (35 * 8, 39 * 8) if FULL_STENCIL else (22 * 8, 26 * 8)
+    K = args.streams or 2
     out = {"mode": "fe3d", "workload": w.name, "grid": f"{w.n + 1}^3 cells", "S": S,
            "samples": w.n_samples, "rtol": w.rtol, "full_stencil": FULL_STENCIL,
-           "step_bytes_per_member_row": step_bytes}
+           "step_bytes_per_member_row": step_bytes, "streams": K}
     for pre in ("jacobi", "chebyshev"):
         opts = E.SolverOptions(precond=pre, rtol=w.rtol, max_iter=w.max_iter, time_spmv=True,
                                full_stencil=FULL_STENCIL)
-        uq.nonadaptive(prob, S, ys[:S], 1, opts, solve_groups=[0])       # warm-up
-        res = uq.nonadaptive(prob, S, ys, 2, opts)
+        uq.nonadaptive(prob, S, ys[:S], 1, opts, solve_groups=[0], streams=K)       # warm-up
+        res = uq.nonadaptive(prob, S, ys, 2, opts, streams=K)
         its = res.iters
         us = 1e3 * res.spmv_ms / max(1, res.spmv_launches)
         rows = prob.rows * S
@@ -654,6 +656,9 @@ def main() -> int:
                          "copy, for hardware-counter runs")
     ap.add_argument("--iters", type=int, default=100, help="iterations in --mode kernel")
     ap.add_argument("--S-list", default="4,8,16,32,64", help="ensemble widths in --mode table")
+    ap.add_argument("--streams", type=int, default=0,
+                    help="ensembles solved at a time on separate HIP streams (0: 2 in --mode fe3d, "
+                         "else 1)")
     ap.add_argument("--dim", type=int, default=2, choices=(2, 3),
                     help="--mode table: the 2-D benchmark problem or the 3-D test problem")
     ap.add_argument("--full-stencil", action="store_true",

@@ -21,6 +21,7 @@ grouping of the same samples follows exactly from the recorded counts.
 from __future__ import annotations
 
 import time
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 from typing import List, Optional
 
@@ -71,20 +72,59 @@ class UQResult:
 
 
 class _Workspaces:
-    """Solver workspaces by ensemble width, allocated on first use."""
+    """Solver workspaces by ensemble width (and by worker, for concurrent
+    solves), allocated on first use; one HIP stream per extra worker."""
 
     def __init__(self, prob, opts, device):
-        self.prob, self.opts, self.device, self.by_width = prob, opts, device, {}
+        self.prob, self.opts, self.device, self.by_width, self.streams = prob, opts, device, {}, {}
 
-    def __call__(self, S: int):
-        if S not in self.by_width:
-            self.by_width[S] = E.workspace(self.prob, S, self.opts, self.device)
-        return self.by_width[S]
+    def __call__(self, S: int, worker: int = 0):
+        if (S, worker) not in self.by_width:
+            self.by_width[(S, worker)] = E.workspace(self.prob, S, self.opts, self.device)
+        return self.by_width[(S, worker)]
+
+    def stream(self, worker: int):
+        if worker not in self.streams:
+            self.streams[worker] = torch.cuda.Stream(device=self.device)
+        return self.streams[worker]
 
 
-def _solve_groups(prob, y_level, groups, opts, wss, device, spmv_acc):
+def _solve_groups(prob, y_level, groups, opts, wss, device, spmv_acc, streams: int = 1):
     """Solve each group (an id array; its length is the ensemble width) and
-    record per-sample counts and G(y) = ||u||^2."""
+    record per-sample counts and G(y) = ||u||^2.  With streams = K > 1, K
+    host threads solve the groups round-robin, each on its own HIP stream
+    with its own workspace: small ensembles leave most of the GPU idle
+    between kernels, and concurrent ensembles fill it (each ensemble's
+    arithmetic is unchanged).  ens_iters stays in group order."""
+    K = min(max(1, streams), len(groups))
+    if K > 1:
+        torch.cuda.synchronize(device)
+        accs = [[0.0, 0, 0.0, 0.0] for _ in range(K)]
+
+        def work(k):
+            with torch.cuda.stream(wss.stream(k)):
+                out = _solve_serial(prob, y_level, groups[k::K], opts,
+                                    lambda S: wss(S, k), device, accs[k])
+            wss.stream(k).synchronize()
+            return out
+
+        with ThreadPoolExecutor(K) as ex:
+            parts = list(ex.map(work, range(K)))
+        iters = np.full(len(y_level), -1, np.int64)
+        qoi = np.zeros(len(y_level))
+        ens_iters = [0] * len(groups)
+        for k, (it, q, ei) in enumerate(parts):
+            done = it >= 0
+            iters[done], qoi[done] = it[done], q[done]
+            ens_iters[k::K] = ei
+        for acc in accs:
+            for i in range(4):
+                spmv_acc[i] += acc[i]
+        return iters, qoi, ens_iters
+    return _solve_serial(prob, y_level, groups, opts, wss, device, spmv_acc)
+
+
+def _solve_serial(prob, y_level, groups, opts, wss, device, spmv_acc):
     iters = np.full(len(y_level), -1, np.int64)
     qoi = np.zeros(len(y_level))
     ens_iters = []
@@ -117,12 +157,13 @@ def _solve_groups(prob, y_level, groups, opts, wss, device, spmv_acc):
 def adaptive(prob: E.Problem, S: int, budget: int = 1024, max_level: int = 5,
              tau_rel: float = 1e-3, strategy: str = "surrogate",
              opts: Optional[E.SolverOptions] = None, perm_seed: int = 1,
-             device="cuda", widths=None, iter_seconds=None) -> UQResult:
+             device="cuda", widths=None, iter_seconds=None, streams: int = 1) -> UQResult:
     """Run the adaptive loop; every sample is solved on the GPU in ensembles
     of S, or, with strategy "variable", in ensembles of the given ``widths``
     chosen by least predicted time (``iter_seconds`` per ensemble iteration
     at each width; the surrogate predicts the counts, all counts are taken
-    equal on the first level)."""
+    equal on the first level).  ``streams`` > 1 solves that many ensembles
+    at a time on separate HIP streams."""
     opts = opts or E.SolverOptions()
     rng = np.random.default_rng(perm_seed)
     wss = _Workspaces(prob, opts, device)
@@ -157,7 +198,8 @@ def adaptive(prob: E.Problem, S: int, budget: int = 1024, max_level: int = 5,
             raise ValueError(strategy)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        iters, qoi, ens_iters = _solve_groups(prob, y_level, groups, opts, wss, device, spmv_acc)
+        iters, qoi, ens_iters = _solve_groups(prob, y_level, groups, opts, wss, device, spmv_acc,
+                                              streams)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         out.level = np.vstack([out.level, lv])
@@ -260,7 +302,8 @@ def grouping_costs(res: UQResult, S: int, perm_seed: int = 1) -> dict:
 
 def time_groupings(prob: E.Problem, res: UQResult, S: int, opts: Optional[E.SolverOptions] = None,
                    strategies=("natural", "random", "param", "its", "surrogate"),
-                   perm_seed: int = 1, device="cuda", extra: Optional[dict] = None) -> dict:
+                   perm_seed: int = 1, device="cuda", extra: Optional[dict] = None,
+                   streams: int = 1) -> dict:
     """Wall seconds to solve every sample of an adaptive run grouped by each
     strategy, assembly included ("seconds") and without the assemblies'
     device time ("solve_seconds"), and the ensemble iterations it took.
@@ -278,7 +321,7 @@ def time_groupings(prob: E.Problem, res: UQResult, S: int, opts: Optional[E.Solv
         total, start = 0, 0
         for r, groups in zip(res.levels, per[k]):
             y = res.y[start:start + r.n_samples]
-            _, _, ens_iters = _solve_groups(prob, y, groups, opts, wss, device, acc)
+            _, _, ens_iters = _solve_groups(prob, y, groups, opts, wss, device, acc, streams)
             total += sum(ens_iters)
             start += r.n_samples
         torch.cuda.synchronize()
@@ -304,7 +347,7 @@ class NonAdaptiveResult:
 
 def nonadaptive(prob: E.Problem, S: int, y: np.ndarray, train_level: int,
                 opts: Optional[E.SolverOptions] = None, solve_groups: Optional[List[int]] = None,
-                device="cuda") -> NonAdaptiveResult:
+                device="cuda", streams: int = 1) -> NonAdaptiveResult:
     """Surrogate grouping without adaptivity (paper, Section 5: pre-select
     samples, evaluate them, build the iteration surrogate, group the rest).
 
@@ -320,7 +363,7 @@ def nonadaptive(prob: E.Problem, S: int, y: np.ndarray, train_level: int,
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     it_train, _, _ = _solve_groups(prob, yt, G.chunk(list(range(len(yt))), S), opts, wss,
-                                   device, [0.0, 0, 0.0, 0.0])
+                                   device, [0.0, 0, 0.0, 0.0], streams)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     groups, pred = G.group_samples(lv, ix, it_train, y, S)
@@ -328,7 +371,7 @@ def nonadaptive(prob: E.Problem, S: int, y: np.ndarray, train_level: int,
     chosen = np.asarray([groups[k] for k in sel])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    iters, _, ens_iters = _solve_groups(prob, y, chosen, opts, wss, device, acc)
+    iters, _, ens_iters = _solve_groups(prob, y, chosen, opts, wss, device, acc, streams)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     return NonAdaptiveResult(it_train, groups, pred, iters, ens_iters, dt, t_train,

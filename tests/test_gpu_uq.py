@@ -109,3 +109,23 @@ def test_adaptive_loop_variable_widths_matches_oracle():
         x, it, _, _ = opcg.pcg(A, b, dg, rtol, 20000)
         assert abs(int(res.iters[mi]) - it) <= 1
         assert abs(res.qoi[mi] - float(x @ x)) <= 1e-9 * float(x @ x)
+
+
+def test_concurrent_streams_give_the_same_results():
+    """Ensembles solved two or three at a time on separate streams: every
+    sample's count, G and the grouping are bit for bit those of one at a
+    time (each ensemble's arithmetic does not depend on the others)."""
+    from paper_1705_02003_amd import ensemble as E
+    from paper_1705_02003_amd import uq
+    print("CASE adaptive-streams", flush=True)
+    for prob in (E.Problem(20, 4, 0, 0.4), E.Problem(9, 4, dim=3)):
+        base = uq.adaptive(prob, 4, budget=40, max_level=3, tau_rel=1e-3,
+                           opts=E.SolverOptions(rtol=1e-8))
+        for K in (2, 3):
+            res = uq.adaptive(prob, 4, budget=40, max_level=3, tau_rel=1e-3,
+                              opts=E.SolverOptions(rtol=1e-8), streams=K)
+            assert np.array_equal(res.iters, base.iters)
+            assert np.array_equal(res.qoi, base.qoi)
+            for a, b in zip(res.levels, base.levels):
+                assert np.array_equal(np.asarray(a.groups), np.asarray(b.groups))
+                assert a.ens_iters == b.ens_iters
