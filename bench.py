@@ -545,9 +545,11 @@ def fe3d_mode(args) -> int:
         r = {"sample_solves_per_s": round(len(ys) / res.solve_seconds, 2),
              "solve_seconds": round(res.solve_seconds, 3),
              "iters": [int(its.min()), int(its.max())], "sum_ens_iters": int(sum(res.ens_iters)),
-             "R": round(S * sum(res.ens_iters) / float(its.sum()), 4),
-             "step_avg_us": round(us, 2),
-             "step_alg_GBs": round(rows * step_bytes / (us * 1e-6) / 1e9, 1)}
+             "R": round(S * sum(res.ens_iters) / float(its.sum()), 4)}
+        if K == 1:
+            # (with concurrent ensembles the timed launches overlap others' work)
+            r["step_avg_us"] = round(us, 2)
+            r["step_alg_GBs"] = round(rows * step_bytes / (us * 1e-6) / 1e9, 1)
         if pre == "jacobi":
             r["iteration_alg_GBs"] = round(sum(res.ens_iters) * rows * iter_bytes
                                            / res.solve_seconds / 1e9, 1)
