@@ -133,3 +133,30 @@ def test_param_indicator():
     ac = fe3d.element_coefficients(y, m)
     ratios = [np.linalg.eigvalsh(np.diag([a, fe3d.A_Y, fe3d.A_Z])) for a in ac.reshape(-1)]
     assert fe3d.param_indicator(y, m) == pytest.approx(max(r[-1] / r[0] for r in ratios), rel=1e-15)
+
+
+def test_anisotropic_stencil_closed_form():
+    # constant coefficients: the assembled stencil is the tensor product of
+    # the 1-D stencils K = (-1, 2, -1) / h and M = (1, 4, 1) h / 6:
+    # a0 K(di) M(dj) M(dk) + ay M(di) K(dj) M(dk) + az M(di) M(dj) K(dk)
+    m, a0, ay, az = 5, 0.3, 2.0, 5.0
+    h = 1.0 / (m + 1)
+    V = fe3d.slot_values(fe3d.assemble_from_cells(np.full((m + 1,) * 3, a0), m, ay, az), m)
+    K = {-1: -1.0 / h, 0: 2.0 / h, 1: -1.0 / h}
+    M = {-1: h / 6, 0: 4 * h / 6, 1: h / 6}
+    r = (2 * m + 2) * m + 2
+    for s, (di, dj, dk) in enumerate(fe3d.SLOT_OFFSETS):
+        want = a0 * K[di] * M[dj] * M[dk] + ay * M[di] * K[dj] * M[dk] + az * M[di] * M[dj] * K[dk]
+        assert V[s, r] == pytest.approx(want, abs=1e-14)
+
+
+def test_cell_coefficients_are_taken_at_cube_centres():
+    # the leading KL term is even about 1/2 in every direction, so with only
+    # that term the cube-centre values are mirror-symmetric along each axis;
+    # the second term (odd along z) flips sign under the z mirror
+    m = 6
+    a1 = fe3d.element_coefficients(np.array([0.8, 0.0, 0.0, 0.0]), m)
+    for ax in range(3):
+        np.testing.assert_allclose(a1, np.flip(a1, axis=ax), rtol=1e-13)
+    g2 = np.log(fe3d.element_coefficients(np.array([0.0, 0.6, 0.0, 0.0]), m) - fe3d.A_MIN)
+    np.testing.assert_allclose(g2, -np.flip(g2, axis=0), atol=1e-13)
