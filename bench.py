@@ -104,11 +104,13 @@ def cpu_baseline(procs: int):
         out = pool.map(_oracle_one, ys)
     wall = time.perf_counter() - t0
     its = [o[1] for o in out]
+    solve_s = sum(o[0] for o in out)
     return {
         "value": round(len(ys) / wall, 4),
         "unit": "sample-solves/s",
         "cores": procs,
         "kind": "oracle",
+        "ms_per_iteration": round(1e3 * solve_s / sum(its), 3),
         "sample": (f"{len(ys)} samples (level-1 grid then level-2 nodes, generation order), "
                    f"one FP64 scipy Jacobi-PCG solve per process at {N_GRID}x{N_GRID}, "
                    f"rtol {RTOL}; iterations {min(its)}-{max(its)}; wall {wall:.1f} s"),
