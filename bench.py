@@ -587,7 +587,8 @@ def batch_mode(args) -> int:
     d = 8 coefficient model (seed 3), Jacobi-PCG rtol 1e-8, solved together by
     the graph-replayed batched solver.  Launch shapes (member tile width, tile
     height) come from the autotuner (untimed).  Reports total sample-solves/s
-    and p50 / p99 of the per-ensemble retirement latency."""
+    and p50 / p99 of the per-ensemble retirement latency.  --wave-gb G solves
+    the ensembles smallest first in waves of at most G GB per CG iteration."""
     import numpy as np
     import torch
     import workloads
@@ -612,13 +613,14 @@ def batch_mode(args) -> int:
     opts = E.SolverOptions(rtol=w.rtol, max_iter=w.max_iter, full_stencil=FULL_STENCIL)
     torch.cuda.synchronize()
     t = time.perf_counter()
-    res = E.batch_solve(items, opts)
+    res = E.batch_solve(items, opts, max_wave_bytes=args.wave_gb * 1e9 if args.wave_gb > 0 else None)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
     lat = np.array([r.seconds for r in res])
     n_samples = int(sum(widths))
     rows = sum(r.ens_iters * it["prob"].rows * int(it["b"].shape[1]) for r, it in zip(res, items))
     out = {"mode": "batch", "workload": w.name, "ensembles": k, "samples": n_samples,
+           "wave_gb": args.wave_gb or None,
            "seconds": round(dt, 3), "sample_solves_per_s": round(n_samples / dt, 3),
            "latency_p50_s": round(float(np.percentile(lat, 50)), 4),
            "latency_p99_s": round(float(np.percentile(lat, 99)), 4),
@@ -660,6 +662,9 @@ def main() -> int:
                          "copy, for hardware-counter runs")
     ap.add_argument("--iters", type=int, default=100, help="iterations in --mode kernel")
     ap.add_argument("--S-list", default="4,8,16,32,64", help="ensemble widths in --mode table")
+    ap.add_argument("--wave-gb", type=float, default=0.0,
+                    help="--mode batch: smallest-first waves of at most this many GB per CG "
+                         "iteration (0: all ensembles in one batch)")
     ap.add_argument("--streams", type=int, default=0,
                     help="ensembles solved at a time on separate HIP streams (0: 2 in --mode fe3d, "
                          "else 1)")

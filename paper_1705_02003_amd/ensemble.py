@@ -8,6 +8,7 @@ library is missing or no GPU is present, calls raise.
 from __future__ import annotations
 
 import ctypes as C
+import time
 from dataclasses import dataclass
 from typing import NamedTuple, Optional
 
@@ -312,12 +313,39 @@ class BatchResult(NamedTuple):
     seconds: float           # device time from the batch start to this ensemble's retirement
 
 
-def batch_solve(items, opts: Optional[SolverOptions] = None, batch_ws: Optional[torch.Tensor] = None):
+def batch_solve(items, opts: Optional[SolverOptions] = None, batch_ws: Optional[torch.Tensor] = None,
+                max_wave_bytes: Optional[float] = None):
     """Solve several ensembles together (ens_batch_solve).
 
     ``items``: sequence of dicts with keys ``prob`` (Problem), ``V``, ``b`` and
     optionally ``x``, ``ws`` (a Jacobi workspace of that ensemble) and
-    ``tile_lines``.  Returns one BatchResult per item."""
+    ``tile_lines``.  Returns one BatchResult per item, in item order.
+
+    ``max_wave_bytes``: solve the ensembles in waves instead of all at once,
+    smallest first: ensembles sorted by the bytes one CG iteration moves
+    (120 B per member-row) and packed greedily into waves of at most that
+    many bytes (a larger ensemble forms a wave of its own).  The total time
+    stays about the same, but the small ensembles retire early.  A result's
+    ``seconds`` then counts from the start of the first wave."""
+    if max_wave_bytes is not None and len(items) > 1:
+        cost = [120 * it["prob"].rows * _ensemble_width(it["b"]) for it in items]
+        order = sorted(range(len(items)), key=lambda i: (cost[i], i))
+        waves, cur, tot = [], [], 0
+        for i in order:
+            if cur and tot + cost[i] > max_wave_bytes:
+                waves.append(cur)
+                cur, tot = [], 0
+            cur.append(i)
+            tot += cost[i]
+        waves.append(cur)
+        out = [None] * len(items)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for wv in waves:
+            start = time.perf_counter() - t0
+            for i, r in zip(wv, batch_solve([items[i] for i in wv], opts, batch_ws)):
+                out[i] = r._replace(seconds=start + r.seconds)
+        return out
     opts = opts or SolverOptions()
     n = len(items)
     if n == 0:

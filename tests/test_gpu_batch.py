@@ -101,3 +101,26 @@ def test_batch_symmetric_sweep_bitwise():
     for a, b in zip(r1, r2):
         assert np.array_equal(a.iters, b.iters)
         assert torch.equal(a.x, b.x)
+
+
+def test_batch_in_waves_matches_single_solves():
+    """Smallest-first waves (max_wave_bytes): every ensemble still reproduces
+    its single solve, results come back in item order, and each ensemble's
+    retirement time counts from the first wave's start."""
+    from paper_1705_02003_amd import ensemble as E
+    items, _ = make_batch(seed=2)
+    print("CASE batch waves", MIX, flush=True)
+    cost = [120 * it["prob"].rows * int(it["b"].shape[1]) for it in items]
+    res = E.batch_solve(items, E.SolverOptions(rtol=1e-8), max_wave_bytes=2.5 * min(cost))
+    assert len(res) == len(items)
+    for it, r in zip(items, res):
+        single = E.solve(it["prob"], it["V"], it["b"], E.SolverOptions(rtol=1e-8))
+        assert r.x.shape == single.x.shape
+        assert np.all(r.status == 0)
+        assert np.all(np.abs(r.iters - single.iters) <= 1)
+        same = r.iters == single.iters
+        num = torch.linalg.norm(r.x - single.x, dim=0).cpu().numpy()
+        den = torch.linalg.norm(single.x, dim=0).cpu().numpy()
+        assert np.all((num / den)[same] <= 1e-9)
+    # the smallest ensemble is in the first wave, the largest in the last
+    assert res[int(np.argmin(cost))].seconds <= res[int(np.argmax(cost))].seconds
