@@ -129,3 +129,28 @@ def test_concurrent_streams_give_the_same_results():
             for a, b in zip(res.levels, base.levels):
                 assert np.array_equal(np.asarray(a.groups), np.asarray(b.groups))
                 assert a.ens_iters == b.ens_iters
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_adaptive_loop_param_strategy(dim):
+    """Parameter-based grouping (Section 3.2) in the loop: each level's
+    ensembles are the (H, generation index) order cut into S, with H the
+    oracle's indicator (the library's H agrees to 1e-13; ties or near-ties
+    are not present at these samples)."""
+    from oracle import fe3d as ofe
+    from oracle import problem as oprob2
+    from paper_1705_02003_amd import ensemble as E
+    from paper_1705_02003_amd import uq
+    print(f"CASE adaptive-param dim={dim}", flush=True)
+    prob = E.Problem(16, 4, 0, 0.4) if dim == 2 else E.Problem(7, 4, dim=3)
+    res = uq.adaptive(prob, 4, budget=45, max_level=3, tau_rel=1e-3, strategy="param",
+                      opts=E.SolverOptions(rtol=1e-8))
+    start = 0
+    for rec in res.levels:
+        ys = res.y[start:start + rec.n_samples]
+        h = np.array([oprob2.param_indicator(y, 0) if dim == 2 else ofe.param_indicator(y, prob.n)
+                      for y in ys])
+        np.testing.assert_allclose(res.hind[start:start + rec.n_samples], h, rtol=1e-13)
+        want = sg.chunk(sorted(range(rec.n_samples), key=lambda i: (res.hind[start + i], i)), 4)
+        assert rec.groups.tolist() == want
+        start += rec.n_samples
