@@ -133,10 +133,10 @@ def test_concurrent_streams_give_the_same_results():
 
 @pytest.mark.parametrize("dim", [2, 3])
 def test_adaptive_loop_param_strategy(dim):
-    """Parameter-based grouping (Section 3.2) in the loop: each level's
-    ensembles are the (H, generation index) order cut into S, with H the
-    oracle's indicator (the library's H agrees to 1e-13; ties or near-ties
-    are not present at these samples)."""
+    """Parameter-based grouping (Section 3.2) in the loop: the library's H
+    agrees with the oracle's indicator to 1e-13, and each level's ensembles
+    are the (H, generation index) order cut into S (sparse-grid samples share
+    coordinates, so exact ties occur and fall back to generation order)."""
     from oracle import fe3d as ofe
     from oracle import problem as oprob2
     from paper_1705_02003_amd import ensemble as E
