@@ -92,8 +92,8 @@ extern "C" {
  * from the exponential kernel's transcendental equations), ordered by
  * decreasing lambda, ties by their 1-D mode indices (x, y, z).
  * N_r = n^3 rows (x fastest), 27 matrix slots 9 (dz+1) + 3 (dy+1) + (dx+1)
- * (13 = diagonal); eps_model and amp must be 0, 1 <= d <= 16.  The adjoint
- * entry points and the batched solver take the 2-D model only. */
+ * (13 = diagonal); eps_model and amp must be 0, 1 <= d <= 16.  The batched
+ * solver takes the 2-D model only. */
 typedef struct {
   int32_t n;          /* interior points per dimension, 2 <= n            */
   int32_t d;          /* parameters per member, 2 <= d <= 16 (3-D: 1..16) */
@@ -238,7 +238,9 @@ int ens_param_indicator(const ens_problem* prob, int32_t S, const double* y_dev,
  * In: y_dev [S][d], V_dev (assembled for y), u_dev [N_r][S] (forward
  * solution), w_dev [N_r] (shared QoI weights).  Out: lambda_dev [N_r][S],
  * grad_host [S][d], iters_host[S], status_host[S] of the adjoint solve.
- * 2-D model only (ENS_ENOTSUP for dim = 3).  Blocking. */
+ * 3-D model: only a depends on y; on cube c, da_c/dy_j = a_hat exp(g_c)
+ * sqrt(lambda_j) b_j(x_c), and the form is the sum over cubes of that
+ * derivative times lambda_c^T (Kx My Mz) u_c.  Blocking. */
 int ens_adjoint_grad(const ens_problem* prob, const ens_opts* opts, int32_t S,
                      const double* y_dev, const double* V_dev, const double* u_dev,
                      const double* w_dev, double* lambda_dev, double* grad_host,
@@ -246,7 +248,7 @@ int ens_adjoint_grad(const ens_problem* prob, const ens_opts* opts, int32_t S,
                      void* ws_dev, size_t ws_bytes, void* stream);
 
 /* The dQ/dy kernel alone: grad_host[s][j] = -lambda_s^T (dA_s/dy_j) u_s for
- * given u and lambda.  2-D model only (ENS_ENOTSUP for dim = 3).  Blocking. */
+ * given u and lambda (both models).  Blocking. */
 int ens_dqdy(const ens_problem* prob, int32_t S, const double* y_dev,
              const double* u_dev, const double* lambda_dev, double* grad_host,
              void* ws_dev, size_t ws_bytes, void* stream);

@@ -36,6 +36,7 @@ from typing import List, Tuple
 
 import numpy as np
 import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 from scipy.optimize import brentq
 
 SIGMA0 = math.sqrt(300.0)
@@ -89,12 +90,15 @@ def kl_3d(N: int):
 
 
 def element_coefficients(y, m: int) -> np.ndarray:
-    """a at the centroid of every cell, shape (m+1, m+1, m+1) indexed [ez, ey, ex]."""
-    y = np.asarray(y, dtype=np.float64)
+    """a at the centroid of every cell, shape (m+1, m+1, m+1) indexed [ez, ey, ex]
+    (complex y gives complex a, for complex-step derivatives)."""
+    y = np.asarray(y)
+    if not np.iscomplexobj(y):
+        y = y.astype(np.float64)
     terms, m1 = kl_3d(len(y))
     h = 1.0 / (m + 1)
     xc = (np.arange(m + 1) + 0.5) * h
-    g = np.zeros((m + 1, m + 1, m + 1))
+    g = np.zeros((m + 1, m + 1, m + 1), dtype=y.dtype)
     for (sq, (p, q, r)), yn in zip(terms, y):
         bx, by, bz = phi_1d(m1[p], xc), phi_1d(m1[q], xc), phi_1d(m1[r], xc)
         g = g + sq * yn * (bz[:, None, None] * by[None, :, None] * bx[None, None, :])
@@ -110,7 +114,7 @@ def element_matrix(ae: float, ay: float, az: float, h: float) -> np.ndarray:
     (lx, ly, lz) in {0, 1}^3 has index lx + 2 ly + 4 lz."""
     K1 = np.array([[1.0, -1.0], [-1.0, 1.0]]) / h
     M1 = np.array([[2.0, 1.0], [1.0, 2.0]]) * h / 6.0
-    Ke = np.zeros((8, 8))
+    Ke = np.zeros((8, 8), dtype=np.result_type(ae, ay, az, 1.0))
     for a_, b_ in itertools.product(range(8), repeat=2):
         ax, ay_, az_ = a_ & 1, (a_ >> 1) & 1, a_ >> 2
         bx, by, bz = b_ & 1, (b_ >> 1) & 1, b_ >> 2
@@ -140,12 +144,12 @@ def assemble_from_cells(acell: np.ndarray, m: int, ay: float = A_Y, az: float = 
         for a_, b_ in itertools.product(range(8), repeat=2):
             if ids[a_] >= 0 and ids[b_] >= 0:
                 key = (ids[a_], ids[b_])
-                acc[key] = acc[key] + float(Ke[a_, b_]) if key in acc else float(Ke[a_, b_])
+                acc[key] = acc[key] + Ke[a_, b_] if key in acc else Ke[a_, b_]
     N = m ** 3
     rows = np.array([k[0] for k in acc], dtype=np.int64)
     cols = np.array([k[1] for k in acc], dtype=np.int64)
     vals = np.array(list(acc.values()))
-    return sp.csr_matrix((vals, (rows, cols)), shape=(N, N))
+    return sp.csr_matrix((vals, (rows, cols)), shape=(N, N), dtype=vals.dtype)
 
 
 def rhs(m: int) -> np.ndarray:
@@ -182,3 +186,64 @@ def param_indicator(y, m: int) -> float:
     hi = np.maximum(np.maximum(ac, A_Y), A_Z)
     lo = np.minimum(np.minimum(ac, A_Y), A_Z)
     return float(np.max(hi / lo))
+
+
+# ------------------------------------------------------------ adjoint
+def qoi_weights(m: int) -> np.ndarray:
+    """w with w_r = 1/|B| on the interior nodes of [0.4, 0.6]^3, else 0; a
+    node index i (1-based) is inside when 2(m+1) <= 5i <= 3(m+1), decided in
+    integers, the same in every direction (Section 2.1: a spatial mean of u)."""
+    i = np.arange(1, m + 1)
+    inside = (5 * i >= 2 * (m + 1)) & (5 * i <= 3 * (m + 1))
+    mask = (inside[:, None, None] & inside[None, :, None] & inside[None, None, :]).reshape(-1)
+    w = np.zeros(m ** 3)
+    w[mask] = 1.0 / float(mask.sum())
+    return w
+
+
+def dA_bilinear(lam, u, y, m: int) -> np.ndarray:
+    """lambda^T (dA/dy_j) u for j = 0..d-1.  Only a depends on y; on cube c,
+    da_c/dy_j = a_hat exp(g_c) sqrt(lambda_j) b_j(x_c) = (a_c - a_min)
+    sqrt(lambda_j) b_j(x_c), and the part of the cube matrix that a
+    multiplies is Kx My Mz, so the form is the sum over cubes of that
+    derivative times lambda_c^T (Kx My Mz) u_c (nodal values, 0 on the
+    boundary)."""
+    y = np.asarray(y, dtype=np.float64)
+    terms, m1 = kl_3d(len(y))
+    h = 1.0 / (m + 1)
+    xc = (np.arange(m + 1) + 0.5) * h
+    eg = element_coefficients(y, m) - A_MIN
+    Kc = element_matrix(1.0, 0.0, 0.0, h)
+    Lp = np.zeros((m + 2,) * 3)
+    Up = np.zeros((m + 2,) * 3)
+    Lp[1:-1, 1:-1, 1:-1] = np.asarray(lam).reshape(m, m, m)
+    Up[1:-1, 1:-1, 1:-1] = np.asarray(u).reshape(m, m, m)
+    # the eight local nodal values of every cube, local index lx + 2 ly + 4 lz
+    loc = lambda P, l: P[(l >> 2):(l >> 2) + m + 1, ((l >> 1) & 1):((l >> 1) & 1) + m + 1, (l & 1):(l & 1) + m + 1]
+    B = np.zeros((m + 1,) * 3)
+    for a_, b_ in itertools.product(range(8), repeat=2):
+        B = B + loc(Lp, a_) * Kc[a_, b_] * loc(Up, b_)
+    out = np.zeros(len(y))
+    for j, (sq, (p, q, r)) in enumerate(terms):
+        bj = phi_1d(m1[r], xc)[:, None, None] * phi_1d(m1[q], xc)[None, :, None] * phi_1d(m1[p], xc)[None, None, :]
+        out[j] = float(np.sum(eg * sq * bj * B))
+    return out
+
+
+def qoi_and_grad(y, m: int):
+    """(Q, dQ/dy, u, lambda) with direct sparse solves (exact to round-off)."""
+    A, b, _ = assemble(y, m)
+    w = qoi_weights(m)
+    lu = spla.splu(A.tocsc())
+    u = lu.solve(b)
+    lam = lu.solve(w)
+    return float(w @ u), -dA_bilinear(lam, u, y, m), u, lam
+
+
+def qoi_complex_step(y, m: int, j: int, h: float = 1e-30) -> float:
+    """dQ/dy_j = Im Q(y + i h e_j) / h with a complex sparse direct solve."""
+    yc = np.asarray(y, dtype=np.complex128).copy()
+    yc[j] += 1j * h
+    A = assemble_from_cells(element_coefficients(yc, m), m)
+    u = spla.splu(A.tocsc()).solve(rhs(m).astype(np.complex128))
+    return float(np.imag(qoi_weights(m) @ u)) / h

@@ -1,7 +1,8 @@
 """torch.autograd.Function for the ensemble QoI and its adjoint gradient.
 
-Q_s(y_s) = w^T u_s with A(y_s) u_s = 1 and w the mean over the interior
-nodes of [0.4, 0.6]^2 (the paper's QoI is a spatial mean of u, Section 2.1).
+Q_s(y_s) = w^T u_s with A(y_s) u_s = f and w the mean over the interior
+nodes of [0.4, 0.6]^2 (3-D model: [0.4, 0.6]^3; the paper's QoI is a
+spatial mean of u, Section 2.1).
 Forward: ensemble assembly + ensemble PCG + per-member dot.  Backward: the
 adjoint ensemble PCG A lambda = w (A is symmetric) on the same matrix values,
 then dQ/dy_j = -lambda^T (dA/dy_j) u from the dQ/dy kernel.  All of it runs in
@@ -29,7 +30,7 @@ class EnsembleQoI(torch.autograd.Function):
         res = E.solve(prob, V, b, opts, ws=ws)
         if np.any(res.status != 0):
             raise RuntimeError(f"forward solve did not converge: status {res.status.tolist()}")
-        w = E.qoi_weights(prob.n, device=y.device)
+        w = E.qoi_weights(prob.n, device=y.device, dim=prob.dim)
         Q = E.member_dot(res.x, w, ws=ws)
         ctx.save_for_backward(y)
         ctx.cache = (prob, opts, V, res.x, w, ws)

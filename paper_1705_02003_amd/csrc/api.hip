@@ -644,6 +644,53 @@ int ens_member_dot(int32_t N_r, int32_t S, const double* a_dev, const double* b_
   return ENS_OK;
 }
 
+// 3-D model: grad_host[s][j] = -lambda_s^T (dA_s/dy_j) u_s (cube by cube)
+static int dqdy3(const ens_problem* prob, int32_t S, const double* y_dev, const double* u_dev,
+                 const double* lambda_dev, double* grad_host, void* ws_dev, void* stream) {
+  const Workspace w = carve_workspace(ws_dev, 0, S, false);
+  Fe3dDqdyArgs a;
+  std::memset(&a, 0, sizeof(a));
+  Fe3dAsmArgs f;
+  std::memset(&f, 0, sizeof(f));
+  int rc = fe3d_setup(prob, f);
+  if (rc) return rc;
+  std::memcpy(a.term, f.term, sizeof(a.term));
+  a.y = y_dev;
+  a.u = u_dev;
+  a.lam = lambda_dev;
+  a.partial = w.partial;
+  a.m = prob->n;
+  a.S = S;
+  a.logS = log2i(S);
+  a.d = prob->d;
+  a.ncell = (size_t)(prob->n + 1) * (prob->n + 1) * (prob->n + 1);
+  // d <= 16 partial arrays of groups * S doubles must fit the partial buffer
+  const int groups = (int)std::min<size_t>((a.ncell * S + kNT - 1) / kNT,
+                                           (size_t)(3 * kMaxGroups / kMaxTerms));
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHECK(hipMemsetAsync(w.m.ctl, 0, sizeof(int) * CTL_COUNT, s));
+  launch_fe3d_dqdy(a, groups, s);
+  {
+    FinishArgs fa;
+    std::memset(&fa, 0, sizeof(fa));
+    fa.partial = w.partial;
+    fa.G = groups;
+    fa.kind = F_SUMS;
+    fa.m = w.m;
+    fa.g = make_geometry(2, S, 0, 0);
+    fa.nsum = prob->d;
+    fa.scale = -1.0;
+    launch_finish(fa, s);
+  }
+  HIPCHECK(hipGetLastError());
+  double res[kMaxS * 16];
+  HIPCHECK(hipMemcpyAsync(res, w.m.result, sizeof(double) * S * 16, hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  for (int k = 0; k < S; ++k)
+    for (int j = 0; j < prob->d; ++j) grad_host[(size_t)k * prob->d + j] = res[k * 16 + j];
+  return ENS_OK;
+}
+
 int ens_param_indicator(const ens_problem* prob, int32_t S, const double* y_dev, double* h_host,
                         void* ws_dev, size_t ws_bytes, void* stream) {
   int rc = check_problem(prob);
@@ -698,8 +745,8 @@ int ens_dqdy(const ens_problem* prob, int32_t S, const double* y_dev, const doub
   int rc = check_problem(prob);
   if (rc) return rc;
   if (!valid_S(S) || !y_dev || !u_dev || !lambda_dev || !grad_host || !ws_dev) return ENS_EINVAL;
-  if (is3d(prob)) return ENS_ENOTSUP;
   if (ws_bytes < header_bytes()) return ENS_ENOMEM;
+  if (is3d(prob)) return dqdy3(prob, S, y_dev, u_dev, lambda_dev, grad_host, ws_dev, stream);
   const Workspace w = carve_workspace(ws_dev, 0, S, false);
   const Geometry g = make_geometry(prob->n, S, 0, 0);
   hipStream_t s = (hipStream_t)stream;
@@ -750,7 +797,6 @@ int ens_adjoint_grad(const ens_problem* prob, const ens_opts* opts, int32_t S, c
   if (rc) return rc;
   if (!valid_S(S) || !y_dev || !V_dev || !u_dev || !w_dev || !lambda_dev || !grad_host || !ws_dev)
     return ENS_EINVAL;
-  if (is3d(prob)) return ENS_ENOTSUP;
   const bool cheb = o.precond == ENS_PRECOND_CHEBYSHEV;
   if (ws_bytes < workspace_bytes(rows_of(prob), S, cheb)) return ENS_ENOMEM;
   const Workspace w = carve_workspace(ws_dev, rows_of(prob), S, cheb);

@@ -158,6 +158,17 @@ struct DqdyArgs {
 enum Finish { F_ALPHA = 0, F_UPDATE_J = 1, F_UPDATE_C = 2, F_CHEB = 3, F_INIT = 4, F_DOT = 5, F_SUMS = 6,
               F_MAX = 7 };
 
+// 3-D model: lambda^T (dA/dy_j) u per member (the adjoint gradient's form)
+struct Fe3dDqdyArgs {
+  const double* y;    // [S][d]
+  const double* u;    // [N_r][S]
+  const double* lam;  // [N_r][S]
+  double* partial;    // [d][groups][S]
+  int m, S, logS, d;
+  size_t ncell;       // (m+1)^3 cubes
+  Fe3dTerm term[kMaxTerms];
+};
+
 // Parameter-based grouping indicator (both models): per member the largest
 // ratio lambda_max / lambda_min of the diffusion tensor over the domain.
 struct IndArgs {
@@ -211,6 +222,7 @@ Geometry make_geometry3(int m, int S);
 int fe3d_setup(const ens_problem* p, Fe3dAsmArgs& a);
 void launch_fe3d_assemble(const Fe3dAsmArgs& a, hipStream_t s);
 void launch_indicator(const IndArgs& a, int groups, hipStream_t s);
+void launch_fe3d_dqdy(const Fe3dDqdyArgs& a, int groups, hipStream_t s);
 template <int MODE>
 void launch_fe3d(const StencilArgs& a, hipStream_t s);
 // Elements from the start of one matrix slot (or workspace vector) to the

@@ -218,6 +218,84 @@ __global__ __launch_bounds__(kNT) void indicator_kernel(IndArgs a) {
   put_partial<1>(a.partial, S, S, hv);
 }
 
+// ------------------------------------------------------------ adjoint form
+// lambda^T (dA/dy_j) u for every member and j < d.  Only a depends on y:
+// on cube c, da_c/dy_j = a_hat exp(g_c) sqrt(lambda_j) b_j(x_c), and a
+// multiplies the cube matrix Kx My Mz, so the form is the sum over cubes of
+// that derivative times lambda_c^T (Kx My Mz) u_c over the cube's eight
+// nodes (boundary nodes hold 0).  One thread per (cube, member),
+// grid-strided; per-workgroup sums per member for each j.
+__global__ __launch_bounds__(kNT) void fe3d_dqdy_kernel(Fe3dDqdyArgs a) {
+  __shared__ double red[kWaves * 64 * 2];
+  const int S = a.S, t = threadIdx.x, s = t & (S - 1), m = a.m, mc = m + 1;
+  const double* y = a.y + (size_t)s * a.d;
+  const double h = 1.0 / (double)mc;
+  const double kd = 1.0 / h, ko = -1.0 / h, md = (2.0 * h) / 6.0, mo = (1.0 * h) / 6.0;
+  double acc[kMaxTerms];
+#pragma unroll
+  for (int q = 0; q < kMaxTerms; ++q) acc[q] = 0.0;
+  const size_t total = a.ncell * S;
+  const size_t stride = (size_t)gridDim.x * kNT;
+  for (size_t e = (size_t)blockIdx.x * kNT + t; e < total; e += stride) {
+    const size_t c = e >> a.logS;
+    const int cx = (int)(c % mc), cy = (int)((c / mc) % mc), cz = (int)(c / ((size_t)mc * mc));
+    // nodal values of lambda and u at the cube's corners (mesh node
+    // (cx + lx, cy + ly, cz + lz); interior when 1 <= index <= m)
+    double lv[8], uv[8];
+#pragma unroll
+    for (int l = 0; l < 8; ++l) {
+      const int I = cx + (l & 1), J = cy + ((l >> 1) & 1), K = cz + (l >> 2);
+      const bool in = I >= 1 && I <= m && J >= 1 && J <= m && K >= 1 && K <= m;
+      const size_t row = in ? ((size_t)(K - 1) * m + (J - 1)) * m + (I - 1) : 0;
+      const double lx = a.lam[row * S + s], ux = a.u[row * S + s];
+      lv[l] = in ? lx : 0.0;
+      uv[l] = in ? ux : 0.0;
+    }
+    double B = 0.0;
+#pragma unroll
+    for (int p = 0; p < 8; ++p)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const double kx = ((p & 1) == (q & 1)) ? kd : ko;
+        const double my = (((p >> 1) & 1) == ((q >> 1) & 1)) ? md : mo;
+        const double mz = ((p >> 2) == (q >> 2)) ? md : mo;
+        B = B + lv[p] * (kx * my * mz) * uv[q];
+      }
+    const double xc = ((double)cx + 0.5) * h, yc = ((double)cy + 0.5) * h, zc = ((double)cz + 0.5) * h;
+    double bj[kMaxTerms];
+    double g = 0.0;
+#pragma unroll
+    for (int n = 0; n < kMaxTerms; ++n) {
+      bj[n] = 0.0;
+      if (n < a.d) {
+        const Fe3dTerm& f = a.term[n];
+        const double bx = phi1(f.kind[0], f.w[0], f.norm[0], xc);
+        const double by = phi1(f.kind[1], f.w[1], f.norm[1], yc);
+        const double bz = phi1(f.kind[2], f.w[2], f.norm[2], zc);
+        bj[n] = (bz * by) * bx;
+        g = g + (f.sq * y[n]) * bj[n];
+      }
+    }
+    const double eg = kAhat * exp(g);
+#pragma unroll
+    for (int n = 0; n < kMaxTerms; ++n)
+      if (n < a.d) acc[n] += eg * a.term[n].sq * bj[n] * B;
+  }
+  const size_t ps = (size_t)gridDim.x * S;
+#pragma unroll
+  for (int q = 0; q < kMaxTerms; ++q) {
+    if (q < a.d) {
+      double v[1] = {acc[q]};
+      group_reduce<1>(v, S, red);
+      put_partial<1>(a.partial + q * ps, S, S, v);
+    }
+  }
+}
+
+void launch_fe3d_dqdy(const Fe3dDqdyArgs& a, int groups, hipStream_t s) {
+  hipLaunchKernelGGL(fe3d_dqdy_kernel, dim3(groups), dim3(kNT), 0, s, a);
+}
+
 void launch_indicator(const IndArgs& a, int groups, hipStream_t s) {
   hipLaunchKernelGGL(indicator_kernel, dim3(groups), dim3(kNT), 0, s, a);
 }

@@ -294,12 +294,16 @@ def adjoint_grad(prob: Problem, y: torch.Tensor, V: torch.Tensor, u: torch.Tenso
     return lam, g, iters, status
 
 
-def qoi_weights(n: int, device=None) -> torch.Tensor:
-    """Mean over the interior nodes of [0.4, 0.6]^2 (decided in integers:
-    2(n+1) <= 5 i <= 3(n+1) for the 1-based node index i, same for j)."""
+def qoi_weights(n: int, device=None, dim: int = 2) -> torch.Tensor:
+    """Mean over the interior nodes of [0.4, 0.6]^dim (decided in integers:
+    2(n+1) <= 5 i <= 3(n+1) for the 1-based node index i in each direction),
+    in row order (x fastest)."""
     i = np.arange(1, n + 1)
     inside = (5 * i >= 2 * (n + 1)) & (5 * i <= 3 * (n + 1))
-    m = np.outer(inside, inside).reshape(-1)
+    m = inside
+    for _ in range(dim - 1):
+        m = np.multiply.outer(inside, m)
+    m = m.reshape(-1)
     w = np.where(m, 1.0 / m.sum(), 0.0)
     return torch.tensor(w, dtype=torch.float64, device=device or "cuda")
 

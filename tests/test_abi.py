@@ -305,8 +305,8 @@ def test_group_variable_rejects_bad_arguments(L):
 
 def test_3d_model_descriptor_without_gpu(L):
     """dim = 3: slot stride and workspace over n^3 rows, descriptor limits,
-    and the entry points that take the 2-D model only (no device work:
-    every call below fails validation first)."""
+    argument checks, and the batched solver's refusal of the 3-D model (no
+    device work: every call below fails validation first)."""
     lib = L.lib()
     o = L.ens_opts()
     for n, S in ((31, 32), (10, 1), (64, 16)):
@@ -331,11 +331,9 @@ def test_3d_model_descriptor_without_gpu(L):
     a = C.c_void_p(4096)
     g = np.zeros(64)
     assert lib.ens_assemble_ensemble(C.byref(p), 8, None, a, a, None) == L.ENS_EINVAL
-    assert lib.ens_dqdy(C.byref(p), 8, a, a, a, g.ctypes.data_as(L.f64p), a, 1 << 30,
-                        None) == L.ENS_ENOTSUP
-    assert lib.ens_adjoint_grad(C.byref(p), C.byref(o), 8, a, a, a, a, a,
-                                g.ctypes.data_as(L.f64p), None, None, a, 1 << 40,
-                                None) == L.ENS_ENOTSUP
+    assert lib.ens_dqdy(C.byref(p), 8, a, a, None, g.ctypes.data_as(L.f64p), a, 1 << 30,
+                        None) == L.ENS_EINVAL
+    assert lib.ens_dqdy(C.byref(p), 8, a, a, a, g.ctypes.data_as(L.f64p), a, 16, None) == L.ENS_ENOMEM
     nb = lib.ens_batch_workspace_bytes(1)
     items = (L.ens_batch_item * 1)()
     it = items[0]

@@ -160,3 +160,26 @@ def test_cell_coefficients_are_taken_at_cube_centres():
         np.testing.assert_allclose(a1, np.flip(a1, axis=ax), rtol=1e-13)
     g2 = np.log(fe3d.element_coefficients(np.array([0.0, 0.6, 0.0, 0.0]), m) - fe3d.A_MIN)
     np.testing.assert_allclose(g2, -np.flip(g2, axis=0), atol=1e-13)
+
+
+@pytest.mark.parametrize("y", [[0.4, -0.7, 0.2, 0.9], [-0.9, 0.5, -0.3, 0.1, 0.8, -0.6]])
+def test_adjoint_gradient_matches_complex_step(y):
+    # Im Q(y + i h e_j) / h with a complex sparse direct solve is exact to
+    # round-off; the adjoint form must agree to round-off
+    y = np.asarray(y)
+    m = 5
+    Q, g, u, lam = fe3d.qoi_and_grad(y, m)
+    cs = np.array([fe3d.qoi_complex_step(y, m, j) for j in range(len(y))])
+    assert np.max(np.abs(g - cs)) <= 1e-12 * np.max(np.abs(cs))
+    # lambda^T b = w^T u = Q
+    A, b, _ = fe3d.assemble(y, m)
+    assert lam @ b == pytest.approx(Q, rel=1e-13)
+
+
+def test_qoi_weights_window():
+    for m in (9, 14, 31):
+        w = fe3d.qoi_weights(m).reshape(m, m, m)
+        x = np.arange(1, m + 1) / (m + 1)
+        inside = (x >= 0.4 - 1e-12) & (x <= 0.6 + 1e-12)
+        assert np.array_equal(w > 0, inside[:, None, None] & inside[None, :, None] & inside[None, None, :])
+        assert w.sum() == pytest.approx(1.0, rel=1e-14)
