@@ -603,24 +603,53 @@ def batch_mode(args) -> int:
     shapes = {key: autotune.tune(*key) for key in sorted(set(zip(grids, widths)))}
     tune_s = time.perf_counter() - t0
     print(f"[bench] autotuned {len(shapes)} (n, S) shapes in {tune_s:.1f} s", flush=True)
-    items = []
-    for S, n, y in zip(widths, grids, samples):
+    # device bytes an ensemble keeps resident: matrix (9 slots), b, x and its
+    # Jacobi workspace (5 vectors); if the draw does not fit in 80 % of HBM,
+    # it is assembled and solved in residency waves, in draw order
+    def resident(S, n):
         prob = E.Problem(n, w.d, w.eps_model, w.amp)
-        V, b = E.assemble(prob, torch.tensor(y, dtype=torch.float64, device="cuda"))
-        sh = shapes[(n, S)]
-        items.append({"prob": prob, "V": V, "b": b, "tile_lines": sh["tile_lines"],
-                      "member_tile": sh["member_tile"]})
+        return 8 * (9 + 2) * E.matrix_slot_stride(prob, S) + E.workspace_bytes(prob, S)
+    cap = args.resident_gb * 2**30 if args.resident_gb > 0 else \
+        0.8 * torch.cuda.get_device_properties(0).total_memory
+    need = [resident(S, n) for S, n in zip(widths, grids)]
+    residency, cur, tot = [], [], 0
+    for i, nb in enumerate(need):
+        if cur and tot + nb > cap:
+            residency.append(cur)
+            cur, tot = [], 0
+        cur.append(i)
+        tot += nb
+    residency.append(cur)
+    print(f"[bench] draw needs {sum(need) / 2**30:.1f} GiB resident: "
+          f"{len(residency)} residency wave(s)", flush=True)
     opts = E.SolverOptions(rtol=w.rtol, max_iter=w.max_iter, full_stencil=FULL_STENCIL)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    res = E.batch_solve(items, opts, max_wave_bytes=args.wave_gb * 1e9 if args.wave_gb > 0 else None)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t
+    items, res, dt = [None] * k, [None] * k, 0.0
+    for wave in residency:
+        for i in wave:
+            S, n, y = widths[i], grids[i], samples[i]
+            prob = E.Problem(n, w.d, w.eps_model, w.amp)
+            V, b = E.assemble(prob, torch.tensor(y, dtype=torch.float64, device="cuda"))
+            sh = shapes[(n, S)]
+            items[i] = {"prob": prob, "V": V, "b": b, "tile_lines": sh["tile_lines"],
+                        "member_tile": sh["member_tile"]}
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = E.batch_solve([items[i] for i in wave], opts,
+                            max_wave_bytes=args.wave_gb * 1e9 if args.wave_gb > 0 else None)
+        torch.cuda.synchronize()
+        for i, r in zip(wave, out):
+            res[i] = r._replace(seconds=dt + r.seconds)
+        dt += time.perf_counter() - t
+        if len(residency) > 1:
+            for i in wave:
+                items[i] = {"prob": items[i]["prob"], "b_shape": tuple(items[i]["b"].shape)}
+            torch.cuda.empty_cache()
     lat = np.array([r.seconds for r in res])
     n_samples = int(sum(widths))
-    rows = sum(r.ens_iters * it["prob"].rows * int(it["b"].shape[1]) for r, it in zip(res, items))
+    rows = sum(r.ens_iters * E.Problem(n, w.d).rows * S for r, S, n in zip(res, widths, grids))
     out = {"mode": "batch", "workload": w.name, "ensembles": k, "samples": n_samples,
-           "wave_gb": args.wave_gb or None,
+           "wave_gb": args.wave_gb or None, "resident_GiB": round(sum(need) / 2**30, 1),
+           "residency_waves": len(residency),
            "seconds": round(dt, 3), "sample_solves_per_s": round(n_samples / dt, 3),
            "latency_p50_s": round(float(np.percentile(lat, 50)), 4),
            "latency_p99_s": round(float(np.percentile(lat, 99)), 4),
@@ -629,7 +658,7 @@ def batch_mode(args) -> int:
            "iteration_alg_GBs": round(rows * ITER_BYTES / dt / 1e9, 1),
            "all_converged": bool(all(np.all(r.status == 0) for r in res)),
            "shapes": {f"{n}x{S}": [v["member_tile"], v["tile_lines"]] for (n, S), v in shapes.items()}}
-    if args.sequential:
+    if args.sequential and len(residency) == 1:
         torch.cuda.synchronize()
         t = time.perf_counter()
         for it in items:
@@ -662,6 +691,8 @@ def main() -> int:
                          "copy, for hardware-counter runs")
     ap.add_argument("--iters", type=int, default=100, help="iterations in --mode kernel")
     ap.add_argument("--S-list", default="4,8,16,32,64", help="ensemble widths in --mode table")
+    ap.add_argument("--resident-gb", type=float, default=0.0,
+                    help="--mode batch: device memory the draw may keep resident (0: 80 %% of HBM)")
     ap.add_argument("--wave-gb", type=float, default=0.0,
                     help="--mode batch: smallest-first waves of at most this many GB per CG "
                          "iteration (0: all ensembles in one batch)")

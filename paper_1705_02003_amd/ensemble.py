@@ -97,20 +97,25 @@ def _ensemble_width(t: torch.Tensor) -> int:
     return int(t.shape[-1])
 
 
-def workspace(prob: Problem, S: int, opts: Optional[SolverOptions] = None,
-              device=None) -> torch.Tensor:
-    """A device workspace large enough for solve / adjoint_grad / cheb_apply."""
+def workspace_bytes(prob: Problem, S: int, opts: Optional[SolverOptions] = None) -> int:
+    """Bytes of the workspace `workspace` allocates (ens_pcg_workspace_bytes;
+    with Jacobi, the larger Chebyshev layout that cheb_apply also needs)."""
     opts = opts or SolverOptions()
     o = opts.c()
     pc = prob.c()
     nb = L.lib().ens_pcg_workspace_bytes(C.byref(pc), C.byref(o), S)
     if opts.precond == "jacobi":
-        # cheb_apply needs the Chebyshev layout; size for the larger one
         o2 = SolverOptions(precond="chebyshev").c()
         nb = max(nb, L.lib().ens_pcg_workspace_bytes(C.byref(pc), C.byref(o2), S))
     if nb == 0:
         raise ValueError("invalid problem / options / ensemble width")
-    return torch.empty(nb, dtype=torch.uint8, device=device or "cuda")
+    return int(nb)
+
+
+def workspace(prob: Problem, S: int, opts: Optional[SolverOptions] = None,
+              device=None) -> torch.Tensor:
+    """A device workspace large enough for solve / adjoint_grad / cheb_apply."""
+    return torch.empty(workspace_bytes(prob, S, opts), dtype=torch.uint8, device=device or "cuda")
 
 
 def matrix_slot_stride(prob: Problem, S: int) -> int:
