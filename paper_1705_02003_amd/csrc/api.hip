@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "common.h"
+#include "fe3d.h"
 
 namespace ens {
 

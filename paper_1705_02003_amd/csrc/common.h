@@ -80,25 +80,6 @@ struct AsmArgs {
 
 enum Mode { M_SPMV = 0, M_PCG_J = 1, M_PCG_Z = 2, M_CHEB = 3 };
 
-// 3-D model: one term of the log-diffusivity expansion, a product of three
-// 1-D covariance eigenfunctions (kind 0: norm cos(w (s - 1/2)), kind 1:
-// norm sin(w (s - 1/2))) scaled by sqrt(lambda)
-constexpr int kMaxTerms = 16;
-struct Fe3dTerm {
-  double w[3], norm[3];
-  int kind[3];
-  double sq;
-};
-
-struct Fe3dAsmArgs {
-  const double* y;  // [S][d]
-  double* V;        // [27][vstride], slot k holds [N_r][S]
-  double* b;        // [N_r][S]
-  int m, S, logS, d;
-  size_t nelem, vstride;
-  Fe3dTerm term[kMaxTerms];
-};
-
 struct StencilArgs {
   const double* V;
   const double* r;
@@ -158,27 +139,6 @@ struct DqdyArgs {
 enum Finish { F_ALPHA = 0, F_UPDATE_J = 1, F_UPDATE_C = 2, F_CHEB = 3, F_INIT = 4, F_DOT = 5, F_SUMS = 6,
               F_MAX = 7 };
 
-// 3-D model: lambda^T (dA/dy_j) u per member (the adjoint gradient's form)
-struct Fe3dDqdyArgs {
-  const double* y;    // [S][d]
-  const double* u;    // [N_r][S]
-  const double* lam;  // [N_r][S]
-  double* partial;    // [d][groups][S]
-  int m, S, logS, d;
-  size_t ncell;       // (m+1)^3 cubes
-  Fe3dTerm term[kMaxTerms];
-};
-
-// Parameter-based grouping indicator (both models): per member the largest
-// ratio lambda_max / lambda_min of the diffusion tensor over the domain.
-struct IndArgs {
-  const double* y;   // [S][d]
-  double* partial;   // [groups][S] per-workgroup maxima
-  int dim, m, S, d, eps_model;
-  size_t ncell;      // 3-D: cubes (m+1)^3; 2-D: 1 (the ratio does not depend on x)
-  Fe3dTerm term[kMaxTerms];
-};
-
 struct FinishArgs {
   const double* partial;  // consecutive arrays of G * S partials
   int G;                  // workgroups of the producer kernel
@@ -217,12 +177,8 @@ int init_groups(const Geometry& g);   // workgroups of the element-wise kernels
 Geometry make_geometry(int n, int S, int tile_lines, int max_groups, int member_tile = 0);
 Geometry make_geometry3(int m, int S);
 
-// 3-D model (fe3d.hip): assembly, and the stencil step of every mode for
-// dim = 3 geometries (launch_stencil forwards to it)
-int fe3d_setup(const ens_problem* p, Fe3dAsmArgs& a);
-void launch_fe3d_assemble(const Fe3dAsmArgs& a, hipStream_t s);
-void launch_indicator(const IndArgs& a, int groups, hipStream_t s);
-void launch_fe3d_dqdy(const Fe3dDqdyArgs& a, int groups, hipStream_t s);
+// the 3-D model's stencil step of every mode (fe3d.hip; launch_stencil
+// forwards dim = 3 geometries to it); its other kernels are in fe3d.h
 template <int MODE>
 void launch_fe3d(const StencilArgs& a, hipStream_t s);
 // Elements from the start of one matrix slot (or workspace vector) to the

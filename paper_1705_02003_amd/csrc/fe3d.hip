@@ -29,6 +29,7 @@
 #include <vector>
 
 #include "device.h"
+#include "fe3d.h"
 
 namespace ens {
 
