@@ -1,0 +1,158 @@
+"""Parity at the full sizes of the measured workloads, in the launch
+configuration the benchmark times (512 workgroups, 32-line tiles, the
+symmetric read), on outputs the oracle can compute one by one:
+
+  * 512^2, d = 4, S = 32 (the benchmark's adaptive workload; inputs are the
+    workload's first sparse-grid nodes): assembly at every row of sampled
+    members, the product at sampled members, the solve of two members
+    against full oracle solves (counts +-1, the solution within 1e-9 at
+    equal count for one of them), the true residual of every member;
+  * 1024^2, d = 8, S = 32, Chebyshev-4 (the Chebyshev workload, uniform
+    samples of its seed): the preconditioner application of sampled members
+    and the true residual of sampled members of the solve;
+  * 512^2, d = 6, S = 32 (the adjoint workload): the dQ/dy kernel against
+    the oracle's form for sampled members, given the GPU's u and lambda;
+  * 31^3, d = 4, S = 32 (the 3-D workload): solves of two members against
+    full oracle solves.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import CONVERGED
+from oracle import adjoint as oadj
+from oracle import fe3d as ofe
+from oracle import pcg as opcg
+from oracle import problem as oprob
+from oracle import sparse_grid as sg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible: the gpu tests must run on an MI355X")
+    yield
+
+
+def E():
+    from paper_1705_02003_amd import ensemble
+    return ensemble
+
+
+def to_dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def log_case(**kw):
+    print("CASE", " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+def adaptive_first_nodes(d, count):
+    """The benchmark workload's first samples: the level-1 grid, then the
+    level-2 nodes, in generation (canonical) order."""
+    nodes = sg.full_grid(d, 1) + [nd for nd in sg.full_grid(d, 2) if sg.total_level(nd) == 2]
+    return np.array([sg.coords(nd) for nd in nodes[:count]])
+
+
+def test_benchmark_size_512_s32():
+    ens = E()
+    n, d, S, amp = 512, 4, 32, 0.4
+    log_case(test="fullsize-512", n=n, S=S)
+    ys = adaptive_first_nodes(d, S)
+    prob = ens.Problem(n, d, 0, amp)
+    V, b = ens.assemble(prob, to_dev(ys))
+    Vh = V.cpu().numpy()
+    # assembly: every row of three members
+    for s in (0, 13, 31):
+        ref = oprob.stencil_values(ys[s], n, 0, amp)
+        err = np.abs(Vh[:, :, s] - ref).max(axis=0)
+        assert np.all(err <= 4e-15 * np.abs(ref[oprob.CENTER]))
+    # the product at three members
+    rng = np.random.default_rng(7)
+    P = rng.standard_normal((n * n, S))
+    q = ens.spmv(prob, V, to_dev(P)).cpu().numpy()
+    for s in (2, 17, 30):
+        A = oprob.to_csr(Vh[:, :, s], n)
+        ref = A @ P[:, s]
+        assert np.max(np.abs(q[:, s] - ref)) <= 1e-13 * np.abs(A).sum(axis=1).max() * np.abs(P[:, s]).max()
+    # the solve, benchmark options
+    res = ens.solve(prob, V, b, ens.SolverOptions(rtol=1e-8, max_iter=20000))
+    assert np.all(res.status == CONVERGED)
+    x = res.x.cpu().numpy()
+    for s in range(S):
+        A, bo, _ = oprob.assemble(ys[s], n, 0, amp)
+        assert np.linalg.norm(bo - A @ x[:, s]) <= 2e-8 * np.linalg.norm(bo)
+    for s, equal in ((0, True), (9, False)):
+        A, bo, dg = oprob.assemble(ys[s], n, 0, amp)
+        _, I, st, _ = opcg.pcg(A, bo, dg, 1e-8, 20000)
+        assert st == CONVERGED and abs(int(res.iters[s]) - I) <= 1, (s, res.iters[s], I)
+        if equal:
+            xe, _, _, _ = opcg.pcg(A, bo, dg, 0.0, int(res.iters[s]))
+            assert np.linalg.norm(x[:, s] - xe) <= 1e-9 * np.linalg.norm(xe)
+
+
+def test_chebyshev_size_1024_s32():
+    ens = E()
+    w = workloads.CHEB_1024
+    n, S = w.n, 32
+    log_case(test="fullsize-1024-cheb", n=n, S=S)
+    ys = workloads.uniform_samples(w.seed, S, w.d)
+    prob = ens.Problem(n, w.d, w.eps_model, w.amp)
+    V, b = ens.assemble(prob, to_dev(ys))
+    Vh_c = V[4].cpu().numpy()
+    rng = np.random.default_rng(8)
+    R = rng.standard_normal((n * n, S))
+    z, lmax = ens.cheb_apply(prob, V, to_dev(R))
+    z = z.cpu().numpy()
+    for s in (5, 26):
+        vals = np.stack([V[k, :, s].cpu().numpy() for k in range(9)])
+        A = oprob.to_csr(vals, n)
+        lm = opcg.gershgorin_lmax(A, Vh_c[:, s])
+        assert lmax[s] == pytest.approx(lm, rel=1e-15)
+        ref = opcg.chebyshev_apply(A, Vh_c[:, s], R[:, s], lm)
+        assert np.linalg.norm(z[:, s] - ref) <= 1e-13 * np.linalg.norm(ref)
+    res = ens.solve(prob, V, b, ens.SolverOptions(precond="chebyshev", rtol=w.rtol,
+                                                  max_iter=w.max_iter))
+    assert np.all(res.status == CONVERGED)
+    x = res.x.cpu().numpy()
+    for s in (0, 11, 31):
+        A, bo, _ = oprob.assemble(ys[s], n, w.eps_model, w.amp)
+        assert np.linalg.norm(bo - A @ x[:, s]) <= 2 * w.rtol * np.linalg.norm(bo)
+
+
+def test_adjoint_size_512_s32():
+    ens = E()
+    w = workloads.ADJOINT_512
+    n, S = w.n, 32
+    log_case(test="fullsize-512-dqdy", n=n, S=S)
+    ys = workloads.uniform_samples(w.seed, S, w.d)
+    prob = ens.Problem(n, w.d, w.eps_model, w.amp)
+    rng = np.random.default_rng(9)
+    U, Lm = rng.standard_normal((n * n, S)), rng.standard_normal((n * n, S))
+    g = ens.dqdy(prob, to_dev(ys), to_dev(U), to_dev(Lm))
+    for s in (3, 28):
+        ref = -oadj.dA_bilinear(Lm[:, s], U[:, s], ys[s], n, w.eps_model, w.amp)
+        np.testing.assert_allclose(g[s], ref, rtol=1e-10, atol=1e-10 * np.abs(ref).max())
+
+
+def test_fe3d_size_31cube_s32():
+    ens = E()
+    w = workloads.FE3D_32
+    m, S = w.n, 32
+    log_case(test="fullsize-fe3d", m=m, S=S)
+    ys = workloads.uniform_samples(w.seed, S, w.d)
+    prob = ens.Problem(m, w.d, dim=3)
+    V, b = ens.assemble(prob, to_dev(ys))
+    res = ens.solve(prob, V, b, ens.SolverOptions(rtol=w.rtol, max_iter=w.max_iter))
+    assert np.all(res.status == CONVERGED)
+    x = res.x.cpu().numpy()
+    for s in (4, 21):
+        A, bo, dg = ofe.assemble(ys[s], m)
+        _, I, st, _ = opcg.pcg(A, bo, dg, w.rtol, 20000)
+        assert st == CONVERGED and abs(int(res.iters[s]) - I) <= 1
+        xe, _, _, _ = opcg.pcg(A, bo, dg, 0.0, int(res.iters[s]))
+        assert np.linalg.norm(x[:, s] - xe) <= 1e-9 * np.linalg.norm(xe)
+        assert np.linalg.norm(bo - A @ x[:, s]) <= 2 * w.rtol * np.linalg.norm(bo)
