@@ -126,10 +126,12 @@ Geometry make_geometry(int n, int S, int tile_lines, int max_groups, int member_
   return g;
 }
 
-// 3-D model: no tiles; the product kernel strides over points, kNT / tpp
-// points per workgroup and pass, with at most 512 workgroups (two per CU;
-// measured on MI355X at 31^3 points, S = 32 and 64: 6 % faster solves than
-// 1024, whose larger partial arrays cost the finishing kernels more).
+// 3-D model: no tiles; the product kernel strides over pairs of points,
+// kNT / tpp pairs per workgroup and pass, with at most 512 workgroups (two
+// per CU, which its register use allows; at 31^3 points and S = 32 on
+// MI355X the paired kernel at 512 workgroups is 5 % faster than one point
+// per thread at 1024, and keeps the finishing kernels' partials half as
+// large).
 Geometry make_geometry3(int m, int S) {
   Geometry g;
   std::memset(&g, 0, sizeof(g));
@@ -148,8 +150,10 @@ Geometry make_geometry3(int m, int S) {
   g.dim = 3;
   g.nslot = 27;
   g.cslot = 13;
+  // the product kernel takes kFe3dPair x-neighbouring points per thread
   const size_t ppb = (size_t)(kNT / g.tpp);
-  g.groups = (int)std::min<size_t>((g.nr + ppb - 1) / ppb, 512);
+  const size_t npair = (size_t)((m + kFe3dPair - 1) / kFe3dPair) * m * m;
+  g.groups = (int)std::min<size_t>((npair + ppb - 1) / ppb, 512);
   return g;
 }
 

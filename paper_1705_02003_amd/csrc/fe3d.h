@@ -10,6 +10,7 @@ namespace ens {
 // 1-D covariance eigenfunctions (kind 0: norm cos(w (s - 1/2)), kind 1:
 // norm sin(w (s - 1/2))) scaled by sqrt(lambda)
 constexpr int kMaxTerms = 16;
+constexpr int kFe3dPair = 2;   // x-neighbouring points per thread of the product kernel
 struct Fe3dTerm {
   double w[3], norm[3];
   int kind[3];

@@ -92,7 +92,9 @@ def test_matrix_bitwise_symmetric():
         assert (A != A.T).nnz == 0
 
 
-@pytest.mark.parametrize("m,S", [(9, 4), (7, 32), (5, 1), (11, 16)])
+# m = 2 and 3: every point touches the boundary, and at odd m the product
+# kernel's last pair of every grid line holds one point
+@pytest.mark.parametrize("m,S", [(9, 4), (7, 32), (5, 1), (11, 16), (2, 8), (3, 2), (3, 64)])
 def test_spmv_matches_oracle(m, S):
     log_case(test="fe3d-spmv", m=m, S=S)
     ens = E()
