@@ -711,8 +711,8 @@ def main() -> int:
     args = ap.parse_args()
     set_byte_model(args.full_stencil)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build runs the ensemble solver on a "
-              "single MI355X (ensembles are independent; see the design notes for how the "
+        print("bench.py measures one GPU only: the ensemble solver runs on a single "
+              "MI355X (ensembles are independent; see the design notes for how the "
               "path would shard). Run with --gpus 1.", file=sys.stderr)
         return 2
 
