@@ -7,13 +7,17 @@ symmetric read), on outputs the oracle can compute one by one:
     members, the product at sampled members, the solve of two members
     against full oracle solves (counts +-1, the solution within 1e-9 at
     equal count for one of them), the true residual of every member;
-  * 1024^2, d = 8, S = 32, Chebyshev-4 (the Chebyshev workload, uniform
-    samples of its seed): the preconditioner application of sampled members
+  * 1024^2, d = 8, S = 32 and 64, Chebyshev-4 (the Chebyshev workload,
+    uniform samples of its seed): the preconditioner application of sampled members
     and the true residual of sampled members of the solve;
   * 512^2, d = 6, S = 32 (the adjoint workload): the dQ/dy kernel against
     the oracle's form for sampled members, given the GPU's u and lambda;
   * 31^3, d = 4, S = 32 (the 3-D workload): solves of two members against
-    full oracle solves.
+    full oracle solves;
+  * the batched workload's first six ensembles (grids 256^2, 512^2 and
+    1024^2, widths 4, 8 and 64, d = 8) in one batched solve with the
+    autotuner's launch shapes: every ensemble against its single-ensemble
+    solve, sampled members' true residuals and one member's oracle solve.
 """
 import numpy as np
 import pytest
@@ -94,10 +98,11 @@ def test_benchmark_size_512_s32():
             assert np.linalg.norm(x[:, s] - xe) <= 1e-9 * np.linalg.norm(xe)
 
 
-def test_chebyshev_size_1024_s32():
+@pytest.mark.parametrize("S", [32, 64])
+def test_chebyshev_size_1024(S):
     ens = E()
     w = workloads.CHEB_1024
-    n, S = w.n, 32
+    n = w.n
     log_case(test="fullsize-1024-cheb", n=n, S=S)
     ys = workloads.uniform_samples(w.seed, S, w.d)
     prob = ens.Problem(n, w.d, w.eps_model, w.amp)
@@ -107,7 +112,7 @@ def test_chebyshev_size_1024_s32():
     R = rng.standard_normal((n * n, S))
     z, lmax = ens.cheb_apply(prob, V, to_dev(R))
     z = z.cpu().numpy()
-    for s in (5, 26):
+    for s in (5, S - 6):
         vals = np.stack([V[k, :, s].cpu().numpy() for k in range(9)])
         A = oprob.to_csr(vals, n)
         lm = opcg.gershgorin_lmax(A, Vh_c[:, s])
@@ -118,7 +123,7 @@ def test_chebyshev_size_1024_s32():
                                                   max_iter=w.max_iter))
     assert np.all(res.status == CONVERGED)
     x = res.x.cpu().numpy()
-    for s in (0, 11, 31):
+    for s in (0, 11, S - 1):
         A, bo, _ = oprob.assemble(ys[s], n, w.eps_model, w.amp)
         assert np.linalg.norm(bo - A @ x[:, s]) <= 2 * w.rtol * np.linalg.norm(bo)
 
@@ -156,3 +161,43 @@ def test_fe3d_size_31cube_s32():
         xe, _, _, _ = opcg.pcg(A, bo, dg, 0.0, int(res.iters[s]))
         assert np.linalg.norm(x[:, s] - xe) <= 1e-9 * np.linalg.norm(xe)
         assert np.linalg.norm(bo - A @ x[:, s]) <= 2 * w.rtol * np.linalg.norm(bo)
+
+
+def test_batch_full_grid_sizes():
+    ens = E()
+    from paper_1705_02003_amd import autotune
+    w = workloads.BATCHED
+    draw = workloads.batched_draw(w.seed)
+    k = 6
+    log_case(test="fullsize-batch", shapes=list(zip(draw.grids[:k], draw.widths[:k])))
+    items = []
+    for S, n, y in zip(draw.widths[:k], draw.grids[:k], draw.samples[:k]):
+        prob = ens.Problem(n, w.d, w.eps_model, w.amp)
+        V, b = ens.assemble(prob, to_dev(y))
+        sh = autotune.tune(n, S, cache=None)
+        items.append({"prob": prob, "V": V, "b": b, "tile_lines": sh["tile_lines"],
+                      "member_tile": sh["member_tile"]})
+    opts = ens.SolverOptions(rtol=w.rtol, max_iter=w.max_iter)
+    res = ens.batch_solve(items, opts)
+    for e, (it, r, y) in enumerate(zip(items, res, draw.samples[:k])):
+        assert np.all(r.status == CONVERGED), e
+        single = ens.solve(it["prob"], it["V"], it["b"], opts)
+        assert np.all(np.abs(r.iters - single.iters) <= 1), e
+        same = r.iters == single.iters
+        num = torch.linalg.norm(r.x - single.x, dim=0).cpu().numpy()
+        den = torch.linalg.norm(single.x, dim=0).cpu().numpy()
+        assert np.all((num / den)[same] <= 1e-9), e
+        x = r.x.cpu().numpy()
+        n = it["prob"].n
+        for s in (0, x.shape[1] - 1):
+            A, bo, _ = oprob.assemble(y[s], n, w.eps_model, w.amp)
+            assert np.linalg.norm(bo - A @ x[:, s]) <= 2 * w.rtol * np.linalg.norm(bo), (e, s)
+    # one member of the 256^2 ensemble against the oracle's own solve
+    e = draw.grids[:k].index(256)
+    y = draw.samples[e][0]
+    A, bo, dg = oprob.assemble(y, 256, w.eps_model, w.amp)
+    _, I, st, _ = opcg.pcg(A, bo, dg, w.rtol, w.max_iter)
+    assert st == CONVERGED and abs(int(res[e].iters[0]) - I) <= 1
+    xe, _, _, _ = opcg.pcg(A, bo, dg, 0.0, int(res[e].iters[0]))
+    x0 = res[e].x[:, 0].cpu().numpy()
+    assert np.linalg.norm(x0 - xe) <= 1e-9 * np.linalg.norm(xe)
