@@ -13,7 +13,10 @@ symmetric read), on outputs the oracle can compute one by one:
   * 512^2, d = 6, S = 32 (the adjoint workload): the dQ/dy kernel against
     the oracle's form for sampled members, given the GPU's u and lambda;
   * 31^3, d = 4, S = 32 (the 3-D workload): solves of two members against
-    full oracle solves;
+    full oracle solves; the dQ/dy kernel and the grouping indicator of
+    sampled members;
+  * 512^2, d = 4, S = 64 (the widest ensemble of the speed-up curve): the
+    product and the solve's true residual at sampled members;
   * the batched workload's first six ensembles (grids 256^2, 512^2 and
     1024^2, widths 4, 8 and 64, d = 8) in one batched solve with the
     autotuner's launch shapes: every ensemble against its single-ensemble
@@ -201,3 +204,43 @@ def test_batch_full_grid_sizes():
     xe, _, _, _ = opcg.pcg(A, bo, dg, 0.0, int(res[e].iters[0]))
     x0 = res[e].x[:, 0].cpu().numpy()
     assert np.linalg.norm(x0 - xe) <= 1e-9 * np.linalg.norm(xe)
+
+
+def test_fe3d_dqdy_and_indicator_31cube_s32():
+    ens = E()
+    w = workloads.FE3D_32
+    m, S = w.n, 32
+    log_case(test="fullsize-fe3d-dqdy", m=m, S=S)
+    ys = workloads.uniform_samples(w.seed, S, w.d)
+    prob = ens.Problem(m, w.d, dim=3)
+    rng = np.random.default_rng(12)
+    U, Lm = rng.standard_normal((m ** 3, S)), rng.standard_normal((m ** 3, S))
+    g = ens.dqdy(prob, to_dev(ys), to_dev(U), to_dev(Lm))
+    for s in (1, 30):
+        ref = -ofe.dA_bilinear(Lm[:, s], U[:, s], ys[s], m)
+        np.testing.assert_allclose(g[s], ref, rtol=1e-10, atol=1e-10 * np.abs(ref).max())
+    h = ens.param_indicator(prob, to_dev(ys))
+    for s in (0, 17, 31):
+        assert h[s] == pytest.approx(ofe.param_indicator(ys[s], m), rel=1e-13)
+
+
+def test_benchmark_grid_s64():
+    ens = E()
+    n, d, S, amp = 512, 4, 64, 0.4
+    log_case(test="fullsize-512-s64", n=n, S=S)
+    ys = workloads.uniform_samples(21, S, d)
+    prob = ens.Problem(n, d, 0, amp)
+    V, b = ens.assemble(prob, to_dev(ys))
+    rng = np.random.default_rng(13)
+    P = rng.standard_normal((n * n, S))
+    q = ens.spmv(prob, V, to_dev(P)).cpu().numpy()
+    for s in (0, 37, 63):
+        A, _, _ = oprob.assemble(ys[s], n, 0, amp)
+        ref = A @ P[:, s]
+        assert np.max(np.abs(q[:, s] - ref)) <= 1e-13 * np.abs(A).sum(axis=1).max() * np.abs(P[:, s]).max()
+    res = ens.solve(prob, V, b, ens.SolverOptions(rtol=1e-8, max_iter=20000))
+    assert np.all(res.status == CONVERGED)
+    x = res.x.cpu().numpy()
+    for s in (0, 21, 42, 63):
+        A, bo, _ = oprob.assemble(ys[s], n, 0, amp)
+        assert np.linalg.norm(bo - A @ x[:, s]) <= 2e-8 * np.linalg.norm(bo)
