@@ -348,7 +348,10 @@ __global__ __launch_bounds__(kNT) void fe3d_dir_kernel(StencilArgs a) {
 // an index product per neighbour, which at twice the workgroups was still
 // 14 % slower and would double the finishing kernels' partials.  The dk loop is
 // not unrolled: unrolled, the compiler hoists every load of the pair and
-// spills registers.
+// spills registers.  The register budget allows three waves per SIMD: one
+// launch of 512 workgroups fills two, and the third leaves room for another
+// ensemble's kernel on another stream (at two, two ensembles solved
+// concurrently ran slower than one at a time).
 // SYM: the matrix is symmetric, so the thirteen lower values of row P are
 // read as the upper values of the neighbours' rows, A(P, P + o) =
 // A(P + o, P) = slot 26 - s of row P + o; those rows are being read by their
