@@ -135,6 +135,27 @@ def test_jacobi_pcg_matches_oracle(m, S, d, seed):
     assert worst <= 1e-9
 
 
+@pytest.mark.parametrize("groups,pre", [(1, "jacobi"), (8, "jacobi"), (20, "chebyshev"), (36, "jacobi")])
+def test_workgroup_count_does_not_change_the_solve(groups, pre):
+    # one workgroup, a multiple of the eight XCDs and counts that are not
+    # (plain striding): the same solves, up to the reduction order of p^T q
+    m, S, d = 11, 16, 4
+    log_case(test="fe3d-groups", m=m, S=S, groups=groups, pre=pre)
+    ens = E()
+    ys = np.random.default_rng(31).uniform(-1, 1, (S, d))
+    prob, V, b = assemble(m, ys)
+    ref = ens.solve(prob, V, b, ens.SolverOptions(precond=pre, rtol=1e-8))
+    res = ens.solve(prob, V, b, ens.SolverOptions(precond=pre, rtol=1e-8, max_groups=groups))
+    assert np.all(res.status == 0) and np.all(np.abs(res.iters - ref.iters) <= 1)
+    same = res.iters == ref.iters
+    num = torch.linalg.norm(res.x - ref.x, dim=0).cpu().numpy()
+    den = torch.linalg.norm(ref.x, dim=0).cpu().numpy()
+    assert np.all((num / den)[same] <= 1e-9)
+    A, bo, _ = ofe.assemble(ys[0], m)
+    x0 = res.x[:, 0].cpu().numpy()
+    assert np.linalg.norm(bo - A @ x0) <= 2e-8 * np.linalg.norm(bo)
+
+
 def test_chebyshev_apply_matches_oracle():
     log_case(test="fe3d-cheb-apply")
     ens = E()
