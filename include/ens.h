@@ -110,7 +110,12 @@ typedef struct {
   double cheb_ratio;    /* lambda_max / lambda_min of the Chebyshev interval (30) */
   double rtol;          /* relative residual tolerance (1e-8)                 */
   int32_t max_iter;     /* iteration cap (20000)                              */
-  int32_t poll_every;   /* host checks the device done flag every m iterations (16) */
+  int32_t poll_every;   /* iterations between the host's checks of the device
+                           done flag; 0 = adaptive: 16, or for an ensemble of
+                           at least 2^19 member-rows the largest power of two
+                           <= sqrt(iterations so far), between 4 and 16 (a
+                           solve overruns its last iteration by up to two
+                           such intervals of early-exit launches)            */
   int32_t tile_lines;   /* stencil tile height in grid lines, 0 = heuristic   */
   int32_t max_groups;   /* workgroups of the stencil/update kernels, 0 = heuristic */
   int32_t flags;        /* ENS_FLAG_* bits below                              */

@@ -49,7 +49,7 @@ class SolverOptions:
     cheb_ratio: float = 30.0
     rtol: float = 1e-8
     max_iter: int = 20000
-    poll_every: int = 16
+    poll_every: int = 0           # 0: adaptive (see ens_opts.poll_every)
     tile_lines: int = 0           # 0: heuristic
     max_groups: int = 0           # 0: heuristic
     time_spmv: bool = False
