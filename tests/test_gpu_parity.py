@@ -166,6 +166,28 @@ def test_tile_shapes_agree():
         assert rel <= 1e-8
 
 
+@pytest.mark.parametrize("dim,n,S", [(2, 256, 32), (2, 48, 4), (3, 17, 32)])
+def test_poll_interval_does_not_change_the_solve(dim, n, S):
+    """The host's poll interval only decides how many early-exit launches
+    follow convergence: iterations, status and x are the same bits for the
+    adaptive interval (the first two cases span both of its regimes) and for
+    fixed ones."""
+    ens = E()
+    d = 4
+    prob = ens.Problem(n, d, 0, 0.4 if dim == 2 else 0.0, dim=dim)
+    ys = np.random.default_rng(n + S).uniform(-1, 1, (S, d))
+    V, b = gpu_stencil(prob, ys)
+    rtol = 1e-8 if dim == 2 else 1e-7
+    base = ens.solve(prob, V, b, ens.SolverOptions(rtol=rtol))
+    assert np.all(base.status == CONVERGED)
+    for poll in (1, 3, 16, 64):
+        log_case(test="poll", dim=dim, n=n, S=S, poll=poll)
+        r = ens.solve(prob, V, b, ens.SolverOptions(rtol=rtol, poll_every=poll))
+        assert np.array_equal(r.iters, base.iters) and np.array_equal(r.status, base.status)
+        assert r.ens_iters == base.ens_iters
+        assert torch.equal(r.x, base.x)
+
+
 def test_permutation_and_padding_bitwise():
     ens = E()
     n, S = 48, 16
