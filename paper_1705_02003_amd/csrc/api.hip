@@ -289,8 +289,8 @@ struct SolveOut {
 // work (about 2^19 member-rows and up) therefore start with short intervals,
 // growing with the iteration count as sqrt(k) (the overrun then stays a
 // small share of a solve of any length) to the fixed 16 of small ensembles
-// and long solves.  On MI355X this made the 31^3, S = 32 solves 3 % (Jacobi)
-// and 6 % (Chebyshev-4) faster and left the 512^2 workload unchanged; fixed
+// and long solves.  On MI355X this made the 31^3, S = 32 solves 1 % (Jacobi)
+// and 5 % (Chebyshev-4) faster and left the 512^2 workload unchanged; fixed
 // short intervals cost small ensembles up to 9 % (512^2, S = 1).
 static int poll_interval(const Opts& o, const Geometry& g, int it) {
   if (o.poll > 0) return o.poll;
