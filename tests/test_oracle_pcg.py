@@ -100,6 +100,42 @@ def test_chebyshev_closed_form_on_laplacian_eigenvectors():
         np.testing.assert_allclose(z, P * (h * h / 4) * v, rtol=1e-11, atol=1e-14 * np.abs(z).max())
 
 
+@pytest.mark.parametrize("y,n,eps_model,amp", [
+    (np.array([0.7, 0.35, -0.9, 0.8]), 7, 0, 0.4),
+    (np.array([-0.2, -0.6, 0.9, -0.7, 0.5, -0.4, 0.3, 0.8]), 6, 1, 0.45),
+])
+def test_gershgorin_bound_is_the_infinity_norm_of_jacobi_scaled_matrix(y, n, eps_model, amp):
+    # max_i sum_j |a_ij| / a_ii is the maximum absolute row sum of D^-1 A,
+    # i.e. its infinity norm, which numpy computes independently from the
+    # dense matrix.  Anisotropic (theta off the axes) and variable a, so the
+    # ratio differs from row to row and max(row sum) / max(diag) is another
+    # number (checked, so that a mistake of that kind would fail here).
+    A, _, diag = problem.assemble(y, n, eps_model, amp)
+    Ad = A.toarray()
+    DA = Ad / diag[:, None]
+    lmax = pcg.gershgorin_lmax(A, diag)
+    assert lmax == pytest.approx(np.linalg.norm(DA, np.inf), rel=1e-14)
+    rowsum = np.abs(Ad).sum(axis=1)
+    assert abs(rowsum.max() / diag.max() - lmax) > 1e-6 * lmax
+    assert abs(np.mean(rowsum / diag) - lmax) > 1e-6 * lmax
+    # Gershgorin: every eigenvalue of D^-1/2 A D^-1/2 (those of D^-1 A) lies
+    # in [0, lmax]; its diagonal is 1, so the largest is at least 1
+    ev = np.linalg.eigvalsh(Ad / np.sqrt(np.outer(diag, diag)))
+    assert 1.0 <= ev.max() <= lmax * (1 + 1e-14) and ev.min() > 0
+
+
+def test_gershgorin_bound_closed_form_constant_coefficient():
+    # a == 1: every interior row is the same stencil, centre 2(k11 + k22),
+    # E, W -k11, N, S -k22, corners +-k12/2 (times 1/h^2), so the largest
+    # ratio is 2 + |k12| / (k11 + k22) = 2 + |(1 - eps) sin(theta) cos(theta)| / (1 + eps)
+    for y1, y2 in [(0.3, 0.4), (-0.8, -0.25), (0.9, 0.9)]:
+        A, _, diag = problem.assemble(np.array([y1, y2]), 9, 0, 0.0)
+        eps = 10.0 ** (-(1.0 + y1))
+        th = math.pi / 4 * (1 + y2)
+        want = 2.0 + abs((1 - eps) * math.sin(th) * math.cos(th)) / (1 + eps)
+        assert pcg.gershgorin_lmax(A, diag) == pytest.approx(want, rel=1e-13)
+
+
 def test_chebyshev_pcg_converges_to_same_solution():
     y = sample(5, 8)
     A, b, diag = problem.assemble(y, 40, 1, 0.45)

@@ -118,6 +118,49 @@ def test_refine_respects_threshold_and_budget():
     assert len(small) == 2
 
 
+def _level1_grid_2d():
+    """The d = 2 grid of levels 0-1: centre, then (y1, y2) = (-1, 0), (+1, 0),
+    (0, -1), (0, +1), with values whose surpluses (value minus the centre's)
+    are +8, -6, +4, +2: four parents of distinct priority."""
+    C0, M1, P1 = (0, 0), (1, 0), (1, 1)
+    nodes = [(C0, C0), (M1, C0), (P1, C0), (C0, M1), (C0, P1)]
+    vals = [10.0, 18.0, 4.0, 14.0, 12.0]
+    return nodes, vals
+
+
+def test_refine_budget_takes_children_by_decreasing_parent_surplus():
+    # Hand-derived.  Children (one dimension at a time; a level-0 coordinate
+    # has children -1 and +1, a level-1 coordinate -1 has -1/2):
+    #   (-1, 0) |c| 8: (-1/2, 0), (-1, -1), (-1, +1)
+    #   (+1, 0) |c| 6: (+1/2, 0), (+1, -1), (+1, +1)
+    #   (0, -1) |c| 4: (0, -1/2), (-1, -1), (+1, -1)
+    #   (0, +1) |c| 2: (0, +1/2), (-1, +1), (+1, +1)
+    # A child's priority is its largest parent |c|: 8 for the first three,
+    # 6 for the next three, then 4 and 2.  Ties go in canonical order (level
+    # vector (1, 1) before (2, 0), then index vector).
+    nodes, vals = _level1_grid_2d()
+    c = sg.surpluses(nodes, vals)
+    assert [c[nd] for nd in nodes] == [10.0, 8.0, -6.0, 4.0, 2.0]
+    corner = lambda a, b: ((1, a), (1, b))   # noqa: E731  (index 0: -1, index 1: +1)
+    half_x = lambda k: ((2, k), (0, 0))      # noqa: E731
+    half_y = lambda k: ((0, 0), (2, k))      # noqa: E731
+    room = lambda r: len(nodes) + r           # noqa: E731
+    assert sg.refine(nodes, vals, 1, 0.0, room(1)) == [corner(0, 0)]
+    assert sg.refine(nodes, vals, 1, 0.0, room(3)) == [corner(0, 0), corner(0, 1), half_x(0)]
+    assert sg.refine(nodes, vals, 1, 0.0, room(5)) == sorted(
+        [corner(0, 0), corner(0, 1), half_x(0), corner(1, 0), corner(1, 1)], key=sg.canonical_key)
+    assert sg.refine(nodes, vals, 1, 0.0, room(7)) == sorted(
+        [corner(0, 0), corner(0, 1), half_x(0), corner(1, 0), corner(1, 1), half_x(1), half_y(0)],
+        key=sg.canonical_key)
+    everything = sg.refine(nodes, vals, 1, 0.0, 10**9)
+    assert len(everything) == 8 and half_y(1) in everything
+    # the threshold tau = tau_rel |v(centre)| = 3 drops the parent with |c| = 2:
+    # its only child of no other parent, (0, +1/2), is not a candidate
+    thr = sg.refine(nodes, vals, 1, 0.3, 10**9)
+    assert len(thr) == 7 and half_y(1) not in thr and corner(1, 1) in thr
+    assert sg.refine(nodes, vals, 1, 0.3, room(0)) == []
+
+
 def test_grouping_sorted_chunked_and_padded():
     pred = [5.0, 1.0, 3.0, 3.0, 9.0, 0.5, 7.0, 8.0]
     groups = sg.group(pred, 3)
