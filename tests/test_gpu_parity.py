@@ -6,7 +6,8 @@ Tolerances (derivations in the design notes):
   * SpMV and Chebyshev application: 1e-13 relative (summation order);
   * PCG: iteration counts within +-1 of the oracle; at equal iteration count
     (the oracle re-run for exactly the GPU's count) ||x_gpu - x_orc|| /
-    ||x_orc|| <= 1e-9; true residual ||b - A x|| <= 2 rtol ||b||;
+    ||x_orc|| <= 1e-9 and max|x_gpu - x_orc| / max|x_orc| <= 1e-9; true
+    residual ||b - A x|| <= 2 rtol ||b||;
   * reductions are deterministic: permuting members permutes results bit for
     bit, a padded replica equals its original bit for bit.
 """
@@ -110,7 +111,9 @@ def check_solution(res, ys, n, eps_model, amp, rtol, precond="jacobi", real=None
         # same iteration count: rerun the oracle for exactly the GPU's count
         xe, Ie, _, _ = opcg.pcg(A, b, diag, 0.0, int(res.iters[s]), precond)
         rel = np.linalg.norm(x[:, s] - xe) / np.linalg.norm(xe)
-        worst = max(worst, rel)
+        # element-wise, against the largest entry
+        rel_e = np.abs(x[:, s] - xe).max() / np.abs(xe).max()
+        worst = max(worst, rel, rel_e)
         assert np.linalg.norm(b - A @ x[:, s]) <= 2 * rtol * np.linalg.norm(b)
     return worst
 
@@ -144,7 +147,7 @@ def test_ragged_sizes_match_oracle(n, S, d, eps_model, amp, seed):
     ys = np.random.default_rng(seed).uniform(-1, 1, (S, d))
     V, b = gpu_stencil(prob, ys)
     res = ens.solve(prob, V, b, ens.SolverOptions(rtol=1e-8))
-    worst = check_solution(res, ys, n, eps_model, amp, 1e-8, real=min(S, 12))
+    worst = check_solution(res, ys, n, eps_model, amp, 1e-8)
     print("ragged", n, S, "max rel diff", worst)
     assert worst <= 1e-9
 
@@ -278,7 +281,7 @@ def test_chebyshev_pcg_matches_oracle():
     ys = np.random.default_rng(16).uniform(-1, 1, (S, 8))
     V, b = gpu_stencil(prob, ys)
     res = ens.solve(prob, V, b, ens.SolverOptions(precond="chebyshev"))
-    worst = check_solution(res, ys, n, 1, 0.45, 1e-8, precond="chebyshev", real=8)
+    worst = check_solution(res, ys, n, 1, 0.45, 1e-8, precond="chebyshev")
     print("chebyshev max rel diff", worst)
     assert worst <= 1e-9
 
