@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -300,13 +301,76 @@ static int poll_interval(const Opts& o, const Geometry& g, int it) {
   return p;
 }
 
+// Host side of the done-flag polls: a pinned two-slot flag and two events,
+// kept in a process-wide pool and reused by later solves on the same device
+// (created only when every pooled one is in use, never freed), so a solve
+// allocates nothing once the pool holds one per concurrent solve.
+struct Poller {
+  int dev;
+  int32_t* flag;
+  hipEvent_t ev[2];
+};
+
+static std::mutex g_poll_mu;
+static std::vector<Poller*> g_poll_free;
+
+static int acquire_poller(Poller** out) {
+  int dev = 0;
+  HIPCHECK(hipGetDevice(&dev));
+  {
+    std::lock_guard<std::mutex> lk(g_poll_mu);
+    for (size_t k = 0; k < g_poll_free.size(); ++k) {
+      if (g_poll_free[k]->dev == dev) {
+        *out = g_poll_free[k];
+        g_poll_free.erase(g_poll_free.begin() + (long)k);
+        return ENS_OK;
+      }
+    }
+  }
+  Poller* p = new Poller;
+  p->dev = dev;
+  p->flag = nullptr;
+  p->ev[0] = p->ev[1] = nullptr;
+  hipError_t e = hipHostMalloc((void**)&p->flag, 2 * sizeof(int32_t), hipHostMallocDefault);
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&p->ev[k], hipEventDisableTiming);
+  if (e != hipSuccess) {
+    for (int k = 0; k < 2; ++k)
+      if (p->ev[k]) (void)hipEventDestroy(p->ev[k]);
+    if (p->flag) (void)hipHostFree(p->flag);
+    delete p;
+    return set_hip_error(e);
+  }
+  *out = p;
+  return ENS_OK;
+}
+
+static void release_poller(Poller* p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_poll_mu);
+  g_poll_free.push_back(p);
+}
+
+// Clears the control words (a kernel rather than a memset node, so the
+// clearing also behaves under stream capture).
+__global__ void clear_ctl_kernel(int* ctl) {
+  if (threadIdx.x < CTL_COUNT) ctl[threadIdx.x] = 0;
+}
+
+// How run_solve learns that every member has stopped.  POLL_ASYNC: copies
+// of the done flag into pinned memory, checked one interval behind (two
+// intervals stay queued).  POLL_SYNC: allocates nothing and creates no
+// events: each check copies the flag to the host and waits for the stream
+// (the queue drains once per interval).
+enum PollMode { POLL_ASYNC = 0, POLL_SYNC = 1 };
+
 static int run_solve(const ens_problem* prob, const Opts& o, int S, const double* V, const double* b,
-                     int b_bcast, double* x, const Workspace& w, hipStream_t s, SolveOut out) {
+                     int b_bcast, double* x, const Workspace& w, hipStream_t s, SolveOut out,
+                     PollMode mode = POLL_ASYNC) {
   const bool cheb = (o.precond == ENS_PRECOND_CHEBYSHEV);
   const Geometry g = geometry_for(prob, o, S);
   const int ge = init_groups(g);
 
-  HIPCHECK(hipMemsetAsync(w.m.ctl, 0, sizeof(int) * CTL_COUNT, s));
+  hipLaunchKernelGGL(clear_ctl_kernel, dim3(1), dim3(64), 0, s, w.m.ctl);
   InitArgs ia;
   std::memset(&ia, 0, sizeof(ia));
   ia.V = V;
@@ -341,19 +405,21 @@ static int run_solve(const ens_problem* prob, const Opts& o, int S, const double
   if (cheb) zfinal = cheb_apply(V, w, g, o.degree, true, false, s);
   HIPCHECK(hipGetLastError());
 
-  const bool timing = (o.flags & ENS_FLAG_TIME_SPMV) != 0;
+  const bool timing = (o.flags & ENS_FLAG_TIME_SPMV) != 0 && mode == POLL_ASYNC;
   std::vector<hipEvent_t> evs;
   std::vector<int> ev_iter;
 
-  int32_t* flag = nullptr;
-  HIPCHECK(hipHostMalloc((void**)&flag, 2 * sizeof(int32_t), hipHostMallocDefault));
-  hipEvent_t pe[2] = {nullptr, nullptr};
+  Poller* poller = nullptr;
+  if (mode == POLL_ASYNC) {
+    const int prc = acquire_poller(&poller);
+    if (prc != ENS_OK) {
+      (void)hipStreamSynchronize(s);
+      return prc;
+    }
+  }
+  int32_t* flag = poller ? poller->flag : nullptr;
   int rc = ENS_OK;
   auto fail = [&](hipError_t e) { rc = set_hip_error(e); };
-  for (int k = 0; k < 2 && rc == ENS_OK; ++k) {
-    hipError_t e = hipEventCreateWithFlags(&pe[k], hipEventDisableTiming);
-    if (e != hipSuccess) fail(e);
-  }
   int it = 0, slot = 0;
   bool have_prev = false;
   while (rc == ENS_OK && it < o.max_iter) {
@@ -405,10 +471,19 @@ static int run_solve(const ens_problem* prob, const Opts& o, int S, const double
     }
     if (rc != ENS_OK) break;
     hipError_t e = hipGetLastError();
+    if (mode == POLL_SYNC) {
+      int32_t done = 0;
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(&done, w.m.ctl + CTL_DONE, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) { fail(e); break; }
+      if (done) break;
+      continue;
+    }
     if (e == hipSuccess) e = hipMemcpyAsync(&flag[slot], w.m.ctl + CTL_DONE, sizeof(int32_t),
                                             hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipEventRecord(pe[slot], s);
-    if (e == hipSuccess && have_prev) e = hipEventSynchronize(pe[slot ^ 1]);
+    if (e == hipSuccess) e = hipEventRecord(poller->ev[slot], s);
+    if (e == hipSuccess && have_prev) e = hipEventSynchronize(poller->ev[slot ^ 1]);
     if (e != hipSuccess) { fail(e); break; }
     if (have_prev && flag[slot ^ 1]) break;
     have_prev = true;
@@ -454,9 +529,7 @@ static int run_solve(const ens_problem* prob, const Opts& o, int S, const double
     *out.stats = st;
   }
   for (hipEvent_t e : evs) (void)hipEventDestroy(e);
-  for (int k = 0; k < 2; ++k)
-    if (pe[k]) (void)hipEventDestroy(pe[k]);
-  (void)hipHostFree(flag);
+  release_poller(poller);   // the stream is idle: no copy into its flag is pending
   return rc;
 }
 
