@@ -199,6 +199,27 @@ int ens_pcg_solve(const ens_problem* prob, const ens_opts* opts, int32_t S,
                   int32_t* ens_iters_host, ens_stats* stats,
                   void* ws_dev, size_t ws_bytes, void* stream);
 
+/* The solve of ens_pcg_solve, for callers that cannot allocate memory (code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * allocation): the same kernels and results, but the workspace is the
+ * library's own device array of ENS_NOALLOC_SCRATCH_BYTES bytes (one per
+ * device, held until the process ends) and the call allocates nothing --
+ * no device or pinned memory, no events: it checks the done flag by copying
+ * it to the host and synchronising `stream` once per poll interval.
+ * Arguments and outputs as ens_pcg_solve (without stats).
+ * Errors: as ens_pcg_solve; ENS_ENOMEM when ens_pcg_workspace_bytes(prob,
+ * opts, S) exceeds ENS_NOALLOC_SCRATCH_BYTES (Jacobi: up to about 1.6e6
+ * member-rows N_r * S; Chebyshev: about 1.0e6).
+ * Every call on one device uses that device's array and leaves its contents
+ * behind (the solve clears what must start at zero): calls that overlap on
+ * one device, from several threads or streams, race and give wrong results.
+ * Blocking: synchronises `stream` before returning. */
+#define ENS_NOALLOC_SCRATCH_BYTES (64u << 20)
+int ens_pcg_solve_noalloc(const ens_problem* prob, const ens_opts* opts, int32_t S,
+                          const double* V_dev, const double* b_dev, double* x_dev,
+                          int32_t* iters_host, int32_t* status_host, double* relres_host,
+                          int32_t* ens_iters_host, void* stream);
+
 /* One ensemble matrix-vector product q = A p (the operation the solver's fused
  * kernel performs each iteration, without the fused updates).
  * In: V_dev [9][L] (3-D: [27][L]), p_dev [N_r][S]; out: q_dev [N_r][S].

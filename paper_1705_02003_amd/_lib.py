@@ -16,6 +16,7 @@ CONVERGED, MAX_ITER, BREAKDOWN, ZERO_RHS = 0, 1, 2, 3
 PRECOND_JACOBI, PRECOND_CHEBYSHEV = 0, 1
 FLAG_TIME_SPMV = 1
 FLAG_FULL_STENCIL = 2
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 i32 = C.c_int32
 i32p = C.POINTER(C.c_int32)
@@ -57,6 +58,7 @@ SIGNATURES = {
     "ens_matrix_slot_stride": (sz, [PP, i32]),
     "ens_pcg_workspace_bytes": (sz, [PP, OP, i32]),
     "ens_pcg_solve": (C.c_int, [PP, OP, i32, vp, vp, vp, i32p, i32p, f64p, i32p, SP, vp, sz, vp]),
+    "ens_pcg_solve_noalloc": (C.c_int, [PP, OP, i32, vp, vp, vp, i32p, i32p, f64p, i32p, vp]),
     "ens_spmv": (C.c_int, [PP, i32, vp, vp, vp, vp]),
     "ens_cheb_apply": (C.c_int, [PP, OP, i32, vp, vp, vp, f64p, vp, sz, vp]),
     "ens_member_dot": (C.c_int, [i32, i32, vp, vp, i32, f64p, vp, sz, vp]),

@@ -533,6 +533,33 @@ static int run_solve(const ens_problem* prob, const Opts& o, int S, const double
   return rc;
 }
 
+// ------------------------------------------------------------ no-allocation solve
+// Workspace of ens_pcg_solve_noalloc: a file-scope device array, one copy per
+// device, held while the process lives.  Host code never uses the array's
+// name as an address (on the host it names a stand-in, not device memory): the
+// device address comes from hipGetSymbolAddress, taken once per device with
+// that device current, and only that address reaches kernels.
+constexpr size_t kScratchBytes = (size_t)ENS_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+static int scratch_for_current_device(void** out) {
+  int dev = 0;
+  HIPCHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return ENS_ENOTSUP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIPCHECK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return ENS_EHIP;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return ENS_OK;
+}
+
 }  // namespace ens
 
 using namespace ens;
@@ -630,6 +657,26 @@ int ens_pcg_solve(const ens_problem* prob, const ens_opts* opts, int32_t S, cons
   const Workspace w = carve_workspace(ws_dev, rows_of(prob), S, cheb);
   SolveOut out{iters_host, status_host, relres_host, ens_iters_host, stats};
   return run_solve(prob, o, S, V_dev, b_dev, 0, x_dev, w, (hipStream_t)stream, out);
+}
+
+int ens_pcg_solve_noalloc(const ens_problem* prob, const ens_opts* opts, int32_t S,
+                          const double* V_dev, const double* b_dev, double* x_dev,
+                          int32_t* iters_host, int32_t* status_host, double* relres_host,
+                          int32_t* ens_iters_host, void* stream) {
+  int rc = check_problem(prob);
+  if (rc) return rc;
+  Opts o;
+  rc = resolve_opts(opts, o);
+  if (rc) return rc;
+  if (!valid_S(S) || !V_dev || !b_dev || !x_dev) return ENS_EINVAL;
+  const bool cheb = o.precond == ENS_PRECOND_CHEBYSHEV;
+  if (workspace_bytes(rows_of(prob), S, cheb) > kScratchBytes) return ENS_ENOMEM;
+  void* base = nullptr;
+  rc = scratch_for_current_device(&base);
+  if (rc) return rc;
+  const Workspace w = carve_workspace(base, rows_of(prob), S, cheb);
+  SolveOut out{iters_host, status_host, relres_host, ens_iters_host, nullptr};
+  return run_solve(prob, o, S, V_dev, b_dev, 0, x_dev, w, (hipStream_t)stream, out, POLL_SYNC);
 }
 
 int ens_spmv(const ens_problem* prob, int32_t S, const double* V_dev, const double* p_dev,

@@ -189,6 +189,32 @@ def solve(prob: Problem, V: torch.Tensor, b: torch.Tensor, opts: Optional[Solver
     return SolveResult(x, iters, status, relres, int(ens_iters.value), st)
 
 
+def solve_noalloc(prob: Problem, V: torch.Tensor, b: torch.Tensor,
+                  opts: Optional[SolverOptions] = None, x: Optional[torch.Tensor] = None):
+    """The solve of `solve` through ens_pcg_solve_noalloc: the library's own
+    per-device workspace, nothing allocated by the call (x must be given for
+    that).  Calls that overlap on one device race.  Returns SolveResult
+    (stats empty)."""
+    opts = opts or SolverOptions()
+    S = _ensemble_width(b)
+    _require_matrix(V, prob, S)
+    _require_cuda(b, "b", (prob.rows, S))
+    if x is None:
+        x = torch.empty_like(b)
+    _require_cuda(x, "x", (prob.rows, S))
+    iters = np.zeros(S, np.int32)
+    status = np.zeros(S, np.int32)
+    relres = np.zeros(S, np.float64)
+    ens_iters = C.c_int32(0)
+    pc, oc = prob.c(), opts.c()
+    L.check(L.lib().ens_pcg_solve_noalloc(
+        C.byref(pc), C.byref(oc), S, _p(V), _p(b), _p(x),
+        iters.ctypes.data_as(L.i32p), status.ctypes.data_as(L.i32p),
+        relres.ctypes.data_as(L.f64p), C.byref(ens_iters), _stream(V.device)),
+        "ens_pcg_solve_noalloc")
+    return SolveResult(x, iters, status, relres, int(ens_iters.value), {})
+
+
 def spmv(prob: Problem, V: torch.Tensor, p: torch.Tensor) -> torch.Tensor:
     S = _ensemble_width(p)
     _require_matrix(V, prob, S)
