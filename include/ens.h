@@ -27,9 +27,12 @@
  *    (i + di, j + dj): k = 0 SW, 1 S, 2 SE, 3 W, 4 C (diagonal), 5 E, 6 NW,
  *    7 N, 8 NE -- the column order of a CSR row.  Slots that would couple to
  *    a boundary node hold 0 (zero Dirichlet data).
- *  - S must be a power of two, 1 <= S <= 64.  Callers with another count pad
- *    the ensemble by repeating its last sample (paper, Section 4, Test 1
- *    footnote).
+ *  - Any ensemble width 1 <= S <= 64 (the paper's typical widths are 4 to
+ *    32, Section 2.3; its Table 1 uses 20).  Inside the kernels a point's
+ *    members are handled by a power-of-two group of lanes, so a width that
+ *    is not a power of two leaves some lanes idle but moves only the S
+ *    members' bytes.  (The batched solver, ens_batch_solve, takes widths
+ *    that are powers of two, at least 2.)
  *  - "_dev" pointers are device memory of the current HIP device, "_host"
  *    pointers are host memory.  The caller owns every buffer; the library
  *    allocates no device memory, keeps no pointer after a call returns, and
@@ -119,8 +122,9 @@ typedef struct {
   int32_t tile_lines;   /* stencil tile height in grid lines, 0 = heuristic   */
   int32_t max_groups;   /* workgroups of the stencil/update kernels, 0 = heuristic */
   int32_t flags;        /* ENS_FLAG_* bits below                              */
-  int32_t member_tile;  /* members per stencil tile: a power of two dividing S
-                           (a wide ensemble is swept in member tiles); 0 = S  */
+  int32_t member_tile;  /* members per stencil tile: a power of two (a wide
+                           ensemble is swept in tiles of this many members,
+                           the last tile holding the rest); 0 or >= S: S */
 } ens_opts;
 
 /* Time the fused SpMV kernel with HIP events (ens_stats.spmv_ms). */
@@ -148,18 +152,20 @@ typedef struct {
 /* ------------------------------------------------------------ assembly */
 /* Assemble the ensemble matrix and right-hand side for S members.
  * Paper: Section 2.3 (each nonzero stored as a length-S array; mesh and graph
- * are sample independent and shared).  y_dev: [S][d] parameters (device).
+ * are sample independent and shared: the tables of the a(x) modes at the grid
+ * nodes are computed once per tile for all members).  y_host: [S][d]
+ * parameters (host memory; read before the call returns -- they travel with
+ * the kernel launches -- so the array may be reused at once).
  * Outputs V_dev [9][L] (A, with the 1/h^2 included; L the slot stride, the
  * padding is not written) and b_dev [N_r][S]
  * (f = 1).  3-D model: V_dev [27][L], the finite-element stiffness matrix
  * (each cube's matrix integrated exactly with a held at the cube's centre),
  * b = h^3 (the load of f = 1).  Asynchronous on `stream`.
- * Errors: ENS_EINVAL for a NULL pointer, n < 2, d outside [2,16], eps_model
- * outside {0,1}, S not a power of two in [1,64], or non-finite amp (3-D: the
- * limits of the descriptor above; n <= 1024).  The
- * parameter values themselves are read on the device; a non-finite y gives
- * non-finite matrix values for that member only (reject them on the host). */
-int ens_assemble_ensemble(const ens_problem* prob, int32_t S, const double* y_dev,
+ * Errors (before any device work): ENS_EINVAL for a NULL pointer, a
+ * non-finite parameter value, n < 2, d outside [2,16], eps_model outside
+ * {0,1}, S outside [1,64], or non-finite amp (3-D: the limits of the
+ * descriptor above; n <= 1024). */
+int ens_assemble_ensemble(const ens_problem* prob, int32_t S, const double* y_host,
                           double* V_dev, double* b_dev, void* stream);
 
 /* Elements L from the start of one matrix slot to the next in every V_dev
@@ -248,11 +254,11 @@ int ens_member_dot(int32_t N_r, int32_t S, const double* a_dev, const double* b_
  * lambda_max / lambda_min of the diffusion tensor.  2-D model: a(x) K(y) has
  * eigenvalues a and a eps, so H = 1 / eps(y'_0).  3-D model: diag(a, a_y,
  * a_z) with a held on each cube, so H = the largest max(a, a_y, a_z) /
- * min(a, a_y, a_z) over the cubes.  In: y_dev [S][d] (device).  Out:
- * h_host [S].  Uses the first ens_pcg_workspace_bytes(...) bytes of ws.
- * Blocking.  Errors: as ens_assemble_ensemble; ENS_ENOMEM for a too-small
- * workspace. */
-int ens_param_indicator(const ens_problem* prob, int32_t S, const double* y_dev,
+ * min(a, a_y, a_z) over the cubes.  In: y_host [S][d] (host; copied into the
+ * workspace).  Out: h_host [S].  Uses the first ens_pcg_workspace_bytes(...)
+ * bytes of ws.  Blocking.  Errors: as ens_assemble_ensemble; ENS_ENOMEM for
+ * a too-small workspace. */
+int ens_param_indicator(const ens_problem* prob, int32_t S, const double* y_host,
                         double* h_host, void* ws_dev, size_t ws_bytes, void* stream);
 
 /* ----------------------------------------------------------- adjoint */
@@ -261,21 +267,32 @@ int ens_param_indicator(const ens_problem* prob, int32_t S, const double* y_dev,
  *   dQ_s/dy_j = -lambda_s^T (dA_s/dy_j) u_s,
  * the bilinear form evaluated face by face and node by node from the
  * coefficient derivatives (not from a differentiated matrix).
- * In: y_dev [S][d], V_dev (assembled for y), u_dev [N_r][S] (forward
- * solution), w_dev [N_r] (shared QoI weights).  Out: lambda_dev [N_r][S],
+ * In: y_host [S][d] (host; finite, else ENS_EINVAL; copied into the
+ * workspace), V_dev (assembled for y), u_dev [N_r][S] (forward solution),
+ * w_dev [N_r] (shared QoI weights, e.g. ens_qoi_weights).  Out: lambda_dev [N_r][S],
  * grad_host [S][d], iters_host[S], status_host[S] of the adjoint solve.
  * 3-D model: only a depends on y; on cube c, da_c/dy_j = a_hat exp(g_c)
  * sqrt(lambda_j) b_j(x_c), and the form is the sum over cubes of that
  * derivative times lambda_c^T (Kx My Mz) u_c.  Blocking. */
 int ens_adjoint_grad(const ens_problem* prob, const ens_opts* opts, int32_t S,
-                     const double* y_dev, const double* V_dev, const double* u_dev,
+                     const double* y_host, const double* V_dev, const double* u_dev,
                      const double* w_dev, double* lambda_dev, double* grad_host,
                      int32_t* iters_host, int32_t* status_host,
                      void* ws_dev, size_t ws_bytes, void* stream);
 
+/* The weights of the quantity of interest Q = w^T u, the mean of u over the
+ * interior nodes in the box [0.4, 0.6]^dim (paper, Section 2.1: the output of
+ * interest is a spatial functional of the solution; the box mean is this
+ * model's choice).  w_dev [N_r]: 1 / count at the nodes inside, 0 elsewhere;
+ * node index i in [1, n] is inside when 2 (n + 1) <= 5 i <= 3 (n + 1), decided
+ * in integers.  Asynchronous on `stream`.  Errors: as the problem descriptor;
+ * ENS_EINVAL for a NULL pointer or when no node lies in the box (n = 2). */
+int ens_qoi_weights(const ens_problem* prob, double* w_dev, void* stream);
+
 /* The dQ/dy kernel alone: grad_host[s][j] = -lambda_s^T (dA_s/dy_j) u_s for
- * given u and lambda (both models).  Blocking. */
-int ens_dqdy(const ens_problem* prob, int32_t S, const double* y_dev,
+ * given u and lambda (both models); y_host [S][d] as in ens_adjoint_grad.
+ * Blocking. */
+int ens_dqdy(const ens_problem* prob, int32_t S, const double* y_host,
              const double* u_dev, const double* lambda_dev, double* grad_host,
              void* ws_dev, size_t ws_bytes, void* stream);
 

@@ -64,6 +64,7 @@ SIGNATURES = {
     "ens_member_dot": (C.c_int, [i32, i32, vp, vp, i32, f64p, vp, sz, vp]),
     "ens_adjoint_grad": (C.c_int, [PP, OP, i32, vp, vp, vp, vp, vp, f64p, i32p, i32p, vp, sz, vp]),
     "ens_dqdy": (C.c_int, [PP, i32, vp, vp, vp, f64p, vp, sz, vp]),
+    "ens_qoi_weights": (C.c_int, [PP, vp, vp]),
     "ens_group_samples": (C.c_int, [i32, i32, i32p, i32p, f64p, i32, f64p, i32, i32p, f64p]),
     "ens_sg_surpluses": (C.c_int, [i32, i32, i32p, i32p, f64p, f64p]),
     "ens_sg_expectation": (C.c_int, [i32, i32, i32p, i32p, f64p, f64p]),

@@ -60,18 +60,27 @@ __device__ __forceinline__ void reduce_group(double (&v)[VEC], int tpp, double* 
 
 constexpr int kMaxD = 16;
 
+// Tiles of kAsmTX x kAsmTY grid points, grid-strided over the workgroups.
+// Per tile the mode tables sin(k pi I h) at the tile's node columns and rows
+// are computed once and shared by every point and member of the tile (the
+// sample-independent part of the form); per (point, member) the five a
+// values and their mode derivatives follow from the tables.
 template <int VEC>
 __global__ __launch_bounds__(kNT) void dqdy_kernel(DqdyArgs a) {
   __shared__ double red[kWaves * 64 * 2];
+  __shared__ double sI[kMaxModes][kAsmTX + 2];
+  __shared__ double sJ[kMaxModes][kAsmTY + 2];
   const Geometry& g = a.g;
-  const int S = g.S, n = g.n, tpp = g.tpp, t = threadIdx.x, d = a.d;
+  const int S = g.S, n = g.n, tpp = g.tpp, t = threadIdx.x, d = a.d, nm = a.d - 2;
   const int sv = (t % tpp) * VEC;
+  const bool lane_ok = sv < S;
+  const int svl = lane_ok ? sv : S - VEC;   // idle slots compute on real members, add nothing
 
   // per-member coefficients and their derivatives
   double k11[VEC], k22[VEC], k12[VEC], dk[2][3][VEC], ym[VEC][kMaxD];
 #pragma unroll
   for (int c = 0; c < VEC; ++c) {
-    const double* y = a.y + (size_t)(sv + c) * d;
+    const double* y = a.y + (size_t)(svl + c) * d;
 #pragma unroll
     for (int q = 0; q < kMaxD; ++q) ym[c][q] = (q < d) ? y[q] : 0.0;
     const double eps = (a.eps_model == 0) ? pow(10.0, -(1.0 + y[0])) : pow(10.0, -(1.5 + 1.5 * y[0]));
@@ -96,72 +105,83 @@ __global__ __launch_bounds__(kNT) void dqdy_kernel(DqdyArgs a) {
     for (int c = 0; c < VEC; ++c) acc[q][c] = 0.0;
 
   const double np1 = (double)(n + 1);
-  const size_t stride = (size_t)gridDim.x * kNT * VEC;
-  for (size_t e = ((size_t)blockIdx.x * kNT + t) * VEC; e < g.nelem; e += stride) {
-    const size_t row = e >> g.logS;
-    const int i = (int)(row % n), j = (int)(row / n);
-    const size_t rS = (size_t)S;
-    double uC[VEC], uE[VEC], uW[VEC], uN[VEC], uS[VEC];
-    double lC[VEC], lE[VEC], lW[VEC], lN[VEC], lS[VEC];
-    ldv<VEC>(uC, a.u + e);
-    ldv<VEC>(lC, a.lam + e);
-#pragma unroll
-    for (int c = 0; c < VEC; ++c) uE[c] = uW[c] = uN[c] = uS[c] = lE[c] = lW[c] = lN[c] = lS[c] = 0.0;
-    if (i + 1 < n) { ldv<VEC>(uE, a.u + e + rS); ldv<VEC>(lE, a.lam + e + rS); }
-    if (i > 0) { ldv<VEC>(uW, a.u + e - rS); ldv<VEC>(lW, a.lam + e - rS); }
-    if (j + 1 < n) { ldv<VEC>(uN, a.u + e + rS * n); ldv<VEC>(lN, a.lam + e + rS * n); }
-    if (j > 0) { ldv<VEC>(uS, a.u + e - rS * n); ldv<VEC>(lS, a.lam + e - rS * n); }
-    // node values of sin(k pi x) at the five nodes (1-based I = i+1, J = j+1)
-    const int I = i + 1, J = j + 1;
-    double fE[VEC], fN[VEC], fW[VEC], fS[VEC], fm[VEC];
-#pragma unroll
-    for (int c = 0; c < VEC; ++c) {
-      fE[c] = (lE[c] - lC[c]) * (uE[c] - uC[c]);
-      fN[c] = (lN[c] - lC[c]) * (uN[c] - uC[c]);
-      fW[c] = (i == 0) ? lC[c] * uC[c] : 0.0;   // face from the boundary node
-      fS[c] = (j == 0) ? lC[c] * uC[c] : 0.0;
-      fm[c] = (lE[c] - lW[c]) * (uN[c] - uS[c]) + (lN[c] - lS[c]) * (uE[c] - uW[c]);
+  const size_t rS = (size_t)S;
+  for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+    const int i0 = (tile % a.ntx) * kAsmTX, j0 = (tile / a.ntx) * kAsmTY;
+    __syncthreads();   // the previous tile's readers are done with the tables
+    for (int x = t; x < nm * (kAsmTX + 2); x += kNT) {
+      const int k = x / (kAsmTX + 2), q = x % (kAsmTX + 2);
+      sI[k][q] = sin((double)(k + 1) * M_PI * ((double)(i0 + q) / np1));
     }
-    // a and its mode derivatives at C, E, W, N, S
-    double aC[VEC], aE[VEC], aW[VEC], aN[VEC], aS[VEC];
+    for (int x = t; x < nm * (kAsmTY + 2); x += kNT) {
+      const int k = x / (kAsmTY + 2), q = x % (kAsmTY + 2);
+      sJ[k][q] = sin((double)(k + 1) * M_PI * ((double)(j0 + q) / np1));
+    }
+    __syncthreads();
+    if (!lane_ok) continue;
+    for (int pt = t / tpp; pt < kAsmTX * kAsmTY; pt += kNT / tpp) {
+      const int i = i0 + pt % kAsmTX, j = j0 + pt / kAsmTX;
+      if (i >= n || j >= n) continue;
+      const size_t e = ((size_t)j * n + i) * rS + sv;
+      double uC[VEC], uE[VEC], uW[VEC], uN[VEC], uS[VEC];
+      double lC[VEC], lE[VEC], lW[VEC], lN[VEC], lS[VEC];
+      ldv<VEC>(uC, a.u + e);
+      ldv<VEC>(lC, a.lam + e);
 #pragma unroll
-    for (int c = 0; c < VEC; ++c) aC[c] = aE[c] = aW[c] = aN[c] = aS[c] = 1.0;
-#pragma unroll
-    for (int k = 1; k <= kMaxD - 2; ++k) {
-      if (k <= d - 2) {
-      const double kp = (double)k * M_PI;
-      const double sIm = sin(kp * ((double)(I - 1) / np1)), sI = sin(kp * ((double)I / np1));
-      const double sIp = sin(kp * ((double)(I + 1) / np1));
-      const double sJm = sin(kp * ((double)(J - 1) / np1)), sJ = sin(kp * ((double)J / np1));
-      const double sJp = sin(kp * ((double)(J + 1) / np1));
-      const double w = a.amp / (double)(k * k);
-      const double mC = w * sJ * sI, mE = w * sJ * sIp, mW = w * sJ * sIm;
-      const double mN = w * sJp * sI, mS = w * sJm * sI;
+      for (int c = 0; c < VEC; ++c) uE[c] = uW[c] = uN[c] = uS[c] = lE[c] = lW[c] = lN[c] = lS[c] = 0.0;
+      if (i + 1 < n) { ldv<VEC>(uE, a.u + e + rS); ldv<VEC>(lE, a.lam + e + rS); }
+      if (i > 0) { ldv<VEC>(uW, a.u + e - rS); ldv<VEC>(lW, a.lam + e - rS); }
+      if (j + 1 < n) { ldv<VEC>(uN, a.u + e + rS * n); ldv<VEC>(lN, a.lam + e + rS * n); }
+      if (j > 0) { ldv<VEC>(uS, a.u + e - rS * n); ldv<VEC>(lS, a.lam + e - rS * n); }
+      double fE[VEC], fN[VEC], fW[VEC], fS[VEC], fm[VEC];
 #pragma unroll
       for (int c = 0; c < VEC; ++c) {
-        const double yk = ym[c][k + 1];
-        aC[c] += yk * mC;
-        aE[c] += yk * mE;
-        aW[c] += yk * mW;
-        aN[c] += yk * mN;
-        aS[c] += yk * mS;
-        // mode derivative contributions
-        const double gx = ((mC + mE) / 2.0) * fE[c] + ((mW + mC) / 2.0) * fW[c];
-        const double gy = ((mC + mN) / 2.0) * fN[c] + ((mS + mC) / 2.0) * fS[c];
-        acc[k + 1][c] += k11[c] * gx + k22[c] * gy + k12[c] * mC * fm[c] / 4.0;
+        fE[c] = (lE[c] - lC[c]) * (uE[c] - uC[c]);
+        fN[c] = (lN[c] - lC[c]) * (uN[c] - uC[c]);
+        fW[c] = (i == 0) ? lC[c] * uC[c] : 0.0;   // face from the boundary node
+        fS[c] = (j == 0) ? lC[c] * uC[c] : 0.0;
+        fm[c] = (lE[c] - lW[c]) * (uN[c] - uS[c]) + (lN[c] - lS[c]) * (uE[c] - uW[c]);
       }
+      // a and its mode derivatives at C, E, W, N, S; table columns of the
+      // nodes i, i + 1, i + 2 (1-based node I = i + 1)
+      const int qi = i - i0 + 1, qj = j - j0 + 1;
+      double aC[VEC], aE[VEC], aW[VEC], aN[VEC], aS[VEC];
+#pragma unroll
+      for (int c = 0; c < VEC; ++c) aC[c] = aE[c] = aW[c] = aN[c] = aS[c] = 1.0;
+#pragma unroll
+      for (int k = 1; k <= kMaxD - 2; ++k) {
+        if (k <= nm) {
+          const double sIm = sI[k - 1][qi - 1], sIc = sI[k - 1][qi], sIp = sI[k - 1][qi + 1];
+          const double sJm = sJ[k - 1][qj - 1], sJc = sJ[k - 1][qj], sJp = sJ[k - 1][qj + 1];
+          const double w = a.amp / (double)(k * k);
+          const double mC = w * sJc * sIc, mE = w * sJc * sIp, mW = w * sJc * sIm;
+          const double mN = w * sJp * sIc, mS = w * sJm * sIc;
+#pragma unroll
+          for (int c = 0; c < VEC; ++c) {
+            const double yk = ym[c][k + 1];
+            aC[c] += yk * mC;
+            aE[c] += yk * mE;
+            aW[c] += yk * mW;
+            aN[c] += yk * mN;
+            aS[c] += yk * mS;
+            // mode derivative contributions
+            const double gx = ((mC + mE) / 2.0) * fE[c] + ((mW + mC) / 2.0) * fW[c];
+            const double gy = ((mC + mN) / 2.0) * fN[c] + ((mS + mC) / 2.0) * fS[c];
+            acc[k + 1][c] += k11[c] * gx + k22[c] * gy + k12[c] * mC * fm[c] / 4.0;
+          }
+        }
       }
-    }
 #pragma unroll
-    for (int c = 0; c < VEC; ++c) {
-      const double gx = ((aC[c] + aE[c]) / 2.0) * fE[c] + ((aW[c] + aC[c]) / 2.0) * fW[c];
-      const double gy = ((aC[c] + aN[c]) / 2.0) * fN[c] + ((aS[c] + aC[c]) / 2.0) * fS[c];
-      const double gm = aC[c] * fm[c] / 4.0;
+      for (int c = 0; c < VEC; ++c) {
+        const double gx = ((aC[c] + aE[c]) / 2.0) * fE[c] + ((aW[c] + aC[c]) / 2.0) * fW[c];
+        const double gy = ((aC[c] + aN[c]) / 2.0) * fN[c] + ((aS[c] + aC[c]) / 2.0) * fS[c];
+        const double gm = aC[c] * fm[c] / 4.0;
 #pragma unroll
-      for (int q = 0; q < 2; ++q) acc[q][c] += dk[q][0][c] * gx + dk[q][1][c] * gy + dk[q][2][c] * gm;
+        for (int q = 0; q < 2; ++q) acc[q][c] += dk[q][0][c] * gx + dk[q][1][c] * gy + dk[q][2][c] * gm;
+      }
     }
   }
-  const size_t ps = (size_t)gridDim.x * S;
+  const size_t ps = (size_t)gridDim.x * g.Sp;
 #pragma unroll
   for (int q = 0; q < kMaxD; ++q) {
     if (q < d) {
@@ -171,7 +191,7 @@ __global__ __launch_bounds__(kNT) void dqdy_kernel(DqdyArgs a) {
       reduce_group<VEC>(v, tpp, red);
       if (t < tpp) {
 #pragma unroll
-        for (int c = 0; c < VEC; ++c) a.partial[q * ps + (size_t)blockIdx.x * S + t * VEC + c] = v[c];
+        for (int c = 0; c < VEC; ++c) a.partial[q * ps + (size_t)blockIdx.x * g.Sp + t * VEC + c] = v[c];
       }
     }
   }

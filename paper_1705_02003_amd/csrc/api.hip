@@ -18,13 +18,7 @@ int set_hip_error(hipError_t e) {
   return ENS_EHIP;
 }
 
-int valid_S(int S) { return S >= 1 && S <= kMaxS && (S & (S - 1)) == 0; }
-
-static int log2i(int v) {
-  int l = 0;
-  while ((1 << l) < v) ++l;
-  return l;
-}
+int valid_S(int S) { return S >= 1 && S <= kMaxS; }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -32,6 +26,7 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // followed by the ensemble vectors.
 static size_t header_bytes() {
   size_t b = 0;
+  b += align256(sizeof(double) * (size_t)kMaxS * 16);              // staged parameters
   b += align256(sizeof(double) * 3 * (size_t)kMaxGroups * kMaxS);  // partials
   b += align256(sizeof(double) * 7 * (size_t)kMaxS);               // doubles
   b += align256(sizeof(double) * (size_t)kMaxS * kChebCoef);       // cheb
@@ -54,6 +49,8 @@ Workspace carve_workspace(void* base, size_t nr, int S, bool cheb) {
   Workspace w;
   std::memset(&w, 0, sizeof(w));
   char* p = static_cast<char*>(base);
+  w.y = reinterpret_cast<double*>(p);
+  p += align256(sizeof(double) * (size_t)kMaxS * 16);
   w.partial = reinterpret_cast<double*>(p);
   p += align256(sizeof(double) * 3 * (size_t)kMaxGroups * kMaxS);
   double* dd = reinterpret_cast<double*>(p);
@@ -87,20 +84,29 @@ Workspace carve_workspace(void* base, size_t nr, int S, bool cheb) {
   return w;
 }
 
+// Member lanes of an ensemble of S: VEC = 2 for even S, the slots of a point
+// rounded up to a power of two.
+static void member_lanes(Geometry& g, int S) {
+  g.S = S;
+  g.vec = (S % 2 == 0) ? 2 : 1;
+  g.tpp = pow2ceil(S / g.vec);
+  g.Sp = g.tpp * g.vec;
+}
+
 Geometry make_geometry(int n, int S, int tile_lines, int max_groups, int member_tile) {
   Geometry g;
+  std::memset(&g, 0, sizeof(g));
   g.n = n;
-  g.S = S;
-  g.logS = log2i(S);
-  g.vec = (S >= 2) ? 2 : 1;
-  g.tpp = S / g.vec;
-  // member tile: a power of two dividing S, at least one thread pair wide
-  int sw = (member_tile > 0) ? std::min(member_tile, S) : S;
+  member_lanes(g, S);
+  // member tile: a power of two (the whole ensemble when it is at least S),
+  // at least one thread's members wide; the last tile may hold fewer
+  int sw = (member_tile > 0 && member_tile < S) ? member_tile : S;
   if (sw < g.vec) sw = g.vec;
   g.sw = sw;
-  g.nstile = S / sw;
-  g.stpp = sw / g.vec;
-  g.tx = kNT * g.vec / sw;
+  g.nstile = (S + sw - 1) / sw;
+  g.stpp = (sw == S) ? g.tpp : pow2ceil(sw / g.vec);
+  g.swp = g.stpp * g.vec;
+  g.tx = kNT * g.vec / g.swp;
   g.nchunk = (n + g.tx - 1) / g.tx;
   // Defaults measured on MI355X at 512^2 and S = 1..64: 512 workgroups (two
   // per CU) with the tallest tile of at most 32 lines that still gives every
@@ -137,13 +143,11 @@ Geometry make_geometry3(int m, int S) {
   Geometry g;
   std::memset(&g, 0, sizeof(g));
   g.n = m;
-  g.S = S;
-  g.logS = log2i(S);
-  g.vec = (S >= 2) ? 2 : 1;
-  g.tpp = S / g.vec;
+  member_lanes(g, S);
   g.sw = S;
   g.nstile = 1;
   g.stpp = g.tpp;
+  g.swp = g.Sp;
   g.nr = (size_t)m * m * m;
   g.nelem = g.nr * S;
   g.vstride = slot_stride(g.nelem);
@@ -159,9 +163,9 @@ Geometry make_geometry3(int m, int S) {
 }
 
 int init_groups(const Geometry& g) {
-  const size_t per = (size_t)kNT * g.vec;
-  const size_t need = (g.nelem + per - 1) / per;
-  return (int)std::min<size_t>(need, 512);
+  const size_t per = (size_t)(kNT / g.tpp);   // points per workgroup and pass
+  const size_t need = (g.nr + per - 1) / per;
+  return (int)std::min<size_t>(std::max<size_t>(need, 1), 512);
 }
 
 static bool is3d(const ens_problem* p) { return p->dim == 3; }
@@ -591,42 +595,104 @@ const char* ens_strerror(int code) {
   }
 }
 
-int ens_assemble_ensemble(const ens_problem* prob, int32_t S, const double* y_dev, double* V_dev,
+// finite parameters only: the matrix of a member with a non-finite parameter
+// would hold non-finite values
+static int check_params(const double* y_host, int S, int d) {
+  if (!y_host) return ENS_EINVAL;
+  for (size_t k = 0; k < (size_t)S * d; ++k)
+    if (!std::isfinite(y_host[k])) return ENS_EINVAL;
+  return ENS_OK;
+}
+
+// members per assembly launch: as many as kAsmY parameter values hold
+static int asm_chunk(int S, int d) { return std::max(1, std::min(S, kAsmY / d)); }
+
+int ens_assemble_ensemble(const ens_problem* prob, int32_t S, const double* y_host, double* V_dev,
                           double* b_dev, void* stream) {
   int rc = check_problem(prob);
   if (rc) return rc;
-  if (!valid_S(S) || !y_dev || !V_dev || !b_dev) return ENS_EINVAL;
+  if (!valid_S(S) || !V_dev || !b_dev) return ENS_EINVAL;
+  rc = check_params(y_host, S, prob->d);
+  if (rc) return rc;
+  const int d = prob->d;
+  const int mcmax = asm_chunk(S, d);
+  hipStream_t st = (hipStream_t)stream;
   if (is3d(prob)) {
     Fe3dAsmArgs f;
     std::memset(&f, 0, sizeof(f));
     rc = fe3d_setup(prob, f);
     if (rc) return rc;
-    f.y = y_dev;
     f.V = V_dev;
     f.b = b_dev;
     f.m = prob->n;
     f.S = S;
-    f.logS = log2i(S);
-    f.d = prob->d;
-    f.nelem = rows_of(prob) * S;
-    f.vstride = slot_stride(f.nelem);
-    launch_fe3d_assemble(f, (hipStream_t)stream);
+    f.d = d;
+    f.nr = rows_of(prob);
+    f.vstride = slot_stride(f.nr * S);
+    for (int m0 = 0; m0 < S; m0 += mcmax) {
+      f.m0 = m0;
+      f.mc = std::min(mcmax, S - m0);
+      f.mcp = pow2ceil(f.mc);
+      std::memcpy(f.y, y_host + (size_t)m0 * d, sizeof(double) * (size_t)f.mc * d);
+      launch_fe3d_assemble(f, st);
+    }
     HIPCHECK(hipGetLastError());
     return ENS_OK;
   }
   AsmArgs a;
-  a.y = y_dev;
+  std::memset(&a, 0, sizeof(a));
   a.V = V_dev;
   a.b = b_dev;
   a.n = prob->n;
   a.S = S;
-  a.logS = log2i(S);
-  a.d = prob->d;
+  a.d = d;
   a.eps_model = prob->eps_model;
   a.amp = prob->amp;
-  a.nelem = (size_t)prob->n * prob->n * S;
-  a.vstride = slot_stride(a.nelem);
-  launch_assemble(a, (hipStream_t)stream);
+  a.ntx = (prob->n + kAsmTX - 1) / kAsmTX;
+  a.vstride = slot_stride((size_t)prob->n * prob->n * S);
+  for (int m0 = 0; m0 < S; m0 += mcmax) {
+    a.m0 = m0;
+    a.mc = std::min(mcmax, S - m0);
+    a.mcp = pow2ceil(a.mc);
+    std::memcpy(a.y, y_host + (size_t)m0 * d, sizeof(double) * (size_t)a.mc * d);
+    launch_assemble(a, st);
+  }
+  HIPCHECK(hipGetLastError());
+  return ENS_OK;
+}
+
+// The QoI weights (paper, Section 2.1: a spatial mean of u): 1 / count at the
+// interior nodes inside [0.4, 0.6]^dim, 0 elsewhere, in row order.  A node
+// index i (1-based) is inside when 2 (n + 1) <= 5 i <= 3 (n + 1), decided in
+// integers.
+__global__ void qoi_weights_kernel(double* w, int n, int dim, double inv_count, size_t nr) {
+  const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nr) return;
+  size_t rest = r;
+  bool in = true;
+  for (int q = 0; q < dim; ++q) {
+    const long long i = (long long)(rest % (size_t)n) + 1;
+    rest /= (size_t)n;
+    in = in && 5 * i >= 2LL * (n + 1) && 5 * i <= 3LL * (n + 1);
+  }
+  w[r] = in ? inv_count : 0.0;
+}
+
+int ens_qoi_weights(const ens_problem* prob, double* w_dev, void* stream) {
+  int rc = check_problem(prob);
+  if (rc) return rc;
+  if (!w_dev) return ENS_EINVAL;
+  const int n = prob->n, dim = is3d(prob) ? 3 : 2;
+  long long per = 0;
+  for (long long i = 1; i <= n; ++i)
+    if (5 * i >= 2LL * (n + 1) && 5 * i <= 3LL * (n + 1)) ++per;
+  if (per == 0) return ENS_EINVAL;   // no node inside the box (n = 2)
+  long long count = 1;
+  for (int q = 0; q < dim; ++q) count *= per;
+  const size_t nr = rows_of(prob);
+  const unsigned blocks = (unsigned)((nr + kNT - 1) / kNT);
+  hipLaunchKernelGGL(qoi_weights_kernel, dim3(blocks), dim3(kNT), 0, (hipStream_t)stream, w_dev, n,
+                     dim, 1.0 / (double)count, nr);
   HIPCHECK(hipGetLastError());
   return ENS_OK;
 }
@@ -792,6 +858,9 @@ int ens_member_dot(int32_t N_r, int32_t S, const double* a_dev, const double* b_
 static int dqdy3(const ens_problem* prob, int32_t S, const double* y_dev, const double* u_dev,
                  const double* lambda_dev, double* grad_host, void* ws_dev, void* stream) {
   const Workspace w = carve_workspace(ws_dev, 0, S, false);
+  Geometry lanes;
+  std::memset(&lanes, 0, sizeof(lanes));
+  member_lanes(lanes, S);
   Fe3dDqdyArgs a;
   std::memset(&a, 0, sizeof(a));
   Fe3dAsmArgs f;
@@ -805,11 +874,11 @@ static int dqdy3(const ens_problem* prob, int32_t S, const double* y_dev, const 
   a.partial = w.partial;
   a.m = prob->n;
   a.S = S;
-  a.logS = log2i(S);
+  a.Sp = pow2ceil(S);
   a.d = prob->d;
   a.ncell = (size_t)(prob->n + 1) * (prob->n + 1) * (prob->n + 1);
-  // d <= 16 partial arrays of groups * S doubles must fit the partial buffer
-  const int groups = (int)std::min<size_t>((a.ncell * S + kNT - 1) / kNT,
+  // d <= 16 partial arrays of groups * Sp doubles must fit the partial buffer
+  const int groups = (int)std::min<size_t>((a.ncell * a.Sp + kNT - 1) / kNT,
                                            (size_t)(3 * kMaxGroups / kMaxTerms));
   hipStream_t s = (hipStream_t)stream;
   HIPCHECK(hipMemsetAsync(w.m.ctl, 0, sizeof(int) * CTL_COUNT, s));
@@ -821,7 +890,9 @@ static int dqdy3(const ens_problem* prob, int32_t S, const double* y_dev, const 
     fa.G = groups;
     fa.kind = F_SUMS;
     fa.m = w.m;
-    fa.g = make_geometry(2, S, 0, 0);
+    fa.g = lanes;
+    fa.g.vec = 1;        // one member per thread: slots Sp = pow2ceil(S)
+    fa.g.tpp = fa.g.Sp = pow2ceil(S);
     fa.nsum = prob->d;
     fa.scale = -1.0;
     launch_finish(fa, s);
@@ -835,13 +906,24 @@ static int dqdy3(const ens_problem* prob, int32_t S, const double* y_dev, const 
   return ENS_OK;
 }
 
-int ens_param_indicator(const ens_problem* prob, int32_t S, const double* y_dev, double* h_host,
+// copy the caller's parameters into the workspace (the blocking entry points
+// synchronise the stream before returning, so the host array is read in time)
+static int stage_params(const Workspace& w, const double* y_host, int S, int d, hipStream_t s) {
+  HIPCHECK(hipMemcpyAsync(w.y, y_host, sizeof(double) * (size_t)S * d, hipMemcpyHostToDevice, s));
+  return ENS_OK;
+}
+
+int ens_param_indicator(const ens_problem* prob, int32_t S, const double* y_host, double* h_host,
                         void* ws_dev, size_t ws_bytes, void* stream) {
   int rc = check_problem(prob);
   if (rc) return rc;
-  if (!valid_S(S) || !y_dev || !h_host || !ws_dev) return ENS_EINVAL;
+  if (!valid_S(S) || !h_host || !ws_dev) return ENS_EINVAL;
+  rc = check_params(y_host, S, prob->d);
+  if (rc) return rc;
   if (ws_bytes < header_bytes()) return ENS_ENOMEM;
   const Workspace w = carve_workspace(ws_dev, 0, S, false);
+  rc = stage_params(w, y_host, S, prob->d, (hipStream_t)stream);
+  if (rc) return rc;
   IndArgs a;
   std::memset(&a, 0, sizeof(a));
   if (is3d(prob)) {
@@ -856,13 +938,14 @@ int ens_param_indicator(const ens_problem* prob, int32_t S, const double* y_dev,
     a.dim = 2;
     a.ncell = 1;
   }
-  a.y = y_dev;
+  a.y = w.y;
   a.partial = w.partial;
   a.m = prob->n;
   a.S = S;
+  a.Sp = pow2ceil(S);
   a.d = prob->d;
   a.eps_model = prob->eps_model;
-  const int groups = (int)std::min<size_t>((a.ncell * S + kNT - 1) / kNT, 512);
+  const int groups = (int)std::min<size_t>((a.ncell * a.Sp + kNT - 1) / kNT, 512);
   hipStream_t s = (hipStream_t)stream;
   launch_indicator(a, groups, s);
   {
@@ -872,7 +955,9 @@ int ens_param_indicator(const ens_problem* prob, int32_t S, const double* y_dev,
     f.G = groups;
     f.kind = F_MAX;
     f.m = w.m;
-    f.g = make_geometry(2, S, 0, 0);
+    member_lanes(f.g, S);
+    f.g.vec = 1;         // one member per thread: slots Sp = pow2ceil(S)
+    f.g.tpp = f.g.Sp = pow2ceil(S);
     launch_finish(f, s);
   }
   HIPCHECK(hipGetLastError());
@@ -883,20 +968,16 @@ int ens_param_indicator(const ens_problem* prob, int32_t S, const double* y_dev,
   return ENS_OK;
 }
 
-int ens_dqdy(const ens_problem* prob, int32_t S, const double* y_dev, const double* u_dev,
-             const double* lambda_dev, double* grad_host, void* ws_dev, size_t ws_bytes,
-             void* stream) {
-  int rc = check_problem(prob);
-  if (rc) return rc;
-  if (!valid_S(S) || !y_dev || !u_dev || !lambda_dev || !grad_host || !ws_dev) return ENS_EINVAL;
-  if (ws_bytes < header_bytes()) return ENS_ENOMEM;
-  if (is3d(prob)) return dqdy3(prob, S, y_dev, u_dev, lambda_dev, grad_host, ws_dev, stream);
+// dQ/dy kernel on parameters already in the workspace
+static int dqdy_staged(const ens_problem* prob, int32_t S, const double* u_dev,
+                       const double* lambda_dev, double* grad_host, void* ws_dev, void* stream) {
   const Workspace w = carve_workspace(ws_dev, 0, S, false);
+  if (is3d(prob)) return dqdy3(prob, S, w.y, u_dev, lambda_dev, grad_host, ws_dev, stream);
   const Geometry g = make_geometry(prob->n, S, 0, 0);
   hipStream_t s = (hipStream_t)stream;
   HIPCHECK(hipMemsetAsync(w.m.ctl, 0, sizeof(int) * CTL_COUNT, s));
   DqdyArgs a;
-  a.y = y_dev;
+  a.y = w.y;
   a.u = u_dev;
   a.lam = lambda_dev;
   a.partial = w.partial;
@@ -904,9 +985,11 @@ int ens_dqdy(const ens_problem* prob, int32_t S, const double* y_dev, const doub
   a.d = prob->d;
   a.eps_model = prob->eps_model;
   a.amp = prob->amp;
+  a.ntx = (prob->n + kAsmTX - 1) / kAsmTX;
+  a.ntiles = a.ntx * ((prob->n + kAsmTY - 1) / kAsmTY);
   // the partial buffer holds 3 * kMaxGroups * kMaxS doubles; d <= 16 rows of
-  // groups * S partials fit for groups <= 3 * kMaxGroups / 16
-  const int groups = std::min(init_groups(g), 3 * kMaxGroups / 16);
+  // groups * Sp partials fit for groups <= 3 * kMaxGroups / 16
+  const int groups = std::min(a.ntiles, 3 * kMaxGroups / 16);
   launch_dqdy(a, groups, s);
   {
     // dQ/dy_j = -(n+1)^2 * (the face/node sums of h^2 lambda^T dA/dy_j u)
@@ -930,7 +1013,22 @@ int ens_dqdy(const ens_problem* prob, int32_t S, const double* y_dev, const doub
   return ENS_OK;
 }
 
-int ens_adjoint_grad(const ens_problem* prob, const ens_opts* opts, int32_t S, const double* y_dev,
+int ens_dqdy(const ens_problem* prob, int32_t S, const double* y_host, const double* u_dev,
+             const double* lambda_dev, double* grad_host, void* ws_dev, size_t ws_bytes,
+             void* stream) {
+  int rc = check_problem(prob);
+  if (rc) return rc;
+  if (!valid_S(S) || !u_dev || !lambda_dev || !grad_host || !ws_dev) return ENS_EINVAL;
+  rc = check_params(y_host, S, prob->d);
+  if (rc) return rc;
+  if (ws_bytes < header_bytes()) return ENS_ENOMEM;
+  const Workspace w = carve_workspace(ws_dev, 0, S, false);
+  rc = stage_params(w, y_host, S, prob->d, (hipStream_t)stream);
+  if (rc) return rc;
+  return dqdy_staged(prob, S, u_dev, lambda_dev, grad_host, ws_dev, stream);
+}
+
+int ens_adjoint_grad(const ens_problem* prob, const ens_opts* opts, int32_t S, const double* y_host,
                      const double* V_dev, const double* u_dev, const double* w_dev,
                      double* lambda_dev, double* grad_host, int32_t* iters_host,
                      int32_t* status_host, void* ws_dev, size_t ws_bytes, void* stream) {
@@ -939,15 +1037,19 @@ int ens_adjoint_grad(const ens_problem* prob, const ens_opts* opts, int32_t S, c
   Opts o;
   rc = resolve_opts(opts, o);
   if (rc) return rc;
-  if (!valid_S(S) || !y_dev || !V_dev || !u_dev || !w_dev || !lambda_dev || !grad_host || !ws_dev)
+  if (!valid_S(S) || !V_dev || !u_dev || !w_dev || !lambda_dev || !grad_host || !ws_dev)
     return ENS_EINVAL;
+  rc = check_params(y_host, S, prob->d);
+  if (rc) return rc;
   const bool cheb = o.precond == ENS_PRECOND_CHEBYSHEV;
   if (ws_bytes < workspace_bytes(rows_of(prob), S, cheb)) return ENS_ENOMEM;
   const Workspace w = carve_workspace(ws_dev, rows_of(prob), S, cheb);
   SolveOut out{iters_host, status_host, nullptr, nullptr, nullptr};
   rc = run_solve(prob, o, S, V_dev, w_dev, 1, lambda_dev, w, (hipStream_t)stream, out);
   if (rc) return rc;
-  return ens_dqdy(prob, S, y_dev, u_dev, lambda_dev, grad_host, ws_dev, ws_bytes, stream);
+  rc = stage_params(w, y_host, S, prob->d, (hipStream_t)stream);
+  if (rc) return rc;
+  return dqdy_staged(prob, S, u_dev, lambda_dev, grad_host, ws_dev, stream);
 }
 
 }  // extern "C"

@@ -162,6 +162,7 @@ __global__ __launch_bounds__(kNT) void batch_stencil_kernel(BatchArgs a) {
       tv.n = uni(E.n);
       tv.S = S;
       tv.sw = uni(E.sw);
+      tv.swp = tv.sw;   // power-of-two widths: every member tile is full
       tv.tpp = tpp;
       tv.tx = uni(E.tx);
       tv.ty = uni(E.ty);
@@ -320,6 +321,7 @@ __global__ __launch_bounds__(kFinNT) void batch_finish_kernel(BatchArgs a) {
   f.partial = E.partial;
   f.m = E.m;
   f.g.S = E.S;
+  f.g.Sp = E.S;
   f.g.vec = 2;
   f.rtol = a.rtol;
   if (STAGE == 0) {
@@ -404,7 +406,8 @@ int ens_batch_solve(const ens_opts* opts, int32_t n_items, ens_batch_item* items
     const ens_batch_item& it = items[k];
     const int S = it.S;
     if (it.prob.dim == 3) return ENS_ENOTSUP;
-    if (it.prob.n < 2 || it.prob.n > 16384 || S < 2 || !valid_S(S)) return ENS_EINVAL;
+    if (it.prob.n < 2 || it.prob.n > 16384 || !valid_S(S)) return ENS_EINVAL;
+    if (S < 2 || (S & (S - 1)) != 0) return ENS_ENOTSUP;   // batched widths: powers of two
     if (!it.V_dev || !it.b_dev || !it.x_dev || !it.ws_dev || it.tile_lines < 0) return ENS_EINVAL;
     if (it.member_tile < 0 || (it.member_tile & (it.member_tile - 1)) != 0) return ENS_EINVAL;
     const size_t nr = (size_t)it.prob.n * it.prob.n;

@@ -45,6 +45,7 @@ struct Members {
 };
 
 struct Workspace {
+  double* y;      // [S][d] parameters staged from the host (kMaxS * 16 doubles)
   double* p[2];   // search directions (ping-pong)
   double* q;      // A p
   double* r;      // residual
@@ -55,9 +56,16 @@ struct Workspace {
   Members m;
 };
 
+// Member lanes.  A grid point's S members are contiguous (row stride S, any
+// S in [1, 64]); VEC = 2 members per thread when S is even, else 1.  The
+// threads of one point form a power-of-two group of tpp lanes, so a point
+// has Sp = tpp * VEC >= S member slots; slots s >= S are idle lanes that load
+// a valid address, compute, and neither store nor add to any sum.  Partial
+// sums and per-member state are indexed by slot (stride Sp).
 struct Geometry {
-  int n, S, logS, vec, tpp;  // tpp: threads per grid point of the flat kernels (S / vec)
-  int sw, nstile, stpp;      // member tile: sw members per stencil tile, S / sw tiles, sw / vec threads
+  int n, S, Sp, vec, tpp;    // tpp: threads per grid point of the flat kernels
+  int sw, swp, nstile, stpp; // member tile: sw members per stencil tile (the last
+                             // may hold fewer), swp = stpp * vec slots, ceil(S / sw) tiles
   int tx, ty;                // tile: points per line chunk, lines per band
   int nchunk, nband, ntiles, groups;   // ntiles counts spatial tiles (per member tile)
   size_t nr, nelem;          // rows, rows * S
@@ -69,13 +77,23 @@ struct Geometry {
 
 
 // ------------------------------------------------------------ kernel args
+// Assembly takes the parameters by value, kAsmY doubles per launch (the
+// members m0 .. m0 + mc - 1 of the ensemble), so the caller's host array is
+// copied at launch and no device buffer is needed; a wide ensemble with
+// many parameters is assembled in several launches.
+constexpr int kAsmY = 128;
+constexpr int kAsmTX = 32, kAsmTY = 8;   // grid points per assembly tile (x, y)
+constexpr int kMaxModes = 14;            // sine modes of a(x): d - 2 <= 14
+
 struct AsmArgs {
-  const double* y;  // [S][d]
+  double y[kAsmY];  // [mc][d]: members m0 .. m0 + mc - 1
   double* V;        // [9][vstride], slot k holds [N_r][S]
   double* b;        // [N_r][S]
-  int n, S, logS, d, eps_model;
+  int n, S, d, eps_model;
+  int m0, mc, mcp;  // first member, members, threads per point (power of two >= mc)
+  int ntx;          // tiles per grid line
   double amp;
-  size_t nelem, vstride;
+  size_t vstride;
 };
 
 enum Mode { M_SPMV = 0, M_PCG_J = 1, M_PCG_Z = 2, M_CHEB = 3 };
@@ -90,7 +108,7 @@ struct StencilArgs {
   double* x;           // solution, deferred update (PCG)
   double* d;           // Chebyshev increment
   double* zout;        // Chebyshev output z
-  double* partial;     // [groups][S]
+  double* partial;     // [groups][Sp]
   Members m;
   Geometry g;
   int cheb_step;       // Chebyshev step 1..deg-1
@@ -104,7 +122,7 @@ struct UpdateArgs {
   const double* q;
   double* d;        // Chebyshev: D^-1 r / theta
   double* z;        // Chebyshev: z = d
-  double* partial;  // [2][groups][S]: r^T z (Jacobi), r^T r
+  double* partial;  // [2][groups][Sp]: r^T z (Jacobi), r^T r
   Members m;
   Geometry g;
   double rtol;
@@ -117,7 +135,7 @@ struct InitArgs {
   double* x;
   double* p0;
   double* r;
-  double* partial;   // [3][groups][S]: r^T z, b^T b, Gershgorin max
+  double* partial;   // [3][groups][Sp]: r^T z, b^T b, Gershgorin max
   Members m;
   Geometry g;
   int max_iter;
@@ -130,9 +148,10 @@ struct DqdyArgs {
   const double* y;   // [S][d]
   const double* u;   // [N_r][S]
   const double* lam; // [N_r][S]
-  double* partial;   // [d][groups][S]
+  double* partial;   // [d][groups][Sp]
   Geometry g;
   int d, eps_model;
+  int ntx, ntiles;   // assembly-shaped tiles (kAsmTX x kAsmTY points)
   double amp;
 };
 
@@ -140,7 +159,7 @@ enum Finish { F_ALPHA = 0, F_UPDATE_J = 1, F_UPDATE_C = 2, F_CHEB = 3, F_INIT = 
               F_MAX = 7 };
 
 struct FinishArgs {
-  const double* partial;  // consecutive arrays of G * S partials
+  const double* partial;  // consecutive arrays of G * Sp partials
   int G;                  // workgroups of the producer kernel
   int kind;               // Finish
   Members m;
@@ -188,5 +207,10 @@ void launch_fe3d(const StencilArgs& a, hipStream_t s);
 inline size_t slot_stride(size_t nelem) { return ((nelem + 31) & ~(size_t)31) + 512; }
 int set_hip_error(hipError_t e);
 int valid_S(int S);
+inline int pow2ceil(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
 
 }  // namespace ens

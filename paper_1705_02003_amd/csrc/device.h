@@ -117,22 +117,24 @@ __device__ __forceinline__ void group_max(double (&v)[VEC], int tpp, double* lds
   }
 }
 
-// write this workgroup's partial [S] (threads t < tpp); a finish kernel
-// launched after this one reads them (the kernel boundary makes them visible
-// across XCDs, so no in-kernel device-scope fence is needed)
+// write this workgroup's partial [Sp] (member slots s0 .. s0 + tpp VEC - 1,
+// threads t < tpp); a finish kernel launched after this one reads them (the
+// kernel boundary makes them visible across XCDs, so no in-kernel
+// device-scope fence is needed)
 template <int VEC>
-__device__ __forceinline__ void put_partial(double* partial, int S, int tpp, const double (&v)[VEC],
+__device__ __forceinline__ void put_partial(double* partial, int Sp, int tpp, const double (&v)[VEC],
                                             int s0 = 0) {
   if ((int)threadIdx.x < tpp) {
 #pragma unroll
-    for (int c = 0; c < VEC; ++c) partial[(size_t)blockIdx.x * S + s0 + threadIdx.x * VEC + c] = v[c];
+    for (int c = 0; c < VEC; ++c) partial[(size_t)blockIdx.x * Sp + s0 + threadIdx.x * VEC + c] = v[c];
   }
 }
 
-// Member sums of NARR partial arrays P[a][g][s] over the workgroups g < G,
-// returned for member s = threadIdx.x (t < S), in a block of kFinNT
-// threads.  Thread t loads VEC members per row (16-byte loads when VEC = 2);
-// the R = kFinNT * VEC / S row sets are k, k + R, k + 2R, ... with
+// Member sums of NARR partial arrays P[a][g][s] (s < S, S here the slot
+// count Sp, a power of two) over the workgroups g < G, returned for slot
+// s = threadIdx.x (t < S), in a block of kFinNT threads.  Thread t loads
+// VEC members per row (16-byte loads when VEC = 2); the
+// R = kFinNT * VEC / S row sets are k, k + R, k + 2R, ... with
 // k = t / (S / VEC), summed in that order with up to 32 loads in flight,
 // then a fixed halving tree over k.  The order does not depend on the
 // member.  `lds` holds NARR * kFinNT * VEC doubles.
@@ -248,7 +250,8 @@ struct TileView {
   double* zout;
   int n, S;        // grid size, ensemble width (row stride of every vector)
   int sw, s0;      // members this tile covers: s0 .. s0 + sw - 1
-  int tpp;         // threads per grid point = sw / VEC
+  int swp;         // member slots per point (tpp * VEC >= sw): the LDS point stride
+  int tpp;         // threads per grid point (a power of two)
   int tx, ty, nchunk;
   size_t nelem, vstride;   // elements per vector; from one matrix slot to the next
   int cheb_last;
@@ -282,10 +285,13 @@ __device__ __forceinline__ void stencil_tile(const TileView& a, int tile, double
                                              double (&acc)[VEC]) {
   constexpr bool PCG = (MODE == M_PCG_J || MODE == M_PCG_Z);
   const int t = threadIdx.x;
-  const int S = a.S, n = a.n, tpp = a.tpp, sw = a.sw;
+  const int S = a.S, n = a.n, tpp = a.tpp, sw = a.swp;
   const int lp = t / tpp;
-  const int cl = (t % tpp) * VEC;   // first member of this thread within the tile
-  const int sv = a.s0 + cl;         // ... within the ensemble
+  const int cl = (t % tpp) * VEC;   // first member slot of this thread within the tile
+  // idle slots (past the tile's members) read the tile's last members and
+  // store and sum nothing
+  const bool lane_ok = cl < a.sw;
+  const int sv = a.s0 + (lane_ok ? cl : a.sw - VEC);   // member whose values this lane loads
   const size_t slot_stride = a.vstride;
   const size_t line_stride = (size_t)n * S;
   const int chunk = tile % a.nchunk, band = tile / a.nchunk;
@@ -293,6 +299,7 @@ __device__ __forceinline__ void stencil_tile(const TileView& a, int tile, double
   const int j1 = min(j0 + a.ty, n);
   const int i = i0 + lp;
   const bool own_i = i < n;
+  const bool own_s = own_i && lane_ok;   // this lane's point and members exist
   // halo duty: threads t < tpp also hold the point left of the chunk,
   // threads tpp <= t < 2 tpp the point right of it
   const bool halo = t < 2 * tpp, left_halo = t < tpp;
@@ -356,7 +363,7 @@ __device__ __forceinline__ void stencil_tile(const TileView& a, int tile, double
       rval[c] = val[c];
     }
     if constexpr (PCG) {
-      if (ok && own) st<VEC>(a.pnew + row(jj) + col, val);
+      if (ok && own && lane_ok) st<VEC>(a.pnew + row(jj) + col, val);
     }
   };
   auto put_halo = [&](int jj, const double (&h0)[VEC], const double (&h1)[VEC],
@@ -496,14 +503,14 @@ __device__ __forceinline__ void stencil_tile(const TileView& a, int tile, double
     // lanes without a point (the last chunk of a line) store nothing and
     // add nothing
     if constexpr (MODE == M_SPMV) {
-      if (own_i) st<VEC>(a.q + e, q);
+      if (own_s) st<VEC>(a.q + e, q);
     } else if constexpr (PCG) {
 #pragma unroll
       for (int c = 0; c < VEC; ++c) {
-        acc[c] = own_i ? fma(cur_val[c], q[c], acc[c]) : acc[c];
+        acc[c] = own_s ? fma(cur_val[c], q[c], acc[c]) : acc[c];
         if (aprev[c] != 0.0) xv[c] = fma(aprev[c], cur_pold[c], xv[c]);
       }
-      if (own_i) {
+      if (own_s) {
         st<VEC>(a.q + e, q);
         st<VEC>(a.x + e, xv);
       }
@@ -513,9 +520,9 @@ __device__ __forceinline__ void stencil_tile(const TileView& a, int tile, double
       for (int c = 0; c < VEC; ++c) {
         dd[c] = c1[c] * dd[c] + c2[c] * ((rr[c] - q[c]) / vk[4][c]);
         zn[c] = cur_val[c] + dd[c];
-        if (a.cheb_last) acc[c] = own_i ? fma(rr[c], zn[c], acc[c]) : acc[c];
+        if (a.cheb_last) acc[c] = own_s ? fma(rr[c], zn[c], acc[c]) : acc[c];
       }
-      if (own_i) {
+      if (own_s) {
         st<VEC>(a.d + e, dd);
         st<VEC>(a.zout + e, zn);
       }
@@ -535,9 +542,9 @@ __device__ __forceinline__ void stencil_tile(const TileView& a, int tile, double
 // ensemble.
 template <int VEC>
 __device__ __forceinline__ int finish_body(const FinishArgs& a, double* fin, int& live) {
-  const int S = a.g.S, t = threadIdx.x;
+  const int S = a.g.S, Sp = a.g.Sp, t = threadIdx.x;   // members, member slots
   const Members& m = a.m;
-  const size_t ps = (size_t)a.G * S;
+  const size_t ps = (size_t)a.G * Sp;
   switch (a.kind) {
     case F_ALPHA:
     case F_CHEB:
@@ -563,12 +570,12 @@ __device__ __forceinline__ int finish_body(const FinishArgs& a, double* fin, int
         // r^T r and r^T z
         const double* const P[2] = {a.partial + ps, a.partial};
         double o2[2];
-        final_sums<VEC, 2>(P, a.G, S, fin, o2);
+        final_sums<VEC, 2>(P, a.G, Sp, fin, o2);
         s0 = o2[0];
         s1 = o2[1];
       } else {
         // p^T A p (F_ALPHA), r^T z (F_CHEB) or r^T r (F_UPDATE_C)
-        s0 = final_sum<VEC>(a.partial + (a.kind == F_UPDATE_C ? ps : 0), a.G, S, fin);
+        s0 = final_sum<VEC>(a.partial + (a.kind == F_UPDATE_C ? ps : 0), a.G, Sp, fin);
       }
       if (done) return 0;
       if (a.kind == F_ALPHA) {
@@ -642,12 +649,23 @@ __device__ __forceinline__ int finish_body(const FinishArgs& a, double* fin, int
       return retired;
     }
     case F_INIT: {
-      const double bbs = final_sum<VEC>(a.partial + ps, a.G, S, fin);
+      const double bbs = final_sum<VEC>(a.partial + ps, a.G, Sp, fin);
       double rzs = 0.0, lmax = 0.0;
-      if (!a.cheb) rzs = final_sum<VEC>(a.partial, a.G, S, fin);
-      else lmax = final_max(a.partial + 2 * ps, a.G, S, fin);
+      if (!a.cheb) rzs = final_sum<VEC>(a.partial, a.G, Sp, fin);
+      else lmax = final_max(a.partial + 2 * ps, a.G, Sp, fin);
       if (t == 0) live = 0;
       __syncthreads();
+      if (t >= S && t < Sp) {
+        // idle slots: inactive, every step zero
+        gstore(&m.active[t], 0);
+        gstore(&m.alpha[t], 0.0);
+        gstore(&m.alpha_prev[t], 0.0);
+        gstore(&m.beta[t], 0.0);
+        gstore(&m.rho[t], 0.0);
+        gstore(&m.bnorm[t], 1.0);
+        gstore(&m.cheb[(size_t)t * kChebCoef], 1.0);
+        for (int k = 1; k < 2 * kMaxCheb + 1; ++k) gstore(&m.cheb[(size_t)t * kChebCoef + k], 0.0);
+      }
       if (t < S) {
         const double bn = sqrt(bbs);
         gstore(&m.bnorm[t], bn);
@@ -696,7 +714,7 @@ __device__ __forceinline__ int finish_body(const FinishArgs& a, double* fin, int
     }
     case F_MAX: {
       // per-member maximum of one partial array into result[s][0]
-      const double v = final_max(a.partial, a.G, S, fin);
+      const double v = final_max(a.partial, a.G, Sp, fin);
       if (t < S) gstore(&m.result[(size_t)t * 16], v);
       return 0;
     }
@@ -704,7 +722,7 @@ __device__ __forceinline__ int finish_body(const FinishArgs& a, double* fin, int
     case F_SUMS: {
       // nsum member sums, scaled, into result[s][q]
       for (int q = 0; q < a.nsum; ++q) {
-        const double v = final_sum<VEC>(a.partial + q * ps, a.G, S, fin);
+        const double v = final_sum<VEC>(a.partial + q * ps, a.G, Sp, fin);
         if (t < S) gstore(&m.result[(size_t)t * 16 + q], a.scale * v);
       }
       return 0;

@@ -18,11 +18,12 @@ struct Fe3dTerm {
 };
 
 struct Fe3dAsmArgs {
-  const double* y;  // [S][d]
+  double y[kAsmY];  // [mc][d]: members m0 .. m0 + mc - 1 (by value, as in AsmArgs)
   double* V;        // [27][vstride], slot k holds [N_r][S]
   double* b;        // [N_r][S]
-  int m, S, logS, d;
-  size_t nelem, vstride;
+  int m, S, d;
+  int m0, mc, mcp;  // first member, members, threads per row (power of two >= mc)
+  size_t nr, vstride;
   Fe3dTerm term[kMaxTerms];
 };
 
@@ -31,8 +32,8 @@ struct Fe3dDqdyArgs {
   const double* y;    // [S][d]
   const double* u;    // [N_r][S]
   const double* lam;  // [N_r][S]
-  double* partial;    // [d][groups][S]
-  int m, S, logS, d;
+  double* partial;    // [d][groups][Sp]
+  int m, S, Sp, d;    // Sp: member slots (power of two >= S); one thread per slot and cube
   size_t ncell;       // (m+1)^3 cubes
   Fe3dTerm term[kMaxTerms];
 };
@@ -41,8 +42,8 @@ struct Fe3dDqdyArgs {
 // ratio lambda_max / lambda_min of the diffusion tensor over the domain.
 struct IndArgs {
   const double* y;   // [S][d]
-  double* partial;   // [groups][S] per-workgroup maxima
-  int dim, m, S, d, eps_model;
+  double* partial;   // [groups][Sp] per-workgroup maxima
+  int dim, m, S, Sp, d, eps_model;
   size_t ncell;      // 3-D: cubes (m+1)^3; 2-D: 1 (the ratio does not depend on x)
   Fe3dTerm term[kMaxTerms];
 };

@@ -112,20 +112,25 @@ int fe3d_setup(const ens_problem* p, Fe3dAsmArgs& a) {
 }
 
 // ------------------------------------------------------------ assembly
-// One thread per (row, member).  The cube matrices follow from the 1-D
+// One thread per (row, member) of the launch's members m0 .. m0 + mc - 1
+// (mcp threads per row).  The cube matrices follow from the 1-D
 // linear-element stiffness K1 = [[1, -1], [-1, 1]] / h and mass
 // M1 = [[2, 1], [1, 2]] h / 6: a cube with coefficient a_c adds
 // a_c Kx My Mz + a_y Mx Ky Mz + a_z Mx My Kz between two of its nodes; the
 // value of slot (di, dj, dk) sums the cubes holding both nodes.
 __global__ __launch_bounds__(kNT) void fe3d_assemble_kernel(Fe3dAsmArgs a) {
 #pragma clang fp contract(off)
-  const size_t e = (size_t)blockIdx.x * kNT + threadIdx.x;
-  if (e >= a.nelem) return;
+  __shared__ double ys[kAsmY];
+  const int t = threadIdx.x;
+  for (int x = t; x < a.mc * a.d; x += kNT) ys[x] = a.y[x];
+  __syncthreads();
+  const int cl = t % a.mcp;
+  const size_t row = (size_t)blockIdx.x * (kNT / a.mcp) + t / a.mcp;
+  if (cl >= a.mc || row >= a.nr) return;
   const int m = a.m;
-  const int s = (int)(e & (size_t)(a.S - 1));
-  const size_t row = e >> a.logS;
+  const size_t e = row * a.S + a.m0 + cl;
   const int i = (int)(row % m), j = (int)((row / m) % m), k = (int)(row / ((size_t)m * m));
-  const double* y = a.y + (size_t)s * a.d;
+  const double* y = ys + cl * a.d;
   const double h = 1.0 / (double)(m + 1);
 
   // a at the centres of the eight cubes around mesh node (i+1, j+1, k+1):
@@ -186,15 +191,15 @@ __global__ __launch_bounds__(kNT) void fe3d_assemble_kernel(Fe3dAsmArgs a) {
 // per (cube, member), grid-strided; per-workgroup maxima per member.
 __global__ __launch_bounds__(kNT) void indicator_kernel(IndArgs a) {
   __shared__ double red[kWaves * 64 * 2];
-  const int S = a.S, t = threadIdx.x, s = t & (S - 1);
-  const double* y = a.y + (size_t)s * a.d;
+  const int Sp = a.Sp, t = threadIdx.x, s = t & (Sp - 1);
+  const bool lane_ok = s < a.S;
+  const double* y = a.y + (size_t)(lane_ok ? s : a.S - 1) * a.d;
   double hv[1] = {0.0};
-  const size_t total = a.ncell * S;
-  const size_t stride = (size_t)gridDim.x * kNT;
-  for (size_t e = (size_t)blockIdx.x * kNT + t; e < total; e += stride) {
+  const size_t cpb = (size_t)(kNT / Sp);   // cubes per workgroup and pass
+  const size_t stride = (size_t)gridDim.x * cpb;
+  for (size_t c = (size_t)blockIdx.x * cpb + t / Sp; lane_ok && c < a.ncell; c += stride) {
     double r;
     if (a.dim == 3) {
-      const size_t c = e / S;
       const int mc = a.m + 1;
       const int cx = (int)(c % mc), cy = (int)((c / mc) % mc), cz = (int)(c / ((size_t)mc * mc));
       const double h = 1.0 / (double)(a.m + 1);
@@ -215,8 +220,8 @@ __global__ __launch_bounds__(kNT) void indicator_kernel(IndArgs a) {
     }
     hv[0] = fmax(hv[0], r);
   }
-  group_max<1>(hv, S, red);
-  put_partial<1>(a.partial, S, S, hv);
+  group_max<1>(hv, Sp, red);
+  put_partial<1>(a.partial, Sp, Sp, hv);
 }
 
 // ------------------------------------------------------------ adjoint form
@@ -228,17 +233,19 @@ __global__ __launch_bounds__(kNT) void indicator_kernel(IndArgs a) {
 // grid-strided; per-workgroup sums per member for each j.
 __global__ __launch_bounds__(kNT) void fe3d_dqdy_kernel(Fe3dDqdyArgs a) {
   __shared__ double red[kWaves * 64 * 2];
-  const int S = a.S, t = threadIdx.x, s = t & (S - 1), m = a.m, mc = m + 1;
+  const int S = a.S, Sp = a.Sp, t = threadIdx.x, m = a.m, mc = m + 1;
+  const int s0 = t & (Sp - 1);
+  const bool lane_ok = s0 < S;
+  const int s = lane_ok ? s0 : S - 1;   // idle slots compute on a real member, add nothing
   const double* y = a.y + (size_t)s * a.d;
   const double h = 1.0 / (double)mc;
   const double kd = 1.0 / h, ko = -1.0 / h, md = (2.0 * h) / 6.0, mo = (1.0 * h) / 6.0;
   double acc[kMaxTerms];
 #pragma unroll
   for (int q = 0; q < kMaxTerms; ++q) acc[q] = 0.0;
-  const size_t total = a.ncell * S;
-  const size_t stride = (size_t)gridDim.x * kNT;
-  for (size_t e = (size_t)blockIdx.x * kNT + t; e < total; e += stride) {
-    const size_t c = e >> a.logS;
+  const size_t cpb = (size_t)(kNT / Sp);   // cubes per workgroup and pass
+  const size_t stride = (size_t)gridDim.x * cpb;
+  for (size_t c = (size_t)blockIdx.x * cpb + t / Sp; lane_ok && c < a.ncell; c += stride) {
     const int cx = (int)(c % mc), cy = (int)((c / mc) % mc), cz = (int)(c / ((size_t)mc * mc));
     // nodal values of lambda and u at the cube's corners (mesh node
     // (cx + lx, cy + ly, cz + lz); interior when 1 <= index <= m)
@@ -282,13 +289,13 @@ __global__ __launch_bounds__(kNT) void fe3d_dqdy_kernel(Fe3dDqdyArgs a) {
     for (int n = 0; n < kMaxTerms; ++n)
       if (n < a.d) acc[n] += eg * a.term[n].sq * bj[n] * B;
   }
-  const size_t ps = (size_t)gridDim.x * S;
+  const size_t ps = (size_t)gridDim.x * Sp;
 #pragma unroll
   for (int q = 0; q < kMaxTerms; ++q) {
     if (q < a.d) {
       double v[1] = {acc[q]};
-      group_reduce<1>(v, S, red);
-      put_partial<1>(a.partial + q * ps, S, S, v);
+      group_reduce<1>(v, Sp, red);
+      put_partial<1>(a.partial + q * ps, Sp, Sp, v);
     }
   }
 }
@@ -309,6 +316,7 @@ __global__ __launch_bounds__(kNT) void fe3d_dir_kernel(StencilArgs a) {
   if (gload(&a.m.ctl[CTL_DONE])) return;
   const Geometry& g = a.g;
   const int t = threadIdx.x, sv = (t % g.tpp) * VEC;
+  if (sv >= g.S) return;
   double beta[VEC], aprev[VEC];
 #pragma unroll
   for (int c = 0; c < VEC; ++c) {
@@ -316,8 +324,10 @@ __global__ __launch_bounds__(kNT) void fe3d_dir_kernel(StencilArgs a) {
     aprev[c] = gload(&a.m.alpha_prev[sv + c]);
   }
   const double* diag = a.V + (size_t)g.cslot * g.vstride;
-  const size_t stride = (size_t)gridDim.x * kNT * VEC;
-  for (size_t e = ((size_t)blockIdx.x * kNT + t) * VEC; e < g.nelem; e += stride) {
+  const size_t P = (size_t)(kNT / g.tpp);
+  const size_t stride = (size_t)gridDim.x * P;
+  for (size_t p = (size_t)blockIdx.x * P + t / g.tpp; p < g.nr; p += stride) {
+    const size_t e = p * g.S + sv;
     double v0[VEC], dv[VEC], po[VEC], xv[VEC], pv[VEC];
     if constexpr (MODE == M_PCG_J) {
       ld<VEC>(v0, a.r + e);
@@ -371,6 +381,9 @@ void fe3d_stencil_kernel(StencilArgs a) {
   }
   const int S = g.S, tpp = g.tpp, t = threadIdx.x, m = g.n;
   const int sv = (t % tpp) * VEC;
+  // idle slots (sv >= S) load the last members' values and store and sum nothing
+  const bool lane_ok = sv < S;
+  const int svl = lane_ok ? sv : S - VEC;
   const int ppb = kNT / tpp;   // pairs per workgroup and pass
   const int mi = (m + NP - 1) / NP;
   const size_t npair = (size_t)mi * m * m;
@@ -398,7 +411,7 @@ void fe3d_stencil_kernel(StencilArgs a) {
     const int ig = (int)(gi % mi), j = (int)((gi / mi) % m), k = (int)(gi / ((size_t)mi * m));
     const int i0 = ig * NP;
     // offset of the pair's first point; x = i0 - 1 + c is inside for colok[c]
-    const size_t eb = (((size_t)k * m + j) * m + i0) * S + sv;
+    const size_t eb = (((size_t)k * m + j) * m + i0) * S + svl;
     bool colok[NP + 2];
 #pragma unroll
     for (int c = 0; c < NP + 2; ++c) colok[c] = (unsigned)(i0 - 1 + c) < (unsigned)m;
@@ -453,7 +466,7 @@ void fe3d_stencil_kernel(StencilArgs a) {
     }
 #pragma unroll
     for (int u = 0; u < NP; ++u) {
-      if (!colok[u + 1]) continue;
+      if (!colok[u + 1] || !lane_ok) continue;
       const size_t e = eb + (size_t)(u * S);
       if constexpr (MODE == M_SPMV) {
         st<VEC>(a.q + e, q[u]);
@@ -487,18 +500,19 @@ void fe3d_stencil_kernel(StencilArgs a) {
   }
   if constexpr (PCG) {
     group_reduce<VEC>(acc, tpp, red);
-    put_partial<VEC>(a.partial, S, tpp, acc);
+    put_partial<VEC>(a.partial, g.Sp, tpp, acc);
   } else if constexpr (MODE == M_CHEB) {
     if (a.cheb_last) {
       group_reduce<VEC>(acc, tpp, red);
-      put_partial<VEC>(a.partial, S, tpp, acc);
+      put_partial<VEC>(a.partial, g.Sp, tpp, acc);
     }
   }
 }
 
 // ------------------------------------------------------------ launchers
 void launch_fe3d_assemble(const Fe3dAsmArgs& a, hipStream_t s) {
-  const unsigned blocks = (unsigned)((a.nelem + kNT - 1) / kNT);
+  const size_t rpb = (size_t)(kNT / a.mcp);   // rows per workgroup
+  const unsigned blocks = (unsigned)((a.nr + rpb - 1) / rpb);
   hipLaunchKernelGGL(fe3d_assemble_kernel, dim3(blocks), dim3(kNT), 0, s, a);
 }
 

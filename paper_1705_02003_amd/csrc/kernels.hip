@@ -7,9 +7,13 @@
 // pattern) is implicit: there is no index array at all, it is "read" once
 // per tile for all S members (Section 2.3, reuse of sample-independent data).
 //
-// Thread mapping: VEC = 2 members per thread (one 16-byte load) when S >= 2,
-// VEC = 1 for S = 1.  tpp = S / VEC threads cover one grid point; a wave64
-// covers 64 / tpp consecutive points of one grid line.
+// Thread mapping: VEC = 2 members per thread (one 16-byte load) when S is
+// even, else VEC = 1.  A power-of-two group of tpp >= S / VEC threads covers
+// one grid point (slots past S are idle lanes); a wave64 covers 64 / tpp
+// consecutive points of one grid line.  The element-wise kernels stride over
+// points: thread t of workgroup b handles points b P + t / tpp + k G P
+// (P = kNT / tpp points per workgroup, G workgroups) and slots
+// (t % tpp) VEC .. + VEC - 1.
 //
 // Reductions: every per-member inner product is reduced in a fixed tree
 // (per-thread sequential sums, xor-shuffles across lanes that hold the same
@@ -26,67 +30,92 @@
 namespace ens {
 
 // ------------------------------------------------------------ assembly
-// One thread per (row, member).  Evaluation order of every expression
-// follows the scheme's definition term by term; contraction into FMA is off
-// so the values are the plainly rounded ones.
+// One workgroup per tile of kAsmTX x kAsmTY grid points, for the members
+// m0 .. m0 + mc - 1 of one launch.  What does not depend on the member is
+// computed once per tile: the mode tables sin(k pi I h) at the tile's node
+// columns I and rows J (paper, Section 2.3: sample-independent quantities
+// are computed once for the whole ensemble); what depends only on the
+// member (eps, theta, the entries of K) once per member and tile.  Then
+// every (point, member) forms a at its node and the four neighbours from
+// the tables, the face means and the nine values.  Evaluation order of every
+// expression follows the scheme's definition term by term; contraction into
+// FMA is off so the values are the plainly rounded ones.
 __global__ __launch_bounds__(kNT) void assemble_kernel(AsmArgs a) {
 #pragma clang fp contract(off)
-  const size_t e = (size_t)blockIdx.x * kNT + threadIdx.x;
-  if (e >= a.nelem) return;
-  const int n = a.n;
-  const int s = (int)(e & (size_t)(a.S - 1));
-  const size_t row = e >> a.logS;
-  const int i = (int)(row % n), j = (int)(row / n);
-  const double* y = a.y + (size_t)s * a.d;
-
-  const double eps = (a.eps_model == 0) ? pow(10.0, -(1.0 + y[0])) : pow(10.0, -(1.5 + 1.5 * y[0]));
-  const double theta = (M_PI / 4.0) * (1.0 + y[1]);
-  const double c = cos(theta), sn = sin(theta);
-  const double k11 = c * c + eps * (sn * sn);
-  const double k22 = sn * sn + eps * (c * c);
-  const double k12 = (1.0 - eps) * (sn * c);
-
-  // a at the node (I, J) = (i + 1, j + 1) and its four neighbours, 1-based
-  // node indices on the (n+2)^2 grid, x = index / (n + 1).
-  const int I = i + 1, J = j + 1;
-  double aC = 1.0, aE = 1.0, aW = 1.0, aN = 1.0, aS = 1.0;
-  for (int k = 1; k <= a.d - 2; ++k) {
-    const double kp = (double)k * M_PI;
-    const double sIm = sin(kp * ((double)(I - 1) / (double)(n + 1)));
-    const double sI = sin(kp * ((double)I / (double)(n + 1)));
-    const double sIp = sin(kp * ((double)(I + 1) / (double)(n + 1)));
-    const double sJm = sin(kp * ((double)(J - 1) / (double)(n + 1)));
-    const double sJ = sin(kp * ((double)J / (double)(n + 1)));
-    const double sJp = sin(kp * ((double)(J + 1) / (double)(n + 1)));
-    const double yk = y[k + 1], kk = (double)(k * k);
-    aC = aC + a.amp * ((yk * (sJ * sI)) / kk);
-    aE = aE + a.amp * ((yk * (sJ * sIp)) / kk);
-    aW = aW + a.amp * ((yk * (sJ * sIm)) / kk);
-    aN = aN + a.amp * ((yk * (sJp * sI)) / kk);
-    aS = aS + a.amp * ((yk * (sJm * sI)) / kk);
+  __shared__ double sI[kMaxModes][kAsmTX + 2];
+  __shared__ double sJ[kMaxModes][kAsmTY + 2];
+  __shared__ double kc[3][kMaxS];
+  __shared__ double ys[kAsmY];
+  const int n = a.n, d = a.d, t = threadIdx.x, nm = a.d - 2;
+  for (int x = t; x < a.mc * d; x += kNT) ys[x] = a.y[x];
+  const int i0 = (blockIdx.x % a.ntx) * kAsmTX, j0 = (blockIdx.x / a.ntx) * kAsmTY;
+  const double np1 = (double)(n + 1);
+  // sin(k pi x) at nodes I = i0 + q (q = 0 .. kAsmTX + 1) and J = j0 + q
+  for (int x = t; x < nm * (kAsmTX + 2); x += kNT) {
+    const int k = x / (kAsmTX + 2), q = x % (kAsmTX + 2);
+    const double kp = (double)(k + 1) * M_PI;
+    sI[k][q] = sin(kp * ((double)(i0 + q) / np1));
   }
-  const double fE = (aC + aE) / 2.0, fW = (aC + aW) / 2.0;
-  const double fN = (aC + aN) / 2.0, fS = (aC + aS) / 2.0;
-  const double bE = k12 * aE, bW = k12 * aW, bN = k12 * aN, bS = k12 * aS;
+  for (int x = t; x < nm * (kAsmTY + 2); x += kNT) {
+    const int k = x / (kAsmTY + 2), q = x % (kAsmTY + 2);
+    const double kp = (double)(k + 1) * M_PI;
+    sJ[k][q] = sin(kp * ((double)(j0 + q) / np1));
+  }
+  __syncthreads();
+  if (t < a.mc) {
+    const double* y = ys + t * d;
+    const double eps = (a.eps_model == 0) ? pow(10.0, -(1.0 + y[0])) : pow(10.0, -(1.5 + 1.5 * y[0]));
+    const double theta = (M_PI / 4.0) * (1.0 + y[1]);
+    const double c = cos(theta), sn = sin(theta);
+    kc[0][t] = c * c + eps * (sn * sn);
+    kc[1][t] = sn * sn + eps * (c * c);
+    kc[2][t] = (1.0 - eps) * (sn * c);
+  }
+  __syncthreads();
+  const int cl = t % a.mcp;
+  if (cl >= a.mc) return;
+  const double* y = ys + cl * d;
+  const double k11 = kc[0][cl], k22 = kc[1][cl], k12 = kc[2][cl];
+  const double inv_h2 = np1 * np1;
+  for (int pt = t / a.mcp; pt < kAsmTX * kAsmTY; pt += kNT / a.mcp) {
+    const int i = i0 + pt % kAsmTX, j = j0 + pt / kAsmTX;
+    if (i >= n || j >= n) continue;
+    // table columns of the nodes i, i + 1, i + 2 (1-based node I = i + 1)
+    const int qi = i - i0 + 1, qj = j - j0 + 1;
+    double aC = 1.0, aE = 1.0, aW = 1.0, aN = 1.0, aS = 1.0;
+    for (int k = 1; k <= nm; ++k) {
+      const double sIm = sI[k - 1][qi - 1], sIc = sI[k - 1][qi], sIp = sI[k - 1][qi + 1];
+      const double sJm = sJ[k - 1][qj - 1], sJc = sJ[k - 1][qj], sJp = sJ[k - 1][qj + 1];
+      const double yk = y[k + 1], kk = (double)(k * k);
+      aC = aC + a.amp * ((yk * (sJc * sIc)) / kk);
+      aE = aE + a.amp * ((yk * (sJc * sIp)) / kk);
+      aW = aW + a.amp * ((yk * (sJc * sIm)) / kk);
+      aN = aN + a.amp * ((yk * (sJp * sIc)) / kk);
+      aS = aS + a.amp * ((yk * (sJm * sIc)) / kk);
+    }
+    const double fE = (aC + aE) / 2.0, fW = (aC + aW) / 2.0;
+    const double fN = (aC + aN) / 2.0, fS = (aC + aS) / 2.0;
+    const double bE = k12 * aE, bW = k12 * aW, bN = k12 * aN, bS = k12 * aS;
 
-  double h2[9];
-  h2[4] = k11 * (fE + fW) + k22 * (fN + fS);
-  h2[5] = -k11 * fE;
-  h2[3] = -k11 * fW;
-  h2[7] = -k22 * fN;
-  h2[1] = -k22 * fS;
-  h2[8] = -(bE + bN) / 4.0;
-  h2[0] = -(bW + bS) / 4.0;
-  h2[6] = (bW + bN) / 4.0;
-  h2[2] = (bE + bS) / 4.0;
-  if (i == 0) h2[0] = h2[3] = h2[6] = 0.0;
-  if (i == n - 1) h2[2] = h2[5] = h2[8] = 0.0;
-  if (j == 0) h2[0] = h2[1] = h2[2] = 0.0;
-  if (j == n - 1) h2[6] = h2[7] = h2[8] = 0.0;
-  const double inv_h2 = (double)(n + 1) * (double)(n + 1);
+    double h2[9];
+    h2[4] = k11 * (fE + fW) + k22 * (fN + fS);
+    h2[5] = -k11 * fE;
+    h2[3] = -k11 * fW;
+    h2[7] = -k22 * fN;
+    h2[1] = -k22 * fS;
+    h2[8] = -(bE + bN) / 4.0;
+    h2[0] = -(bW + bS) / 4.0;
+    h2[6] = (bW + bN) / 4.0;
+    h2[2] = (bE + bS) / 4.0;
+    if (i == 0) h2[0] = h2[3] = h2[6] = 0.0;
+    if (i == n - 1) h2[2] = h2[5] = h2[8] = 0.0;
+    if (j == 0) h2[0] = h2[1] = h2[2] = 0.0;
+    if (j == n - 1) h2[6] = h2[7] = h2[8] = 0.0;
+    const size_t e = ((size_t)j * n + i) * a.S + a.m0 + cl;
 #pragma unroll
-  for (int k = 0; k < 9; ++k) a.V[(size_t)k * a.vstride + e] = h2[k] * inv_h2;
-  a.b[e] = 1.0;
+    for (int k = 0; k < 9; ++k) a.V[(size_t)k * a.vstride + e] = h2[k] * inv_h2;
+    a.b[e] = 1.0;
+  }
 }
 
 // ------------------------------------------------------------ stencil
@@ -115,6 +144,7 @@ __global__ __launch_bounds__(kNT) void stencil_kernel(StencilArgs a) {
   const int t = threadIdx.x;
   const int tpp = g.stpp;
   TileView tv;
+  tv.swp = g.swp;
   tv.V = a.V;
   tv.r = a.r;
   tv.src = a.src;
@@ -126,7 +156,6 @@ __global__ __launch_bounds__(kNT) void stencil_kernel(StencilArgs a) {
   tv.zout = a.zout;
   tv.n = g.n;
   tv.S = g.S;
-  tv.sw = g.sw;
   tv.tpp = tpp;
   tv.tx = g.tx;
   tv.ty = g.ty;
@@ -138,7 +167,8 @@ __global__ __launch_bounds__(kNT) void stencil_kernel(StencilArgs a) {
   // each member's partial sums follow the same tree.
   for (int js = 0; js < g.nstile; ++js) {
     tv.s0 = js * g.sw;
-    const int sv = tv.s0 + (t % tpp) * VEC;
+    tv.sw = min(g.sw, g.S - tv.s0);
+    const int sv = tv.s0 + (t % tpp) * VEC;   // member slot (< Sp)
     double beta[VEC], aprev[VEC], c1[VEC], c2[VEC], acc[VEC];
 #pragma unroll
     for (int c = 0; c < VEC; ++c) {
@@ -161,11 +191,11 @@ __global__ __launch_bounds__(kNT) void stencil_kernel(StencilArgs a) {
     for (; tile < tend; tile += tstep) stencil_tile<VEC, MODE, SYM>(tv, tile, ring, sym, beta, aprev, c1, c2, acc);
     if constexpr (MODE == M_PCG_J || MODE == M_PCG_Z) {
       group_reduce<VEC>(acc, tpp, red);
-      put_partial<VEC>(a.partial, g.S, tpp, acc, tv.s0);
+      put_partial<VEC>(a.partial, g.Sp, tpp, acc, tv.s0);
     } else if constexpr (MODE == M_CHEB) {
       if (a.cheb_last) {
         group_reduce<VEC>(acc, tpp, red);
-        put_partial<VEC>(a.partial, g.S, tpp, acc, tv.s0);
+        put_partial<VEC>(a.partial, g.Sp, tpp, acc, tv.s0);
       }
     }
   }
@@ -185,6 +215,7 @@ __global__ __launch_bounds__(kNT) void update_kernel(UpdateArgs a) {
   const int S = g.S, tpp = g.tpp;
   const int t = threadIdx.x;
   const int sv = (t % tpp) * VEC;
+  const bool lane_ok = sv < S;
   double alpha[VEC], act[VEC], ith[VEC], rz[VEC], rr[VEC];
 #pragma unroll
   for (int c = 0; c < VEC; ++c) {
@@ -194,24 +225,28 @@ __global__ __launch_bounds__(kNT) void update_kernel(UpdateArgs a) {
     rz[c] = 0.0;
     rr[c] = 0.0;
   }
-  // grid-stride loop, four strides per pass so 12 loads are in flight
+  // point-strided loop, four strides per pass so 12 loads are in flight
   constexpr int U = 4;
-  const size_t stride = (size_t)gridDim.x * kNT * VEC;
-  for (size_t e0 = ((size_t)blockIdx.x * kNT + t) * VEC; e0 < g.nelem; e0 += U * stride) {
+  const size_t P = (size_t)(kNT / tpp);
+  const size_t stride = (size_t)gridDim.x * P;
+  const double* diag = a.V + (size_t)g.cslot * g.vstride;
+  for (size_t p0 = (size_t)blockIdx.x * P + t / tpp; lane_ok && p0 < g.nr; p0 += U * stride) {
     double rv[U][VEC], qv[U][VEC], dv[U][VEC];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const size_t e = e0 + u * stride;
-      if (e < g.nelem) {
+      const size_t p = p0 + u * stride;
+      if (p < g.nr) {
+        const size_t e = p * S + sv;
         ld<VEC>(rv[u], a.r + e);
         ld<VEC>(qv[u], a.q + e);
-        ld<VEC>(dv[u], a.V + (size_t)g.cslot * g.vstride + e);
+        ld<VEC>(dv[u], diag + e);
       }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const size_t e = e0 + u * stride;
-      if (e >= g.nelem) break;
+      const size_t p = p0 + u * stride;
+      if (p >= g.nr) break;
+      const size_t e = p * S + sv;
 #pragma unroll
       for (int c = 0; c < VEC; ++c) {
         if (act[c] != 0.0 && alpha[c] != 0.0) rv[u][c] = fma(-alpha[c], qv[u][c], rv[u][c]);
@@ -230,12 +265,12 @@ __global__ __launch_bounds__(kNT) void update_kernel(UpdateArgs a) {
       }
     }
   }
-  const size_t pstride = (size_t)gridDim.x * S;
+  const size_t pstride = (size_t)gridDim.x * g.Sp;
   group_reduce<VEC>(rr, tpp, red);
-  put_partial<VEC>(a.partial + pstride, S, tpp, rr);
+  put_partial<VEC>(a.partial + pstride, g.Sp, tpp, rr);
   if constexpr (!CHEB) {
     group_reduce<VEC>(rz, tpp, red);
-    put_partial<VEC>(a.partial, S, tpp, rz);
+    put_partial<VEC>(a.partial, g.Sp, tpp, rz);
   }
 }
 
@@ -248,15 +283,19 @@ __global__ __launch_bounds__(kNT) void init_kernel(InitArgs a) {
   __shared__ double red[kWaves * 64 * 2];
   const Geometry& g = a.g;
   const int S = g.S, tpp = g.tpp, t = threadIdx.x;
+  const int sv = (t % tpp) * VEC;
+  const bool lane_ok = sv < S;
   double rz[VEC], bb[VEC], gm[VEC];
 #pragma unroll
   for (int c = 0; c < VEC; ++c) rz[c] = bb[c] = gm[c] = 0.0;
-  const size_t stride = (size_t)gridDim.x * kNT * VEC;
-  for (size_t e = ((size_t)blockIdx.x * kNT + t) * VEC; e < g.nelem; e += stride) {
+  const size_t P = (size_t)(kNT / tpp);
+  const size_t stride = (size_t)gridDim.x * P;
+  for (size_t p = (size_t)blockIdx.x * P + t / tpp; lane_ok && p < g.nr; p += stride) {
+    const size_t e = p * S + sv;
     double bv[VEC], dv[VEC], zero[VEC];
     if (a.b_broadcast) {
 #pragma unroll
-      for (int c = 0; c < VEC; ++c) bv[c] = a.b[(e + c) >> g.logS];
+      for (int c = 0; c < VEC; ++c) bv[c] = a.b[p];
     } else {
       ld<VEC>(bv, a.b + e);
     }
@@ -284,15 +323,15 @@ __global__ __launch_bounds__(kNT) void init_kernel(InitArgs a) {
       for (int c = 0; c < VEC; ++c) gm[c] = fmax(gm[c], rs[c] / dv[c]);
     }
   }
-  const size_t ps = (size_t)gridDim.x * S;
+  const size_t ps = (size_t)gridDim.x * g.Sp;
   group_reduce<VEC>(bb, tpp, red);
-  put_partial<VEC>(a.partial + ps, S, tpp, bb);
+  put_partial<VEC>(a.partial + ps, g.Sp, tpp, bb);
   if (!a.cheb) {
     group_reduce<VEC>(rz, tpp, red);
-    put_partial<VEC>(a.partial, S, tpp, rz);
+    put_partial<VEC>(a.partial, g.Sp, tpp, rz);
   } else {
     group_max<VEC>(gm, tpp, red);
-    put_partial<VEC>(a.partial + 2 * ps, S, tpp, gm);
+    put_partial<VEC>(a.partial + 2 * ps, g.Sp, tpp, gm);
   }
 }
 
@@ -301,11 +340,14 @@ template <int VEC>
 __global__ __launch_bounds__(kNT) void cheb_start_kernel(const double* V, const double* r, double* d,
                                                          double* z, Members m, Geometry g) {
   const int t = threadIdx.x, sv = (t % g.tpp) * VEC;
+  if (sv >= g.S) return;
   double ith[VEC];
 #pragma unroll
   for (int c = 0; c < VEC; ++c) ith[c] = m.cheb[(size_t)(sv + c) * kChebCoef];
-  const size_t stride = (size_t)gridDim.x * kNT * VEC;
-  for (size_t e = ((size_t)blockIdx.x * kNT + t) * VEC; e < g.nelem; e += stride) {
+  const size_t P = (size_t)(kNT / g.tpp);
+  const size_t stride = (size_t)gridDim.x * P;
+  for (size_t p = (size_t)blockIdx.x * P + t / g.tpp; p < g.nr; p += stride) {
+    const size_t e = p * g.S + sv;
     double rv[VEC], dv[VEC], zz[VEC];
     ld<VEC>(rv, r + e);
     ld<VEC>(dv, V + (size_t)g.cslot * g.vstride + e);
@@ -321,6 +363,7 @@ template <int VEC>
 __global__ __launch_bounds__(kNT) void final_kernel(double* x, const double* p0, const double* p1,
                                                     Members m, Geometry g) {
   const int t = threadIdx.x, sv = (t % g.tpp) * VEC;
+  if (sv >= g.S) return;
   const double* p = (m.ctl[CTL_K] & 1) ? p1 : p0;
   double ap[VEC];
   bool any = false;
@@ -330,8 +373,10 @@ __global__ __launch_bounds__(kNT) void final_kernel(double* x, const double* p0,
     any |= (ap[c] != 0.0);
   }
   if (!any) return;
-  const size_t stride = (size_t)gridDim.x * kNT * VEC;
-  for (size_t e = ((size_t)blockIdx.x * kNT + t) * VEC; e < g.nelem; e += stride) {
+  const size_t P = (size_t)(kNT / g.tpp);
+  const size_t stride = (size_t)gridDim.x * P;
+  for (size_t q = (size_t)blockIdx.x * P + t / g.tpp; q < g.nr; q += stride) {
+    const size_t e = q * g.S + sv;
     double xv[VEC], pv[VEC];
     ld<VEC>(xv, x + e);
     ld<VEC>(pv, p + e);
@@ -348,16 +393,20 @@ __global__ __launch_bounds__(kNT) void dot_kernel(const double* x, const double*
                                                   double* partial, Geometry g) {
   __shared__ double red[kWaves * 64 * 2];
   const int t = threadIdx.x, S = g.S, tpp = g.tpp;
+  const int sv = (t % tpp) * VEC;
+  const bool lane_ok = sv < S;
   double acc[VEC];
 #pragma unroll
   for (int c = 0; c < VEC; ++c) acc[c] = 0.0;
-  const size_t stride = (size_t)gridDim.x * kNT * VEC;
-  for (size_t e = ((size_t)blockIdx.x * kNT + t) * VEC; e < g.nelem; e += stride) {
+  const size_t P = (size_t)(kNT / tpp);
+  const size_t stride = (size_t)gridDim.x * P;
+  for (size_t p = (size_t)blockIdx.x * P + t / tpp; lane_ok && p < g.nr; p += stride) {
+    const size_t e = p * S + sv;
     double xv[VEC], yv[VEC];
     ld<VEC>(xv, x + e);
     if (y_bcast) {
 #pragma unroll
-      for (int c = 0; c < VEC; ++c) yv[c] = y[(e + c) >> g.logS];
+      for (int c = 0; c < VEC; ++c) yv[c] = y[p];
     } else {
       ld<VEC>(yv, y + e);
     }
@@ -365,7 +414,7 @@ __global__ __launch_bounds__(kNT) void dot_kernel(const double* x, const double*
     for (int c = 0; c < VEC; ++c) acc[c] = fma(xv[c], yv[c], acc[c]);
   }
   group_reduce<VEC>(acc, tpp, red);
-  put_partial<VEC>(partial, S, tpp, acc);
+  put_partial<VEC>(partial, g.Sp, tpp, acc);
 }
 
 
@@ -388,7 +437,7 @@ __global__ __launch_bounds__(kFinNT) void finish_kernel(FinishArgs a) {
   } while (0)
 
 void launch_assemble(const AsmArgs& a, hipStream_t s) {
-  const unsigned blocks = (unsigned)((a.nelem + kNT - 1) / kNT);
+  const unsigned blocks = (unsigned)a.ntx * (unsigned)((a.n + kAsmTY - 1) / kAsmTY);
   hipLaunchKernelGGL(assemble_kernel, dim3(blocks), dim3(kNT), 0, s, a);
 }
 

@@ -97,6 +97,27 @@ def _ensemble_width(t: torch.Tensor) -> int:
     return int(t.shape[-1])
 
 
+def _host_params(y, d: int, name: str = "y") -> np.ndarray:
+    """Parameters (S, d) as a contiguous float64 host array (the library
+    reads them from host memory).  Accepts a torch tensor on any device or
+    anything numpy converts."""
+    if isinstance(y, torch.Tensor):
+        y = y.detach().to("cpu", torch.float64)
+        y = y.numpy()
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    if y.ndim != 2 or y.shape[1] != d:
+        raise ValueError(f"{name} must have shape (S, {d}), got {y.shape}")
+    return y
+
+
+def _device_of(y, device):
+    if device is not None:
+        return torch.device(device)
+    if isinstance(y, torch.Tensor) and y.is_cuda:
+        return y.device
+    return torch.device("cuda")
+
+
 def workspace_bytes(prob: Problem, S: int, opts: Optional[SolverOptions] = None) -> int:
     """Bytes of the workspace `workspace` allocates (ens_pcg_workspace_bytes;
     with Jacobi, the larger Chebyshev layout that cheb_apply also needs)."""
@@ -144,18 +165,18 @@ def _require_matrix(V: torch.Tensor, prob: Problem, S: int):
         raise ValueError("V must have the library's slot stride (use assemble or empty_matrix)")
 
 
-def assemble(prob: Problem, y: torch.Tensor):
+def assemble(prob: Problem, y, device=None):
     """Ensemble matrix V (slots, N_r, S; slot stride matrix_slot_stride) and
-    right-hand side b (N_r, S) for y (S, d)."""
-    _require_cuda(y, "y")
-    S = int(y.shape[0])
-    if y.dim() != 2 or y.shape[1] != prob.d:
-        raise ValueError(f"y must have shape (S, {prob.d})")
-    V = empty_matrix(prob, S, y.device)
-    b = torch.empty((prob.rows, S), dtype=torch.float64, device=y.device)
+    right-hand side b (N_r, S) for parameters y (S, d), any S in [1, 64].
+    The outputs live on ``device`` (default: y's GPU, else the current one)."""
+    yh = _host_params(y, prob.d)
+    S = int(yh.shape[0])
+    dev = _device_of(y, device)
+    V = empty_matrix(prob, S, dev)
+    b = torch.empty((prob.rows, S), dtype=torch.float64, device=dev)
     pc = prob.c()
-    L.check(L.lib().ens_assemble_ensemble(C.byref(pc), S, _p(y), _p(V), _p(b), _stream(y.device)),
-            "ens_assemble_ensemble")
+    L.check(L.lib().ens_assemble_ensemble(C.byref(pc), S, yh.ctypes.data_as(L.f64p), _p(V), _p(b),
+                                          _stream(dev)), "ens_assemble_ensemble")
     return V, b
 
 
@@ -259,17 +280,20 @@ def member_dot(a: torch.Tensor, b: torch.Tensor, ws: Optional[torch.Tensor] = No
     return out
 
 
-def param_indicator(prob: Problem, y: torch.Tensor, ws: Optional[torch.Tensor] = None) -> np.ndarray:
+def param_indicator(prob: Problem, y, ws: Optional[torch.Tensor] = None,
+                    device=None) -> np.ndarray:
     """H(y) per member (S,): the largest eigenvalue ratio of the diffusion
     tensor over the domain (the parameter-based grouping indicator)."""
-    S = int(y.shape[0])
-    _require_cuda(y, "y", (S, prob.d))
+    yh = _host_params(y, prob.d)
+    S = int(yh.shape[0])
+    dev = ws.device if ws is not None else _device_of(y, device)
     if ws is None:
-        ws = workspace(Problem(2, 2), S, None, y.device)
+        ws = workspace(Problem(2, 2), S, None, dev)
     h = np.zeros(S, np.float64)
     pc = prob.c()
-    L.check(L.lib().ens_param_indicator(C.byref(pc), S, _p(y), h.ctypes.data_as(L.f64p), _p(ws),
-                                        ws.numel(), _stream(y.device)), "ens_param_indicator")
+    L.check(L.lib().ens_param_indicator(C.byref(pc), S, yh.ctypes.data_as(L.f64p),
+                                        h.ctypes.data_as(L.f64p), _p(ws), ws.numel(), _stream(dev)),
+            "ens_param_indicator")
     return h
 
 
@@ -280,63 +304,59 @@ def param_indicator_samples(prob: Problem, ys: np.ndarray, device="cuda") -> np.
     ws = workspace(Problem(2, 2), 64, None, device)
     for a in range(0, len(ys), 64):
         blk = ys[a:a + 64]
-        pad = np.vstack([blk, np.repeat(blk[-1:], 64 - len(blk), axis=0)])
-        out[a:a + len(blk)] = param_indicator(prob, torch.tensor(pad, device=device), ws)[:len(blk)]
+        out[a:a + len(blk)] = param_indicator(prob, blk, ws)
     return out
 
 
-def dqdy(prob: Problem, y: torch.Tensor, u: torch.Tensor, lam: torch.Tensor,
+def dqdy(prob: Problem, y, u: torch.Tensor, lam: torch.Tensor,
          ws: Optional[torch.Tensor] = None) -> np.ndarray:
     """-lambda^T (dA/dy_j) u per member, shape (S, d)."""
-    S = int(y.shape[0])
-    _require_cuda(y, "y", (S, prob.d))
+    yh = _host_params(y, prob.d)
+    S = int(yh.shape[0])
     _require_cuda(u, "u", (prob.rows, S))
     _require_cuda(lam, "lam", (prob.rows, S))
     if ws is None:
-        ws = workspace(Problem(2, 2), S, None, y.device)
+        ws = workspace(Problem(2, 2), S, None, u.device)
     g = np.zeros((S, prob.d), np.float64)
     pc = prob.c()
-    L.check(L.lib().ens_dqdy(C.byref(pc), S, _p(y), _p(u), _p(lam), g.ctypes.data_as(L.f64p),
-                             _p(ws), ws.numel(), _stream(y.device)), "ens_dqdy")
+    L.check(L.lib().ens_dqdy(C.byref(pc), S, yh.ctypes.data_as(L.f64p), _p(u), _p(lam),
+                             g.ctypes.data_as(L.f64p), _p(ws), ws.numel(), _stream(u.device)),
+            "ens_dqdy")
     return g
 
 
-def adjoint_grad(prob: Problem, y: torch.Tensor, V: torch.Tensor, u: torch.Tensor,
+def adjoint_grad(prob: Problem, y, V: torch.Tensor, u: torch.Tensor,
                  w: torch.Tensor, opts: Optional[SolverOptions] = None,
                  ws: Optional[torch.Tensor] = None):
     """(lambda, dQ/dy (S, d), iters, status) for Q = w^T u."""
     opts = opts or SolverOptions()
-    S = int(y.shape[0])
-    _require_cuda(y, "y", (S, prob.d))
+    yh = _host_params(y, prob.d)
+    S = int(yh.shape[0])
     _require_matrix(V, prob, S)
     _require_cuda(u, "u", (prob.rows, S))
     _require_cuda(w, "w", (prob.rows,))
     if ws is None:
-        ws = workspace(prob, S, opts, y.device)
+        ws = workspace(prob, S, opts, u.device)
     lam = torch.empty_like(u)
     g = np.zeros((S, prob.d), np.float64)
     iters = np.zeros(S, np.int32)
     status = np.zeros(S, np.int32)
     pc, oc = prob.c(), opts.c()
     L.check(L.lib().ens_adjoint_grad(
-        C.byref(pc), C.byref(oc), S, _p(y), _p(V), _p(u), _p(w), _p(lam),
+        C.byref(pc), C.byref(oc), S, yh.ctypes.data_as(L.f64p), _p(V), _p(u), _p(w), _p(lam),
         g.ctypes.data_as(L.f64p), iters.ctypes.data_as(L.i32p), status.ctypes.data_as(L.i32p),
-        _p(ws), ws.numel(), _stream(y.device)), "ens_adjoint_grad")
+        _p(ws), ws.numel(), _stream(u.device)), "ens_adjoint_grad")
     return lam, g, iters, status
 
 
 def qoi_weights(n: int, device=None, dim: int = 2) -> torch.Tensor:
-    """Mean over the interior nodes of [0.4, 0.6]^dim (decided in integers:
-    2(n+1) <= 5 i <= 3(n+1) for the 1-based node index i in each direction),
-    in row order (x fastest)."""
-    i = np.arange(1, n + 1)
-    inside = (5 * i >= 2 * (n + 1)) & (5 * i <= 3 * (n + 1))
-    m = inside
-    for _ in range(dim - 1):
-        m = np.multiply.outer(inside, m)
-    m = m.reshape(-1)
-    w = np.where(m, 1.0 / m.sum(), 0.0)
-    return torch.tensor(w, dtype=torch.float64, device=device or "cuda")
+    """The QoI weights w (N_r,) of Q = w^T u, the mean over the interior nodes
+    of [0.4, 0.6]^dim (ens_qoi_weights)."""
+    prob = Problem(n, 4, 0, 0.0, dim=dim) if dim == 3 else Problem(n, 2)
+    w = torch.empty(prob.rows, dtype=torch.float64, device=device or "cuda")
+    pc = prob.c()
+    L.check(L.lib().ens_qoi_weights(C.byref(pc), _p(w), _stream(w.device)), "ens_qoi_weights")
+    return w
 
 
 class BatchResult(NamedTuple):

@@ -132,10 +132,9 @@ def _solve_serial(prob, y_level, groups, opts, wss, device, spmv_acc):
         g = np.asarray(g)
         S = len(g)
         ws = wss(S)
-        y = torch.tensor(y_level[g], dtype=torch.float64, device=device)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        V, b = E.assemble(prob, y)
+        V, b = E.assemble(prob, y_level[g], device=device)
         e1.record()
         res = E.solve(prob, V, b, opts, ws=ws)     # blocks: both events have completed
         spmv_acc[3] += e0.elapsed_time(e1)

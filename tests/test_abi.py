@@ -144,8 +144,10 @@ def test_argument_validation_without_gpu(L):
     assert rc == L.ENS_EINVAL
     prob = L.ens_problem(64, 2, 0, 0, 0.0)
     opts = L.ens_opts()
-    assert lib.ens_pcg_workspace_bytes(C.byref(prob), C.byref(opts), 3) == 0      # S not a power of 2
-    assert lib.ens_pcg_workspace_bytes(C.byref(prob), C.byref(opts), 128) == 0
+    for S in (0, -1, 65, 128):                                                      # S outside [1, 64]
+        assert lib.ens_pcg_workspace_bytes(C.byref(prob), C.byref(opts), S) == 0
+    for S in (3, 20, 24, 48, 64):                                                   # any width in [1, 64]
+        assert lib.ens_pcg_workspace_bytes(C.byref(prob), C.byref(opts), S) > 64 * 64 * S * 8 * 5
     assert lib.ens_pcg_workspace_bytes(C.byref(prob), C.byref(opts), 32) > 64 * 64 * 32 * 8 * 5
     bad = L.ens_problem(1, 2, 0, 0, 0.0)
     assert lib.ens_pcg_workspace_bytes(C.byref(bad), C.byref(opts), 8) == 0
@@ -153,7 +155,10 @@ def test_argument_validation_without_gpu(L):
     rc = lib.ens_pcg_solve(C.byref(prob), C.byref(opts), 8, None, None, None, None, None, None,
                            None, None, None, 0, None)
     assert rc == L.ENS_EINVAL
-    rc = lib.ens_assemble_ensemble(C.byref(prob), 6, C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), None)
+    rc = lib.ens_assemble_ensemble(C.byref(prob), 6, None, C.c_void_p(16), C.c_void_p(16), None)
+    assert rc == L.ENS_EINVAL
+    rc = lib.ens_assemble_ensemble(C.byref(prob), 65, np.zeros((65, 2)).ctypes.data_as(L.f64p),
+                                   C.c_void_p(16), C.c_void_p(16), None)
     assert rc == L.ENS_EINVAL
     opts_bad = L.ens_opts(5, 0, 0.0, 0.0, 0, 0, 0, 0, 0, 0)
     assert lib.ens_pcg_workspace_bytes(C.byref(prob), C.byref(opts_bad), 8) == 0
@@ -216,7 +221,8 @@ def test_layout_and_new_entry_points_without_gpu(L):
         nr_s = n * n * S
         assert Ls == ((nr_s + 31) // 32) * 32 + 512
         assert Ls % 32 == 0 and Ls - nr_s >= 512
-    assert lib.ens_matrix_slot_stride(C.byref(prob), 48) == 0
+    assert lib.ens_matrix_slot_stride(C.byref(prob), 65) == 0
+    assert lib.ens_matrix_slot_stride(C.byref(prob), 48) == ((512 * 512 * 48 + 31) // 32) * 32 + 512
     assert lib.ens_batch_workspace_bytes(0) == 0
     assert lib.ens_batch_workspace_bytes(1025) == 0
     assert lib.ens_batch_workspace_bytes(64) > 0
@@ -234,10 +240,12 @@ def test_layout_and_new_entry_points_without_gpu(L):
     assert lib.ens_batch_solve(None, 1, items, bws, nb - 1, None) == L.ENS_ENOMEM
     it = items[0]
     it.prob = prob
-    it.S = 24
+    it.S = 65
     it.V_dev = it.b_dev = it.x_dev = it.ws_dev = 4096
     it.ws_bytes = 1 << 40
     assert lib.ens_batch_solve(None, 1, items, bws, nb, None) == L.ENS_EINVAL
+    it.S = 24                     # valid width, but the batched solver takes powers of two
+    assert lib.ens_batch_solve(None, 1, items, bws, nb, None) == L.ENS_ENOTSUP
     it.S = 32
     it.ws_bytes = 1024
     assert lib.ens_batch_solve(None, 1, items, bws, nb, None) == L.ENS_ENOMEM
@@ -331,9 +339,10 @@ def test_3d_model_descriptor_without_gpu(L):
     a = C.c_void_p(4096)
     g = np.zeros(64)
     assert lib.ens_assemble_ensemble(C.byref(p), 8, None, a, a, None) == L.ENS_EINVAL
-    assert lib.ens_dqdy(C.byref(p), 8, a, a, None, g.ctypes.data_as(L.f64p), a, 1 << 30,
+    yh = np.zeros((8, 4)).ctypes.data_as(L.f64p)
+    assert lib.ens_dqdy(C.byref(p), 8, yh, a, None, g.ctypes.data_as(L.f64p), a, 1 << 30,
                         None) == L.ENS_EINVAL
-    assert lib.ens_dqdy(C.byref(p), 8, a, a, a, g.ctypes.data_as(L.f64p), a, 16, None) == L.ENS_ENOMEM
+    assert lib.ens_dqdy(C.byref(p), 8, yh, a, a, g.ctypes.data_as(L.f64p), a, 16, None) == L.ENS_ENOMEM
     nb = lib.ens_batch_workspace_bytes(1)
     items = (L.ens_batch_item * 1)()
     it = items[0]
@@ -342,3 +351,32 @@ def test_3d_model_descriptor_without_gpu(L):
     it.V_dev = it.b_dev = it.x_dev = it.ws_dev = 4096
     it.ws_bytes = 1 << 40
     assert lib.ens_batch_solve(None, 1, items, C.c_void_p(4096), nb, None) == L.ENS_ENOTSUP
+
+
+@pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf])
+def test_non_finite_parameters_rejected_before_device_work(L, bad):
+    """A non-finite parameter value is ENS_EINVAL from every entry point that
+    takes parameters, checked on the host before any device call (the device
+    pointers below are never dereferenced)."""
+    lib = L.lib()
+    dev = C.c_void_p(256)
+    for prob in (L.ens_problem(16, 4, 0, 2, 0.4), L.ens_problem(7, 3, 0, 3, 0.0)):
+        for S in (1, 5, 20):
+            y = np.zeros((S, prob.d))
+            y[S - 1, prob.d - 1] = bad
+            yp = y.ctypes.data_as(L.f64p)
+            assert lib.ens_assemble_ensemble(C.byref(prob), S, yp, dev, dev, None) == L.ENS_EINVAL
+            h = np.zeros(S)
+            assert lib.ens_param_indicator(C.byref(prob), S, yp, h.ctypes.data_as(L.f64p), dev,
+                                           1 << 30, None) == L.ENS_EINVAL
+            g = np.zeros((S, prob.d))
+            assert lib.ens_dqdy(C.byref(prob), S, yp, dev, dev, g.ctypes.data_as(L.f64p), dev,
+                                1 << 30, None) == L.ENS_EINVAL
+            it = np.zeros(S, np.int32)
+            assert lib.ens_adjoint_grad(C.byref(prob), None, S, yp, dev, dev, dev, dev,
+                                        g.ctypes.data_as(L.f64p), it.ctypes.data_as(L.i32p),
+                                        it.ctypes.data_as(L.i32p), dev, 1 << 40, None) == L.ENS_EINVAL
+    assert lib.ens_qoi_weights(C.byref(L.ens_problem(16, 4, 0, 2, 0.4)), None, None) == L.ENS_EINVAL
+    # n = 2: no interior node lies in [0.4, 0.6] (5 i in [6, 9] has no solution)
+    assert lib.ens_qoi_weights(C.byref(L.ens_problem(2, 4, 0, 2, 0.4)), C.c_void_p(256),
+                               None) == L.ENS_EINVAL
