@@ -63,40 +63,65 @@ constexpr int kMaxD = 16;
 // Tiles of kAsmTX x kAsmTY grid points, grid-strided over the workgroups.
 // Per tile the mode tables sin(k pi I h) at the tile's node columns and rows
 // are computed once and shared by every point and member of the tile (the
-// sample-independent part of the form); per (point, member) the five a
-// values and their mode derivatives follow from the tables.
+// sample-independent part of the form).  Per (point, member) the form is
+// regrouped by the node a mode value sits at: the x-face terms, y-face
+// terms and cross terms of the row give five coefficients cC, cE, cW, cN, cS
+// (independent of the mode), and the mode-k derivative adds
+//   cC sC + cE sE + cW sW + cN sN + cS sS,   sX = sin(k pi x1) sin(k pi x2) at X,
+// its factor amp / k^2 applied once to the workgroup's sum.  The same
+// products give a = 1 + sum_k (amp y_{k+1} / k^2) sX at the five nodes for
+// the anisotropy derivatives.
 template <int VEC>
 __global__ __launch_bounds__(kNT) void dqdy_kernel(DqdyArgs a) {
   __shared__ double red[kWaves * 64 * 2];
   __shared__ double sI[kMaxModes][kAsmTX + 2];
   __shared__ double sJ[kMaxModes][kAsmTY + 2];
+  __shared__ double wy[kMaxS][kMaxModes];   // amp y_{k+1} / k^2 per member slot
+  __shared__ double wk[kMaxModes];          // amp / k^2
+  __shared__ double coef[9][kMaxS];         // per member slot: K entries and their derivatives
   const Geometry& g = a.g;
   const int S = g.S, n = g.n, tpp = g.tpp, t = threadIdx.x, d = a.d, nm = a.d - 2;
   const int sv = (t % tpp) * VEC;
   const bool lane_ok = sv < S;
   const int svl = lane_ok ? sv : S - VEC;   // idle slots compute on real members, add nothing
+  if (t < nm) wk[t] = a.amp / (double)((t + 1) * (t + 1));
+  for (int x = t; x < S * nm; x += kNT) {
+    const int m = x / nm, k = x % nm;
+    wy[m][k] = (a.amp * a.y[(size_t)m * d + k + 2]) / (double)((k + 1) * (k + 1));
+  }
 
-  // per-member coefficients and their derivatives
-  double k11[VEC], k22[VEC], k12[VEC], dk[2][3][VEC], ym[VEC][kMaxD];
-#pragma unroll
-  for (int c = 0; c < VEC; ++c) {
-    const double* y = a.y + (size_t)(svl + c) * d;
-#pragma unroll
-    for (int q = 0; q < kMaxD; ++q) ym[c][q] = (q < d) ? y[q] : 0.0;
+  // per-member coefficients and their derivatives, once per member and
+  // workgroup: K's entries, and d/dy1 (through eps), d/dy2 (through theta)
+  // of them
+  if (t < S) {
+    const double* y = a.y + (size_t)t * d;
     const double eps = (a.eps_model == 0) ? pow(10.0, -(1.0 + y[0])) : pow(10.0, -(1.5 + 1.5 * y[0]));
     const double th = (M_PI / 4.0) * (1.0 + y[1]);
     const double co = cos(th), si = sin(th);
-    k11[c] = co * co + eps * (si * si);
-    k22[c] = si * si + eps * (co * co);
-    k12[c] = (1.0 - eps) * (si * co);
+    coef[0][t] = co * co + eps * (si * si);
+    coef[1][t] = si * si + eps * (co * co);
+    coef[2][t] = (1.0 - eps) * (si * co);
     const double deps = -((a.eps_model == 0) ? 1.0 : 1.5) * log(10.0) * eps;
-    dk[0][0][c] = si * si * deps;
-    dk[0][1][c] = co * co * deps;
-    dk[0][2][c] = -si * co * deps;
+    coef[3][t] = si * si * deps;
+    coef[4][t] = co * co * deps;
+    coef[5][t] = -si * co * deps;
     const double dth = M_PI / 4.0, s2 = sin(2.0 * th), c2 = cos(2.0 * th);
-    dk[1][0][c] = -(1.0 - eps) * s2 * dth;
-    dk[1][1][c] = (1.0 - eps) * s2 * dth;
-    dk[1][2][c] = (1.0 - eps) * c2 * dth;
+    coef[6][t] = -(1.0 - eps) * s2 * dth;
+    coef[7][t] = (1.0 - eps) * s2 * dth;
+    coef[8][t] = (1.0 - eps) * c2 * dth;
+  }
+  __syncthreads();
+  double k11[VEC], k22[VEC], k12[VEC], dk[2][3][VEC];
+#pragma unroll
+  for (int c = 0; c < VEC; ++c) {
+    const int m = svl + c;
+    k11[c] = coef[0][m];
+    k22[c] = coef[1][m];
+    k12[c] = coef[2][m];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int r = 0; r < 3; ++r) dk[q][r][c] = coef[3 + 3 * q + r][m];
   }
   double acc[kMaxD][VEC];
 #pragma unroll
@@ -123,17 +148,38 @@ __global__ __launch_bounds__(kNT) void dqdy_kernel(DqdyArgs a) {
       const int i = i0 + pt % kAsmTX, j = j0 + pt / kAsmTX;
       if (i >= n || j >= n) continue;
       const size_t e = ((size_t)j * n + i) * rS + sv;
+      // All ten loads are issued unconditionally, a neighbour outside the
+      // grid reading the point itself, and its values are zeroed after:
+      // loads inside lane-dependent branches would each be waited for at
+      // the branch's end, one memory round trip per neighbour.
+      const bool okE = i + 1 < n, okW = i > 0, okN = j + 1 < n, okS = j > 0;
+      const size_t eE = okE ? e + rS : e, eW = okW ? e - rS : e;
+      const size_t eN = okN ? e + rS * n : e, eS = okS ? e - rS * n : e;
       double uC[VEC], uE[VEC], uW[VEC], uN[VEC], uS[VEC];
       double lC[VEC], lE[VEC], lW[VEC], lN[VEC], lS[VEC];
       ldv<VEC>(uC, a.u + e);
       ldv<VEC>(lC, a.lam + e);
+      ldv<VEC>(uE, a.u + eE);
+      ldv<VEC>(lE, a.lam + eE);
+      ldv<VEC>(uW, a.u + eW);
+      ldv<VEC>(lW, a.lam + eW);
+      ldv<VEC>(uN, a.u + eN);
+      ldv<VEC>(lN, a.lam + eN);
+      ldv<VEC>(uS, a.u + eS);
+      ldv<VEC>(lS, a.lam + eS);
 #pragma unroll
-      for (int c = 0; c < VEC; ++c) uE[c] = uW[c] = uN[c] = uS[c] = lE[c] = lW[c] = lN[c] = lS[c] = 0.0;
-      if (i + 1 < n) { ldv<VEC>(uE, a.u + e + rS); ldv<VEC>(lE, a.lam + e + rS); }
-      if (i > 0) { ldv<VEC>(uW, a.u + e - rS); ldv<VEC>(lW, a.lam + e - rS); }
-      if (j + 1 < n) { ldv<VEC>(uN, a.u + e + rS * n); ldv<VEC>(lN, a.lam + e + rS * n); }
-      if (j > 0) { ldv<VEC>(uS, a.u + e - rS * n); ldv<VEC>(lS, a.lam + e - rS * n); }
+      for (int c = 0; c < VEC; ++c) {
+        uE[c] = okE ? uE[c] : 0.0;
+        lE[c] = okE ? lE[c] : 0.0;
+        uW[c] = okW ? uW[c] : 0.0;
+        lW[c] = okW ? lW[c] : 0.0;
+        uN[c] = okN ? uN[c] : 0.0;
+        lN[c] = okN ? lN[c] : 0.0;
+        uS[c] = okS ? uS[c] : 0.0;
+        lS[c] = okS ? lS[c] : 0.0;
+      }
       double fE[VEC], fN[VEC], fW[VEC], fS[VEC], fm[VEC];
+      double cC[VEC], cE[VEC], cW[VEC], cN[VEC], cS[VEC];
 #pragma unroll
       for (int c = 0; c < VEC; ++c) {
         fE[c] = (lE[c] - lC[c]) * (uE[c] - uC[c]);
@@ -141,33 +187,38 @@ __global__ __launch_bounds__(kNT) void dqdy_kernel(DqdyArgs a) {
         fW[c] = (i == 0) ? lC[c] * uC[c] : 0.0;   // face from the boundary node
         fS[c] = (j == 0) ? lC[c] * uC[c] : 0.0;
         fm[c] = (lE[c] - lW[c]) * (uN[c] - uS[c]) + (lN[c] - lS[c]) * (uE[c] - uW[c]);
+        cE[c] = 0.5 * (k11[c] * fE[c]);
+        cW[c] = 0.5 * (k11[c] * fW[c]);
+        cN[c] = 0.5 * (k22[c] * fN[c]);
+        cS[c] = 0.5 * (k22[c] * fS[c]);
+        cC[c] = (cE[c] + cW[c]) + (cN[c] + cS[c]) + 0.25 * (k12[c] * fm[c]);
       }
-      // a and its mode derivatives at C, E, W, N, S; table columns of the
-      // nodes i, i + 1, i + 2 (1-based node I = i + 1)
+      // table columns of the nodes i, i + 1, i + 2 (1-based node I = i + 1)
       const int qi = i - i0 + 1, qj = j - j0 + 1;
       double aC[VEC], aE[VEC], aW[VEC], aN[VEC], aS[VEC];
 #pragma unroll
       for (int c = 0; c < VEC; ++c) aC[c] = aE[c] = aW[c] = aN[c] = aS[c] = 1.0;
 #pragma unroll
-      for (int k = 1; k <= kMaxD - 2; ++k) {
-        if (k <= nm) {
-          const double sIm = sI[k - 1][qi - 1], sIc = sI[k - 1][qi], sIp = sI[k - 1][qi + 1];
-          const double sJm = sJ[k - 1][qj - 1], sJc = sJ[k - 1][qj], sJp = sJ[k - 1][qj + 1];
-          const double w = a.amp / (double)(k * k);
-          const double mC = w * sJc * sIc, mE = w * sJc * sIp, mW = w * sJc * sIm;
-          const double mN = w * sJp * sIc, mS = w * sJm * sIc;
+      for (int k = 0; k < kMaxModes; ++k) {
+        if (k < nm) {
+          const double sIm = sI[k][qi - 1], sIc = sI[k][qi], sIp = sI[k][qi + 1];
+          const double sJm = sJ[k][qj - 1], sJc = sJ[k][qj], sJp = sJ[k][qj + 1];
+          const double pC = sJc * sIc, pE = sJc * sIp, pW = sJc * sIm;
+          const double pN = sJp * sIc, pS = sJm * sIc;
 #pragma unroll
           for (int c = 0; c < VEC; ++c) {
-            const double yk = ym[c][k + 1];
-            aC[c] += yk * mC;
-            aE[c] += yk * mE;
-            aW[c] += yk * mW;
-            aN[c] += yk * mN;
-            aS[c] += yk * mS;
-            // mode derivative contributions
-            const double gx = ((mC + mE) / 2.0) * fE[c] + ((mW + mC) / 2.0) * fW[c];
-            const double gy = ((mC + mN) / 2.0) * fN[c] + ((mS + mC) / 2.0) * fS[c];
-            acc[k + 1][c] += k11[c] * gx + k22[c] * gy + k12[c] * mC * fm[c] / 4.0;
+            const double w = wy[svl + c][k];
+            aC[c] = fma(w, pC, aC[c]);
+            aE[c] = fma(w, pE, aE[c]);
+            aW[c] = fma(w, pW, aW[c]);
+            aN[c] = fma(w, pN, aN[c]);
+            aS[c] = fma(w, pS, aS[c]);
+            double v = cC[c] * pC;
+            v = fma(cE[c], pE, v);
+            v = fma(cW[c], pW, v);
+            v = fma(cN[c], pN, v);
+            v = fma(cS[c], pS, v);
+            acc[k + 2][c] += v;
           }
         }
       }
@@ -181,6 +232,12 @@ __global__ __launch_bounds__(kNT) void dqdy_kernel(DqdyArgs a) {
       }
     }
   }
+  // the modes' factor amp / k^2
+#pragma unroll
+  for (int k = 0; k < kMaxModes; ++k)
+    if (k < nm)
+#pragma unroll
+      for (int c = 0; c < VEC; ++c) acc[k + 2][c] *= wk[k];
   const size_t ps = (size_t)gridDim.x * g.Sp;
 #pragma unroll
   for (int q = 0; q < kMaxD; ++q) {

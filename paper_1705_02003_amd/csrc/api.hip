@@ -987,9 +987,12 @@ static int dqdy_staged(const ens_problem* prob, int32_t S, const double* u_dev,
   a.amp = prob->amp;
   a.ntx = (prob->n + kAsmTX - 1) / kAsmTX;
   a.ntiles = a.ntx * ((prob->n + kAsmTY - 1) / kAsmTY);
-  // the partial buffer holds 3 * kMaxGroups * kMaxS doubles; d <= 16 rows of
-  // groups * Sp partials fit for groups <= 3 * kMaxGroups / 16
-  const int groups = std::min(a.ntiles, 3 * kMaxGroups / 16);
+  // the partial buffer holds 3 * kMaxGroups * kMaxS doubles: d arrays of
+  // groups * Sp partials; at most kMaxGroups workgroups (one tile each when
+  // the grid has that few)
+  const int cap = (int)std::min<size_t>((size_t)3 * kMaxGroups * kMaxS / ((size_t)prob->d * g.Sp),
+                                        (size_t)kMaxGroups);
+  const int groups = std::min(a.ntiles, cap);
   launch_dqdy(a, groups, s);
   {
     // dQ/dy_j = -(n+1)^2 * (the face/node sums of h^2 lambda^T dA/dy_j u)

@@ -35,16 +35,18 @@ namespace ens {
 // computed once per tile: the mode tables sin(k pi I h) at the tile's node
 // columns I and rows J (paper, Section 2.3: sample-independent quantities
 // are computed once for the whole ensemble); what depends only on the
-// member (eps, theta, the entries of K) once per member and tile.  Then
-// every (point, member) forms a at its node and the four neighbours from
-// the tables, the face means and the nine values.  Evaluation order of every
-// expression follows the scheme's definition term by term; contraction into
-// FMA is off so the values are the plainly rounded ones.
+// member once per member and tile: the entries of K(eps, theta) and the mode
+// weights amp y_{k+1} / k^2.  Then every (point, member) forms a at its node
+// and the four neighbours as 1 + sum_k weight_k sin(k pi x1) sin(k pi x2)
+// from the tables, the face means and the nine values.  No division is left
+// in the per-element work.  Contraction into FMA is off so every product
+// and sum is the plainly rounded one.
 __global__ __launch_bounds__(kNT) void assemble_kernel(AsmArgs a) {
 #pragma clang fp contract(off)
   __shared__ double sI[kMaxModes][kAsmTX + 2];
   __shared__ double sJ[kMaxModes][kAsmTY + 2];
   __shared__ double kc[3][kMaxS];
+  __shared__ double wk[kMaxS][kMaxModes];
   __shared__ double ys[kAsmY];
   const int n = a.n, d = a.d, t = threadIdx.x, nm = a.d - 2;
   for (int x = t; x < a.mc * d; x += kNT) ys[x] = a.y[x];
@@ -62,6 +64,10 @@ __global__ __launch_bounds__(kNT) void assemble_kernel(AsmArgs a) {
     sJ[k][q] = sin(kp * ((double)(j0 + q) / np1));
   }
   __syncthreads();
+  for (int x = t; x < a.mc * nm; x += kNT) {
+    const int m = x / nm, k = x % nm + 1;
+    wk[m][k - 1] = (a.amp * ys[m * d + k + 1]) / (double)(k * k);
+  }
   if (t < a.mc) {
     const double* y = ys + t * d;
     const double eps = (a.eps_model == 0) ? pow(10.0, -(1.0 + y[0])) : pow(10.0, -(1.5 + 1.5 * y[0]));
@@ -74,7 +80,6 @@ __global__ __launch_bounds__(kNT) void assemble_kernel(AsmArgs a) {
   __syncthreads();
   const int cl = t % a.mcp;
   if (cl >= a.mc) return;
-  const double* y = ys + cl * d;
   const double k11 = kc[0][cl], k22 = kc[1][cl], k12 = kc[2][cl];
   const double inv_h2 = np1 * np1;
   for (int pt = t / a.mcp; pt < kAsmTX * kAsmTY; pt += kNT / a.mcp) {
@@ -83,15 +88,15 @@ __global__ __launch_bounds__(kNT) void assemble_kernel(AsmArgs a) {
     // table columns of the nodes i, i + 1, i + 2 (1-based node I = i + 1)
     const int qi = i - i0 + 1, qj = j - j0 + 1;
     double aC = 1.0, aE = 1.0, aW = 1.0, aN = 1.0, aS = 1.0;
-    for (int k = 1; k <= nm; ++k) {
-      const double sIm = sI[k - 1][qi - 1], sIc = sI[k - 1][qi], sIp = sI[k - 1][qi + 1];
-      const double sJm = sJ[k - 1][qj - 1], sJc = sJ[k - 1][qj], sJp = sJ[k - 1][qj + 1];
-      const double yk = y[k + 1], kk = (double)(k * k);
-      aC = aC + a.amp * ((yk * (sJc * sIc)) / kk);
-      aE = aE + a.amp * ((yk * (sJc * sIp)) / kk);
-      aW = aW + a.amp * ((yk * (sJc * sIm)) / kk);
-      aN = aN + a.amp * ((yk * (sJp * sIc)) / kk);
-      aS = aS + a.amp * ((yk * (sJm * sIc)) / kk);
+    for (int k = 0; k < nm; ++k) {
+      const double sIm = sI[k][qi - 1], sIc = sI[k][qi], sIp = sI[k][qi + 1];
+      const double sJm = sJ[k][qj - 1], sJc = sJ[k][qj], sJp = sJ[k][qj + 1];
+      const double w = wk[cl][k];
+      aC = aC + w * (sJc * sIc);
+      aE = aE + w * (sJc * sIp);
+      aW = aW + w * (sJc * sIm);
+      aN = aN + w * (sJp * sIc);
+      aS = aS + w * (sJm * sIc);
     }
     const double fE = (aC + aE) / 2.0, fW = (aC + aW) / 2.0;
     const double fN = (aC + aN) / 2.0, fS = (aC + aS) / 2.0;
