@@ -244,13 +244,15 @@ static void finish(const Workspace& w, const Geometry& g, int G, int kind, hipSt
 // d = z = D^-1 r / theta (already done by the caller when `started`), then
 // degree-1 stencil steps ping-ponging z.  Returns the buffer holding z.
 static double* cheb_apply(const double* V, const Workspace& w, const Geometry& g, int degree,
-                          bool init, bool started, hipStream_t s) {
-  if (!started) launch_cheb_start(V, w.r, w.d, w.z[0], w.m, g, init_groups(g), s);
-  for (int k = 1; k < degree; ++k) {
+                          bool init, bool started, hipStream_t s, const double* r = nullptr,
+                          int first_step = 1) {
+  if (!r) r = w.r;
+  if (!started) launch_cheb_start(V, r, w.d, w.z[0], w.m, g, init_groups(g), s);
+  for (int k = first_step; k < degree; ++k) {
     StencilArgs a;
     std::memset(&a, 0, sizeof(a));
     a.V = V;
-    a.r = w.r;
+    a.r = r;
     a.src = w.z[(k - 1) & 1];
     a.zout = w.z[k & 1];
     a.d = w.d;
@@ -458,20 +460,43 @@ static int run_solve(const ens_problem* prob, const Opts& o, int S, const double
         ev_iter.push_back(it);
       }
       finish(w, g, g.groups, F_ALPHA, s);
-      UpdateArgs u;
-      std::memset(&u, 0, sizeof(u));
-      u.V = V;
-      u.r = w.r;
-      u.q = w.q;
-      u.d = w.d;
-      u.z = w.z[0];
-      u.partial = w.partial;
-      u.m = w.m;
-      u.g = g;
-      u.rtol = o.rtol;
-      launch_update(u, cheb, ge, s);
-      finish(w, g, ge, cheb ? F_UPDATE_C : F_UPDATE_J, s, o.rtol);
-      if (cheb) cheb_apply(V, w, g, o.degree, false, true, s);
+      if (cheb && g.dim == 2) {
+        // the residual update fused with the first Chebyshev step; the
+        // residual alternates between two buffers (w.r holds the initial one)
+        double* r_in = (it & 1) ? w.r : w.aux;
+        double* r_out = (it & 1) ? w.aux : w.r;
+        StencilArgs c;
+        std::memset(&c, 0, sizeof(c));
+        c.V = V;
+        c.r = r_in;
+        c.q_in = w.q;
+        c.r_out = r_out;
+        c.d = w.d;
+        c.zout = w.z[1];
+        c.partial = w.partial;
+        c.m = w.m;
+        c.g = g;
+        c.cheb_step = 1;
+        c.cheb_last = (o.degree == 2);
+        launch_stencil<M_CHEB1>(c, s);
+        finish(w, g, g.groups, F_UPDATE_C, s, o.rtol);
+        cheb_apply(V, w, g, o.degree, false, true, s, r_out, 2);
+      } else {
+        UpdateArgs u;
+        std::memset(&u, 0, sizeof(u));
+        u.V = V;
+        u.r = w.r;
+        u.q = w.q;
+        u.d = w.d;
+        u.z = w.z[0];
+        u.partial = w.partial;
+        u.m = w.m;
+        u.g = g;
+        u.rtol = o.rtol;
+        launch_update(u, cheb, ge, s);
+        finish(w, g, ge, cheb ? F_UPDATE_C : F_UPDATE_J, s, o.rtol);
+        if (cheb) cheb_apply(V, w, g, o.degree, false, true, s);
+      }
     }
     if (rc != ENS_OK) break;
     hipError_t e = hipGetLastError();

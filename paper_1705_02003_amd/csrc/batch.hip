@@ -120,7 +120,7 @@ __global__ __launch_bounds__(kNT) void batch_stencil_kernel(BatchArgs a) {
   const double zero2[2] = {0.0, 0.0};
   int cur = -1, cur_js = 0, cur_first = 0, tpp = 1, S = 2, ntiles = 1;
   double* partial = nullptr;
-  double beta[2] = {0.0, 0.0}, aprev[2] = {0.0, 0.0}, acc[2] = {0.0, 0.0};
+  double beta[2] = {0.0, 0.0}, aprev[2] = {0.0, 0.0}, acc[2] = {0.0, 0.0}, acc2[2] = {0.0, 0.0};
   TileView tv = {};
   // rows of a member tile's partials: row r holds its units r, r + G, ...
   auto flush = [&]() {
@@ -183,7 +183,8 @@ __global__ __launch_bounds__(kNT) void batch_stencil_kernel(BatchArgs a) {
         acc[c] = 0.0;
       }
     }
-    stencil_tile<2, M_PCG_J, SYM>(tv, local - js * ntiles, ring, sym, beta, aprev, zero2, zero2, acc);
+    stencil_tile<2, M_PCG_J, SYM>(tv, local - js * ntiles, ring, sym, beta, aprev, zero2, zero2, acc,
+                                  acc2);
   }
   if (cur >= 0) flush();
 }

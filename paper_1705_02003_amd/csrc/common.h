@@ -96,7 +96,11 @@ struct AsmArgs {
   size_t vstride;
 };
 
-enum Mode { M_SPMV = 0, M_PCG_J = 1, M_PCG_Z = 2, M_CHEB = 3 };
+// M_CHEB1: the residual update r -= alpha q fused with the first Chebyshev
+// step (the ring holds z_0 = D^-1 r / theta formed from r, q and the
+// diagonal; r is written to a second buffer, since neighbouring tiles still
+// read the old one)
+enum Mode { M_SPMV = 0, M_PCG_J = 1, M_PCG_Z = 2, M_CHEB = 3, M_CHEB1 = 4 };
 
 struct StencilArgs {
   const double* V;
@@ -108,7 +112,9 @@ struct StencilArgs {
   double* x;           // solution, deferred update (PCG)
   double* d;           // Chebyshev increment
   double* zout;        // Chebyshev output z
-  double* partial;     // [groups][Sp]
+  const double* q_in;  // M_CHEB1: A p of the current step
+  double* r_out;       // M_CHEB1: the updated residual
+  double* partial;     // [groups][Sp]; M_CHEB1: [2][groups][Sp] (r^T z on a last step, r^T r)
   Members m;
   Geometry g;
   int cheb_step;       // Chebyshev step 1..deg-1

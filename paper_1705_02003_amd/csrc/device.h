@@ -248,6 +248,8 @@ struct TileView {
   double* x;
   double* d;
   double* zout;
+  const double* q_in;   // M_CHEB1
+  double* r_out;        // M_CHEB1
   int n, S;        // grid size, ensemble width (row stride of every vector)
   int sw, s0;      // members this tile covers: s0 .. s0 + sw - 1
   int swp;         // member slots per point (tpp * VEC >= sw): the LDS point stride
@@ -268,7 +270,14 @@ struct TileView {
 //   M_PCG_*: store p and q = A p, accumulate p^T q, apply the deferred
 //            x += alpha_prev p_old;
 //   M_CHEB:  one Chebyshev step d = c1 d + c2 D^-1 (r - A z), z += d, and
-//            on the last step accumulate r^T z.
+//            on the last step accumulate r^T z (and do not store d, which no
+//            later step reads);
+//   M_CHEB1: the residual update and the first Chebyshev step in one sweep:
+//            the ring value is z_0 = (r - alpha q) / diag / theta, and per own
+//            point r' = r - alpha q is stored (to r_out), r'^T r' accumulated,
+//            d_1 = c1 z_0 + c2 D^-1 (r' - A z_0), z_1 = z_0 + d_1 stored (and
+//            r'^T z_1 accumulated into acc2 when it is the last step).
+//            `beta` carries alpha of active members (else 0), `aprev` theta.
 //
 // SYM: the matrix is symmetric, so only C, E, N, NE, NW are read; the lower
 // coefficients of row (i, j) are W = E(i-1, j), S = N(i, j-1), SW = NE(i-1,
@@ -282,8 +291,9 @@ __device__ __forceinline__ void stencil_tile(const TileView& a, int tile, double
                                              double* sym,
                                              const double (&beta)[VEC], const double (&aprev)[VEC],
                                              const double (&c1)[VEC], const double (&c2)[VEC],
-                                             double (&acc)[VEC]) {
+                                             double (&acc)[VEC], double (&acc2)[VEC]) {
   constexpr bool PCG = (MODE == M_PCG_J || MODE == M_PCG_Z);
+  constexpr bool DIAG_IN_RING = (MODE == M_PCG_J || MODE == M_CHEB1);   // diagonal loaded with the ring line
   const int t = threadIdx.x;
   const int S = a.S, n = a.n, tpp = a.tpp, sw = a.swp;
   const int lp = t / tpp;
@@ -320,10 +330,15 @@ __device__ __forceinline__ void stencil_tile(const TileView& a, int tile, double
   double nxt_pold[VEC], nxt_v4[VEC], nxt_val[VEC];
 
   // the inputs of a ring value at element e, and the value itself:
-  // M_PCG_J r / diag + beta p_old, M_PCG_Z z + beta p_old, else the source
+  // M_PCG_J r / diag + beta p_old, M_PCG_Z z + beta p_old, M_CHEB1
+  // (r - alpha q) / diag / theta, else the source
   auto fill_load = [&](size_t e, double (&v0)[VEC], double (&v1)[VEC], double (&v2)[VEC]) {
     if constexpr (MODE == M_SPMV || MODE == M_CHEB) {
       ld<VEC>(v0, a.src + e);
+    } else if constexpr (MODE == M_CHEB1) {
+      ld<VEC>(v0, a.r + e);
+      ld<VEC>(v1, a.q_in + e);
+      ld<VEC>(v2, a.V + 4 * slot_stride + e);
     } else if constexpr (MODE == M_PCG_J) {
       ld<VEC>(v0, a.r + e);
       ld<VEC>(v1, a.pold + e);
@@ -333,6 +348,9 @@ __device__ __forceinline__ void stencil_tile(const TileView& a, int tile, double
       ld<VEC>(v1, a.pold + e);
     }
   };
+  // M_CHEB1: the updated residual r - alpha q of member slot c (alpha 0:
+  // unchanged, as in the separate update)
+  auto rnew = [&](double r, double qv, int c) { return beta[c] != 0.0 ? fma(-beta[c], qv, r) : r; };
   auto combine = [&](const double (&v0)[VEC], const double (&v1)[VEC], const double (&v2)[VEC],
                      bool ok, double (&out)[VEC]) {
 #pragma unroll
@@ -340,6 +358,7 @@ __device__ __forceinline__ void stencil_tile(const TileView& a, int tile, double
       double v;
       if constexpr (MODE == M_PCG_J) v = fma(beta[c], v1[c], v0[c] / v2[c]);
       else if constexpr (MODE == M_PCG_Z) v = fma(beta[c], v1[c], v0[c]);
+      else if constexpr (MODE == M_CHEB1) v = (rnew(v0[c], v1[c], c) / v2[c]) / aprev[c];
       else v = v0[c];
       out[c] = ok ? v : 0.0;
     }
@@ -357,8 +376,9 @@ __device__ __forceinline__ void stencil_tile(const TileView& a, int tile, double
     combine(o0, o1, o2, ok, val);
 #pragma unroll
     for (int c = 0; c < VEC; ++c) {
-      rp[c] = PCG ? o1[c] : 0.0;
-      rv4[c] = (MODE == M_PCG_J) ? o2[c] : 0.0;
+      // retained: p_old (PCG) or the updated residual (M_CHEB1), the diagonal
+      rp[c] = PCG ? o1[c] : ((MODE == M_CHEB1) ? rnew(o0[c], o1[c], c) : 0.0);
+      rv4[c] = DIAG_IN_RING ? o2[c] : 0.0;
       line[(lp + 1) * sw + cl + c] = val[c];
       rval[c] = val[c];
     }
@@ -420,7 +440,7 @@ __device__ __forceinline__ void stencil_tile(const TileView& a, int tile, double
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
       if (SYM && k < 4) continue;                 // lower coefficients: from neighbours
-      if (k == 4 && MODE == M_PCG_J) continue;    // the diagonal came with the ring line
+      if (k == 4 && DIAG_IN_RING) continue;       // the diagonal came with the ring line
       ld_stream<VEC>(vk[k], a.V + (size_t)k * slot_stride + e);
     }
     if constexpr (PCG) ld<VEC>(xv, a.x + e);
@@ -454,7 +474,7 @@ __device__ __forceinline__ void stencil_tile(const TileView& a, int tile, double
       }
     }
     put_own(j + 1, j + 1 < j1, o0, o1, o2, nxt_pold, nxt_v4, nxt_val);
-    if constexpr (MODE == M_PCG_J) {
+    if constexpr (DIAG_IN_RING) {
 #pragma unroll
       for (int c = 0; c < VEC; ++c) vk[4][c] = cur_v4[c];
     }
@@ -514,6 +534,22 @@ __device__ __forceinline__ void stencil_tile(const TileView& a, int tile, double
         st<VEC>(a.q + e, q);
         st<VEC>(a.x + e, xv);
       }
+    } else if constexpr (MODE == M_CHEB1) {
+      // d_0 = z_0 (the ring value), r' retained from the ring fill
+      double zn[VEC], dn[VEC];
+#pragma unroll
+      for (int c = 0; c < VEC; ++c) {
+        const double rn = cur_pold[c];
+        dn[c] = c1[c] * cur_val[c] + c2[c] * ((rn - q[c]) / vk[4][c]);
+        zn[c] = cur_val[c] + dn[c];
+        acc[c] = own_s ? fma(rn, rn, acc[c]) : acc[c];
+        if (a.cheb_last) acc2[c] = own_s ? fma(rn, zn[c], acc2[c]) : acc2[c];
+      }
+      if (own_s) {
+        st<VEC>(a.r_out + e, cur_pold);
+        if (!a.cheb_last) st<VEC>(a.d + e, dn);
+        st<VEC>(a.zout + e, zn);
+      }
     } else {  // M_CHEB
       double zn[VEC];
 #pragma unroll
@@ -523,7 +559,7 @@ __device__ __forceinline__ void stencil_tile(const TileView& a, int tile, double
         if (a.cheb_last) acc[c] = own_s ? fma(rr[c], zn[c], acc[c]) : acc[c];
       }
       if (own_s) {
-        st<VEC>(a.d + e, dd);
+        if (!a.cheb_last) st<VEC>(a.d + e, dd);
         st<VEC>(a.zout + e, zn);
       }
     }

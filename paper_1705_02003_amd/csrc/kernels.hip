@@ -159,6 +159,8 @@ __global__ __launch_bounds__(kNT) void stencil_kernel(StencilArgs a) {
   tv.x = a.x;
   tv.d = a.d;
   tv.zout = a.zout;
+  tv.q_in = a.q_in;
+  tv.r_out = a.r_out;
   tv.n = g.n;
   tv.S = g.S;
   tv.tpp = tpp;
@@ -174,7 +176,7 @@ __global__ __launch_bounds__(kNT) void stencil_kernel(StencilArgs a) {
     tv.s0 = js * g.sw;
     tv.sw = min(g.sw, g.S - tv.s0);
     const int sv = tv.s0 + (t % tpp) * VEC;   // member slot (< Sp)
-    double beta[VEC], aprev[VEC], c1[VEC], c2[VEC], acc[VEC];
+    double beta[VEC], aprev[VEC], c1[VEC], c2[VEC], acc[VEC], acc2[VEC];
 #pragma unroll
     for (int c = 0; c < VEC; ++c) {
       beta[c] = 0.0;
@@ -182,18 +184,25 @@ __global__ __launch_bounds__(kNT) void stencil_kernel(StencilArgs a) {
       c1[c] = 0.0;
       c2[c] = 0.0;
       acc[c] = 0.0;
+      acc2[c] = 0.0;
       if constexpr (MODE == M_PCG_J || MODE == M_PCG_Z) {
         beta[c] = a.m.beta[sv + c];
         aprev[c] = a.m.alpha_prev[sv + c];
       }
-      if constexpr (MODE == M_CHEB) {
+      if constexpr (MODE == M_CHEB1) {
+        // alpha of active members, theta
+        beta[c] = a.m.active[sv + c] ? a.m.alpha[sv + c] : 0.0;
+        aprev[c] = a.m.cheb[(size_t)(sv + c) * kChebCoef];
+      }
+      if constexpr (MODE == M_CHEB || MODE == M_CHEB1) {
         c1[c] = a.m.cheb[(size_t)(sv + c) * kChebCoef + 2 * a.cheb_step - 1];
         c2[c] = a.m.cheb[(size_t)(sv + c) * kChebCoef + 2 * a.cheb_step];
       }
     }
     int tile, tstep, tend;
     tile_range(g, tile, tstep, tend);
-    for (; tile < tend; tile += tstep) stencil_tile<VEC, MODE, SYM>(tv, tile, ring, sym, beta, aprev, c1, c2, acc);
+    for (; tile < tend; tile += tstep)
+      stencil_tile<VEC, MODE, SYM>(tv, tile, ring, sym, beta, aprev, c1, c2, acc, acc2);
     if constexpr (MODE == M_PCG_J || MODE == M_PCG_Z) {
       group_reduce<VEC>(acc, tpp, red);
       put_partial<VEC>(a.partial, g.Sp, tpp, acc, tv.s0);
@@ -201,6 +210,15 @@ __global__ __launch_bounds__(kNT) void stencil_kernel(StencilArgs a) {
       if (a.cheb_last) {
         group_reduce<VEC>(acc, tpp, red);
         put_partial<VEC>(a.partial, g.Sp, tpp, acc, tv.s0);
+      }
+    } else if constexpr (MODE == M_CHEB1) {
+      // r^T r into the second partial array (the convergence test), r^T z
+      // into the first when this is the application's last step
+      group_reduce<VEC>(acc, tpp, red);
+      put_partial<VEC>(a.partial + (size_t)gridDim.x * g.Sp, g.Sp, tpp, acc, tv.s0);
+      if (a.cheb_last) {
+        group_reduce<VEC>(acc2, tpp, red);
+        put_partial<VEC>(a.partial, g.Sp, tpp, acc2, tv.s0);
       }
     }
   }
@@ -448,9 +466,11 @@ void launch_assemble(const AsmArgs& a, hipStream_t s) {
 
 template <int MODE>
 void launch_stencil(const StencilArgs& a, hipStream_t s) {
-  if (a.g.dim == 3) {
-    launch_fe3d<MODE>(a, s);
-    return;
+  if constexpr (MODE != M_CHEB1) {   // the 3-D model has no fused first step
+    if (a.g.dim == 3) {
+      launch_fe3d<MODE>(a, s);
+      return;
+    }
   }
   const dim3 grid(a.g.groups), block(kNT);
   if (a.g.vec == 2) {
@@ -465,6 +485,7 @@ template void launch_stencil<M_SPMV>(const StencilArgs&, hipStream_t);
 template void launch_stencil<M_PCG_J>(const StencilArgs&, hipStream_t);
 template void launch_stencil<M_PCG_Z>(const StencilArgs&, hipStream_t);
 template void launch_stencil<M_CHEB>(const StencilArgs&, hipStream_t);
+template void launch_stencil<M_CHEB1>(const StencilArgs&, hipStream_t);
 
 void launch_update(const UpdateArgs& a, bool cheb, int groups, hipStream_t s) {
   if (a.g.vec == 2) {
