@@ -12,7 +12,13 @@ grouping, ensemble assembly, ensemble PCG solves, G(y), refinement.
 Prints one JSON line.  `value` is sample-solves/s of the whole pass (real
 samples / wall time of the step, inputs generated on the device).
 `roofline` is for the dominant kernel, the fused direction-update + SpMV
-kernel, timed live with HIP events on the solver's stream.
+kernel, timed live with HIP events on the solver's stream, beside two
+streaming references measured in the same run (the STREAM triad and the
+kernel's own mix of eight reads and three writes) and the same kernel's
+rate at 1024^2, where no cache holds its working set.  `cpu_baseline` is
+the oracle on the benchmark's first 32 samples in solve order (found by the
+oracle itself, before the GPU run), with the GPU's time on the ensembles
+holding the same samples beside it.
 """
 from __future__ import annotations
 
@@ -35,11 +41,15 @@ HBM_PEAK_GBS = 8000.0
 # values (C, E, N, NE, NW; the other four are the neighbours' by symmetry),
 # r, p_old, x and writes p, q, x: 11 FP64 words (15 with --full-stencil,
 # which reads all nine).  A Jacobi-PCG iteration adds the update kernel's
-# 4 words; a Jacobi-Chebyshev-4 iteration is 47 words (63 with nine).
+# 4 words.  A Jacobi-Chebyshev-4 iteration is 40 words (56 with nine): the
+# fused PCG step (11), the residual update fused with the first Chebyshev
+# step (reads r, q, diagonal and four more matrix values, writes r, d, z:
+# 10), the second step (five matrix values, z, r, d; writes d, z: 10) and
+# the last (the same without writing d: 9).
 FULL_STENCIL = False
 FUSED_BYTES = 11 * 8
 ITER_BYTES = 15 * 8
-CHEB_ITER_BYTES = 47 * 8
+CHEB_ITER_BYTES = 40 * 8
 
 
 def set_byte_model(full: bool) -> None:
@@ -48,7 +58,7 @@ def set_byte_model(full: bool) -> None:
     extra = 4 if full else 0
     FUSED_BYTES = (11 + extra) * 8
     ITER_BYTES = (15 + extra) * 8
-    CHEB_ITER_BYTES = (47 + 4 * extra) * 8
+    CHEB_ITER_BYTES = (40 + 4 * extra) * 8
 
 
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "stencil_pcg_512x512_S32_traffic.json")
@@ -86,24 +96,55 @@ def _oracle_one(y):
         from oracle import pcg, problem
         A, b, diag = problem.assemble(np.asarray(y), N_GRID, 0, AMP)
         t = time.perf_counter()
-        _, I, st, _ = pcg.pcg(A, b, diag, RTOL, 20000)
-        return time.perf_counter() - t, int(I), int(st)
+        x, I, st, _ = pcg.pcg(A, b, diag, RTOL, 20000)
+        return time.perf_counter() - t, int(I), int(st), float(x @ x)
 
 
-def cpu_baseline(procs: int, per_proc: int = 2):
-    """The oracle (per-sample Jacobi-PCG) on the workload's first samples in
-    generation order: the level-1 grid (centre and the 2d axis end points),
-    then level-2 nodes in canonical order, per_proc samples per process
-    (about 15 s of wall time on 16 cores)."""
+def run_order(res):
+    """Ids of the run's real samples in the order the GPU solved them: level
+    by level, ensemble by ensemble (level 1 in generation order, later levels
+    in the surrogate's ascending predicted-iteration order), each sample once."""
+    out, seen, off = [], set(), 0
+    for lvl in res.levels:
+        for g in lvl.groups:
+            for i in g:
+                k = off + int(i)
+                if k not in seen:
+                    seen.add(k)
+                    out.append(k)
+        off += lvl.n_samples
+    return out
+
+
+def cpu_baseline(procs: int, count: int, S: int):
+    """The oracle (per-sample FP64 Jacobi-PCG, one process per core, BLAS on
+    one thread) on the benchmark's first `count` samples in solve order,
+    found by the oracle itself before the GPU is touched (forked workers):
+    the level-1 grid is solved, the oracle's refinement of it on G = ||u||^2
+    gives level 2, and the oracle's surrogate of the level-1 counts orders
+    level 2 into ensembles of S; the first samples of that order follow."""
+    import numpy as np
     from oracle import sparse_grid as sg
-    first = [sg.coords(nd) for nd in sg.full_grid(D, 1)]
-    first += [sg.coords(nd) for nd in sg.full_grid(D, 2) if sg.total_level(nd) == 2]
-    ys = first[:procs * per_proc]
     ctx = mp.get_context("fork")          # no GPU state exists yet in this process
+    lvl1 = sg.full_grid(D, 1)
     t0 = time.perf_counter()
     with ctx.Pool(procs) as pool:
-        out = pool.map(_oracle_one, ys)
+        out1 = pool.map(_oracle_one, [list(sg.coords(nd)) for nd in lvl1])
+        print(f"[bench] oracle: level 1 ({len(lvl1)} samples) in {time.perf_counter() - t0:.1f} s",
+              flush=True)
+        lvl2 = sg.refine(lvl1, [o[3] for o in out1], 1, 1e-3, 1024)
+        groups, _ = sg.group_samples(lvl1, [float(o[1]) for o in out1],
+                                     np.array([sg.coords(nd) for nd in lvl2]), S)
+        order = []
+        for g in groups:
+            for i in g:
+                if i not in order:
+                    order.append(i)
+        more = [lvl2[i] for i in order[:max(0, count - len(lvl1))]]
+        out2 = pool.map(_oracle_one, [list(sg.coords(nd)) for nd in more])
     wall = time.perf_counter() - t0
+    out = out1 + out2
+    ys = np.array([sg.coords(nd) for nd in lvl1 + more])
     its = [o[1] for o in out]
     solve_s = sum(o[0] for o in out)
     return {
@@ -112,10 +153,39 @@ def cpu_baseline(procs: int, per_proc: int = 2):
         "cores": procs,
         "kind": "oracle",
         "ms_per_iteration": round(1e3 * solve_s / sum(its), 3),
-        "sample": (f"{len(ys)} samples (level-1 grid then level-2 nodes, generation order), "
-                   f"FP64 scipy Jacobi-PCG solves on {procs} processes at {N_GRID}x{N_GRID}, "
-                   f"rtol {RTOL}; iterations {min(its)}-{max(its)}; wall {wall:.1f} s"),
-    }
+        "sample": (f"the benchmark's first {len(ys)} samples in its solve order (the level-1 grid, "
+                   f"then level-2 nodes in surrogate order, both derived by the oracle), FP64 "
+                   f"scipy Jacobi-PCG solves on {procs} processes at {N_GRID}x{N_GRID}, rtol {RTOL}; "
+                   f"iterations {min(its)}-{max(its)}; wall {wall:.1f} s"),
+    }, ys
+
+
+def gpu_same_samples(res, ids, S, opts):
+    """GPU time of the ensembles that hold the given samples, solved as the
+    run solved them (assembly included): the GPU side of the CPU baseline's
+    comparison on the same samples."""
+    import torch
+    from paper_1705_02003_amd import ensemble as E
+    want = set(ids)
+    prob = E.Problem(N_GRID, D, 0, AMP)
+    ws = E.workspace(prob, S, opts)
+    jobs, off = [], 0
+    for lvl in res.levels:
+        for g in lvl.groups:
+            ks = [off + int(i) for i in g]
+            if want & set(ks):
+                jobs.append(ks)
+        off += lvl.n_samples
+    covered = len(set(k for ks in jobs for k in ks))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for ks in jobs:
+        V, b = E.assemble(prob, res.y[ks])
+        E.solve(prob, V, b, opts, ws=ws)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    return {"value": round(covered / dt, 3), "unit": "sample-solves/s", "ensembles": len(jobs),
+            "samples_solved": covered, "seconds": round(dt, 3)}
 
 
 # ------------------------------------------------------------ GPU parts
@@ -163,29 +233,71 @@ def s1_comparison(res, S, opts, n_groups=2):
             "iters_S1": [int(min(its1)), int(max(its1))]}
 
 
-def measure_triad(gib: int = 4, reps: int = 5) -> dict:
-    """Achievable HBM bandwidth: the library's STREAM triad (c = a + s b) on
-    three `gib`-GiB FP64 arrays, best of `reps` timed launches."""
+def measure_streams(gib: float = 1.0, reps: int = 5) -> dict:
+    """Achievable HBM bandwidth: the library's STREAM triad (c = a + s b) and
+    the solver step's mix of eight reads and three writes (ens_stream_mix),
+    on arrays of `gib` GiB each, carved from one buffer and offset by 4 KiB
+    (as the solver's matrix slots and vectors are); best of `reps` launches."""
     import torch
     from paper_1705_02003_amd import ensemble as E
-    n = (gib << 30) // 8
-    a = torch.full((n,), 1.0, dtype=torch.float64, device="cuda")
-    b = torch.full((n,), 2.0, dtype=torch.float64, device="cuda")
-    c = torch.empty_like(a)
-    E.stream_triad(a, b, c, 0.5)
-    torch.cuda.synchronize()
-    best = None
-    for _ in range(reps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        E.stream_triad(a, b, c, 0.5)
-        e1.record()
+    n = int(gib * (1 << 30)) // 8
+    stride = ((n + 31) // 32) * 32 + 512
+    buf = torch.empty(14 * stride, dtype=torch.float64, device="cuda")
+    buf.fill_(1.0)
+    src, dst = buf[:8 * stride], buf[8 * stride:]
+
+    def best(fn):
+        fn()
         torch.cuda.synchronize()
-        dt = e0.elapsed_time(e1) * 1e-3
-        best = dt if best is None else min(best, dt)
-    del a, b, c
+        out = None
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            dt = e0.elapsed_time(e1) * 1e-3
+            out = dt if out is None else min(out, dt)
+        return out
+
+    a, b, c = buf[:n], buf[stride:stride + n], buf[2 * stride:2 * stride + n]
+    t_triad = best(lambda: E.stream_triad(a, b, c, 0.5))
+    t_mix = best(lambda: E.stream_mix(src, dst, stride, n, 8, 3))
+    del buf
     torch.cuda.empty_cache()
-    return {"GBs": round(3 * n * 8 / best / 1e9, 1), "array_GiB": gib, "kernel": "ens_stream_triad"}
+    return {"triad_GBs": round(3 * n * 8 / t_triad / 1e9, 1),
+            "mix_8r3w_GBs": round(11 * n * 8 / t_mix / 1e9, 1),
+            "array_GiB": gib, "offset_bytes": (stride - n) * 8,
+            "kernels": "ens_stream_triad, ens_stream_mix(8 reads, 3 writes)"}
+
+
+def measure_triad(gib: int = 4, reps: int = 5) -> dict:
+    """The triad alone (kept for --mode kernel): see measure_streams."""
+    r = measure_streams(gib, reps)
+    return {"GBs": r["triad_GBs"], "array_GiB": gib, "kernel": "ens_stream_triad"}
+
+
+def fused_kernel_rate(n: int, S: int, iters: int = 40) -> dict:
+    """The fused Jacobi step (direction update + nine-point product) on an
+    n x n grid at width S with the benchmark's coefficient model, timed with
+    HIP events over a fixed-iteration solve: at 1024^2 and S = 32 its working
+    set (about 3.8 GB) is far beyond the 256 MB Infinity Cache, so this rate
+    is an HBM rate."""
+    import torch
+    import workloads
+    from paper_1705_02003_amd import ensemble as E
+    prob = E.Problem(n, D, 0, AMP)
+    V, b = E.assemble(prob, workloads.uniform_samples(1, S, D))
+    opts = E.SolverOptions(rtol=0.0, max_iter=iters, time_spmv=True, full_stencil=FULL_STENCIL)
+    ws = E.workspace(prob, S, opts)
+    E.solve(prob, V, b, opts, ws=ws)
+    r = E.solve(prob, V, b, opts, ws=ws)
+    us = 1e3 * r.stats["spmv_ms"] / max(1, r.stats["spmv_timed"])
+    gbs = prob.rows * S * FUSED_BYTES / (us * 1e-6) / 1e9
+    del V, b, ws
+    torch.cuda.empty_cache()
+    return {"grid": f"{n}x{n}", "S": S, "avg_launch_us": round(us, 2), "achieved": round(gbs, 1),
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "timed_launches": r.stats["spmv_timed"]}
 
 
 def device_info() -> dict:
@@ -359,18 +471,28 @@ def grouping_mode(args) -> int:
 
 
 def kernel_mode(args) -> int:
-    """One S-wide ensemble of the workload's coefficient model, solved for a
-    fixed number of iterations (rtol 0) in the default launch configuration,
-    then a plain 1 GiB device-to-device copy whose counter readings calibrate
-    FETCH_SIZE / WRITE_SIZE.  Prints one JSON line with the measured times."""
+    """One S-wide ensemble solved for a fixed number of iterations (rtol 0) in
+    the default launch configuration, then a plain 1 GiB device-to-device
+    copy whose counter readings calibrate FETCH_SIZE / WRITE_SIZE.  Jacobi:
+    the benchmark's coefficient model on the --grid (default 512^2) grid;
+    --precond chebyshev: the Chebyshev workload's (d = 8, eps down to 1e-3),
+    degree 4.  Prints one JSON line with the measured times."""
     import torch
     import workloads
     from paper_1705_02003_amd import ensemble as E
     torch.cuda.set_device(0)
-    prob = E.Problem(N_GRID, D, 0, AMP)
-    y = torch.tensor(workloads.uniform_samples(1, args.S, D), dtype=torch.float64, device="cuda")
+    n = args.grid
+    if args.precond == "chebyshev":
+        w = workloads.CHEB_1024
+        prob = E.Problem(n, w.d, w.eps_model, w.amp)
+        y = workloads.uniform_samples(w.seed, args.S, w.d)
+        words = CHEB_ITER_BYTES // 8
+    else:
+        prob = E.Problem(n, D, 0, AMP)
+        y = workloads.uniform_samples(1, args.S, D)
+        words = ITER_BYTES // 8
     V, b = E.assemble(prob, y)
-    opts = E.SolverOptions(rtol=0.0, max_iter=args.iters, time_spmv=True,
+    opts = E.SolverOptions(precond=args.precond, rtol=0.0, max_iter=args.iters, time_spmv=True,
                            full_stencil=FULL_STENCIL)
     ws = E.workspace(prob, args.S, opts)
     E.solve(prob, V, b, opts, ws=ws)
@@ -383,7 +505,7 @@ def kernel_mode(args) -> int:
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
-    # achievable bandwidth: a plain device copy and the library's triad
+    # achievable bandwidth: a plain device copy and the library's streams
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     reps = 10
     e0.record()
@@ -394,17 +516,19 @@ def kernel_mode(args) -> int:
     copy_bytes = src.numel() * 8
     copy_gbs = 2 * copy_bytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del src, dst
-    triad_gbs = measure_triad()["GBs"]
+    streams = measure_streams()
     us = 1e3 * r.stats["spmv_ms"] / max(1, r.stats["spmv_timed"])
     rows = prob.rows * args.S
-    print(json.dumps({"mode": "kernel", "S": args.S, "iterations": args.iters,
+    print(json.dumps({"mode": "kernel", "grid": f"{n}x{n}", "precond": args.precond, "S": args.S,
+                      "iterations": args.iters,
                       "fused_avg_us": round(us, 2),
                       "fused_alg_GBs": round(rows * FUSED_BYTES / (us * 1e-6) / 1e9, 1),
                       "iteration_us": round(1e6 * dt / args.iters, 2),
-                      "iteration_alg_GBs": round(rows * ITER_BYTES * args.iters / dt / 1e9, 1),
+                      "iteration_words_per_member_row": words,
+                      "iteration_alg_GBs": round(rows * words * 8 * args.iters / dt / 1e9, 1),
                       "fused_alg_bytes": rows * FUSED_BYTES,
                       "copy_bytes_each_way": copy_bytes,
-                      "stream_copy_GBs": round(copy_gbs, 1), "stream_triad_GBs": round(triad_gbs, 1),
+                      "stream_copy_GBs": round(copy_gbs, 1), **streams,
                       "tile_lines": r.stats["tile_lines"], "groups": r.stats["spmv_groups"]}),
           flush=True)
     return 0
@@ -483,7 +607,7 @@ def cheb_mode(args) -> int:
     ys = workloads.uniform_samples(w.seed, w.n_samples, w.d)
     S = args.S
     ng = (w.n_samples + S - 1) // S
-    k = args.ensembles or 4
+    k = ng if args.all_ensembles else (args.ensembles or 4)
     sel = sorted(set(int(v) for v in np.linspace(0, ng - 1, k).round()))
     opts = E.SolverOptions(precond="chebyshev", rtol=w.rtol, max_iter=w.max_iter, time_spmv=True,
                            full_stencil=FULL_STENCIL)
@@ -503,6 +627,30 @@ def cheb_mode(args) -> int:
            "fused_avg_us": round(us, 2),
            "fused_alg_GBs": round(rows * FUSED_BYTES / (us * 1e-6) / 1e9, 1),
            "iteration_alg_GBs": round(sum(res.ens_iters) * rows * CHEB_ITER_BYTES / res.solve_seconds / 1e9, 1)}
+    if len(real) == w.n_samples:
+        # Every sample solved: the cost of other groupings of the same samples
+        # follows from the recorded counts (a member's count does not depend
+        # on its companions), eqs. (Rl), (R); their time is predicted from the
+        # measured time per ensemble iteration.
+        from paper_1705_02003_amd import grouping as G
+        its_all = res.iters
+        per_iter = res.solve_seconds / float(sum(res.ens_iters))
+        hind = E.param_indicator_samples(prob, ys)
+        orders = {"surrogate": None,
+                  "random": list(np.random.default_rng(w.seed).permutation(w.n_samples)),
+                  "natural": list(range(w.n_samples)),
+                  "param": sorted(range(w.n_samples), key=lambda i: (hind[i], i)),
+                  "its": sorted(range(w.n_samples), key=lambda i: (its_all[i], i))}
+        table = {}
+        for name, order in orders.items():
+            groups = res.groups if name == "surrogate" else G.chunk(order, S)
+            tot = G.ensemble_iteration_total(groups, its_all)
+            table[name] = {"sum_ensemble_iters": tot, "R": round(G.cost_ratio(groups, its_all, S), 4),
+                           "seconds": round(res.solve_seconds, 2) if name == "surrogate"
+                           else round(tot * per_iter, 2)}
+        out["grouping"] = table
+        out["grouping_note"] = ("seconds measured for the surrogate grouping (the solved one); for "
+                                "the others Sum K_e times the measured seconds per ensemble iteration")
     print(json.dumps(out), flush=True)
     return 0
 
@@ -684,6 +832,9 @@ def main() -> int:
     ap.add_argument("--budget", type=int, default=1024)
     ap.add_argument("--cpu-procs", type=int, default=0, help="0: min(16, cpu count)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-samples", type=int, default=32,
+                    help="samples the oracle solves for the CPU baseline (the run's first ones; "
+                         "about 30 s on 16 cores at 32)")
     ap.add_argument("--no-s1", action="store_true")
     ap.add_argument("--mode", choices=["full", "kernel", "adjoint", "cheb", "batch", "su", "grouping",
                                        "table", "fe3d"],
@@ -691,6 +842,9 @@ def main() -> int:
                     help="kernel: a fixed-iteration solve of one ensemble plus a 1 GiB "
                          "copy, for hardware-counter runs")
     ap.add_argument("--iters", type=int, default=100, help="iterations in --mode kernel")
+    ap.add_argument("--grid", type=int, default=N_GRID, help="grid size n in --mode kernel")
+    ap.add_argument("--precond", choices=["jacobi", "chebyshev"], default="jacobi",
+                    help="preconditioner in --mode kernel")
     ap.add_argument("--S-list", default="4,8,16,32,64", help="ensemble widths in --mode table")
     ap.add_argument("--resident-gb", type=float, default=0.0,
                     help="--mode batch: device memory the draw may keep resident (0: 80 %% of HBM)")
@@ -708,6 +862,8 @@ def main() -> int:
                     help="--mode batch: also solve the ensembles one after another")
     ap.add_argument("--ensembles", type=int, default=0,
                     help="ensembles to solve in --mode adjoint / cheb (0: the mode's default)")
+    ap.add_argument("--all-ensembles", action="store_true",
+                    help="--mode cheb: solve every ensemble (all 4096 samples) and compare groupings")
     args = ap.parse_args()
     set_byte_model(args.full_stencil)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -733,10 +889,10 @@ def main() -> int:
     if args.mode == "fe3d":
         return fe3d_mode(args)
 
-    cpu = None
+    cpu, cpu_ys = None, None
     if not args.no_cpu_baseline:
         procs = args.cpu_procs or min(16, os.cpu_count() or 1)
-        cpu = cpu_baseline(procs)
+        cpu, cpu_ys = cpu_baseline(procs, args.cpu_samples, args.S)
         print(f"[bench] cpu baseline: {cpu['value']} sample-solves/s on {procs} cores", flush=True)
 
     import numpy as np
@@ -783,6 +939,15 @@ def main() -> int:
     costs16 = uq.grouping_costs(res, 16) if args.S != 16 else None
     asm_s = res.assemble_ms / 1e3
 
+    # the GPU on the ensembles holding the oracle's samples
+    if cpu is not None:
+        pos = {tuple(y): k for k, y in enumerate(res.y)}
+        ids = [pos[tuple(y)] for y in cpu_ys if tuple(y) in pos]
+        cpu["same_samples_as_gpu_run_start"] = sorted(ids) == sorted(run_order(res)[:len(cpu_ys)])
+        cpu["gpu_same_samples"] = gpu_same_samples(res, ids, args.S, opts)
+        print(f"[bench] GPU on the oracle's samples: {cpu['gpu_same_samples']['value']} "
+              f"sample-solves/s", flush=True)
+
     out = {
         "metric": "sample-solves/s + HBM GB/s, ensemble PCG S=32 vs S=1, 512² grid, rtol 1e-8",
         "value": round(value, 3),
@@ -807,6 +972,9 @@ def main() -> int:
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "stencil_kernel<2, M_PCG_J> (fused direction update + SpMV)",
                      "bytes_per_member_row": FUSED_BYTES,
+                     "bytes_note": ("the method's own reads: five stored matrix values per row "
+                                    "(the other four are the neighbours' by symmetry), r, p_old, "
+                                    "x; writes p, q, x"),
                      "timed_launches": launches,
                      "avg_launch_us": round(1e3 * spmv_ms / max(1, launches), 2)},
         "gbps_iteration_alg": round(member_iter_rows * ITER_BYTES / solve_s / 1e9, 1),
@@ -825,10 +993,26 @@ def main() -> int:
     if traffic and spmv_ms > 0:
         # measured HBM bytes per launch over the same launches' average time
         out["roofline"]["measured_GBs"] = round(traffic / 1e9 / (spmv_ms / launches / 1e3), 1)
-    triad = measure_triad()
-    out["roofline"]["stream_triad_GBs"] = triad["GBs"]
+    if achieved and not FULL_STENCIL:
+        # the nine-stored-values byte count of a plain (non-symmetric) read:
+        # 15 words; it exceeds 8 TB/s at this kernel's time, which shows the
+        # kernel does not move those bytes
+        a9 = achieved * 15 / 11
+        out["roofline"]["nine_value_model"] = {
+            "bytes_per_member_row": 120, "achieved": round(a9, 1),
+            "frac": round(a9 / HBM_PEAK_GBS, 4)}
+    streams = measure_streams()
+    out["roofline"]["stream_triad_GBs"] = streams["triad_GBs"]
+    out["roofline"]["stream_mix_8r3w_GBs"] = streams["mix_8r3w_GBs"]
     if achieved:
-        out["roofline"]["frac_of_stream_triad"] = round(achieved / triad["GBs"], 4)
+        out["roofline"]["frac_of_stream_triad"] = round(achieved / streams["triad_GBs"], 4)
+        out["roofline"]["frac_of_stream_mix"] = round(achieved / streams["mix_8r3w_GBs"], 4)
+    # At 512^2 the benchmark's vectors (67 MB each) partly stay in the 256 MB
+    # Infinity Cache between kernels, so the figure above is L2-miss
+    # bandwidth (HBM plus Infinity Cache); the same kernel at 1024^2 has a
+    # working set far beyond that cache: an HBM-only rate.
+    out["roofline"]["memory"] = "L2 misses: HBM + Infinity Cache"
+    out["roofline"]["hbm_only_1024"] = fused_kernel_rate(1024, args.S)
     out["device"] = device_info()
     print(json.dumps(out), flush=True)
     return 0

@@ -441,6 +441,18 @@ int ens_version(void);          /* library ABI version (major * 100 + minor)  */
 int ens_stream_triad(const double* a_dev, const double* b_dev, double* c_dev, double scalar,
                      size_t n, void* stream);
 
+/* STREAM-style streaming with the read/write mix of a solver kernel: for
+ * e < n, dst[w * stride + e] = sum_{k < nread} src[k * stride + e] for every
+ * w < nwrite.  The arrays sit `stride` doubles apart (use a stride a few KiB
+ * past n, as ens_matrix_slot_stride does, so the streams are not a large
+ * power of two apart).  Supported (nread, nwrite): (8, 3) -- the fused
+ * solver step's eight reads and three writes per member-row -- (3, 1),
+ * (2, 1) and (1, 1).  Asynchronous on `stream`.  Errors: ENS_EINVAL for a
+ * NULL or misaligned pointer, odd or zero n, or stride < n; ENS_ENOTSUP for
+ * another mix. */
+int ens_stream_mix(const double* src_dev, double* dst_dev, size_t stride, size_t n,
+                   int32_t nread, int32_t nwrite, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

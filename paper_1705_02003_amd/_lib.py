@@ -78,6 +78,7 @@ SIGNATURES = {
     "ens_last_hip_error": (C.c_int, []),
     "ens_version": (C.c_int, []),
     "ens_stream_triad": (C.c_int, [vp, vp, vp, f64, sz, vp]),
+    "ens_stream_mix": (C.c_int, [vp, vp, sz, sz, i32, i32, vp]),
 }
 
 _lib = None

@@ -607,6 +607,16 @@ int ens_stream_triad(const double* a_dev, const double* b_dev, double* c_dev, do
   return ENS_OK;
 }
 
+int ens_stream_mix(const double* src_dev, double* dst_dev, size_t stride, size_t n, int32_t nread,
+                   int32_t nwrite, void* stream) {
+  if (!src_dev || !dst_dev || n < 2 || (n & 1) || stride < n || (stride & 1)) return ENS_EINVAL;
+  if ((((uintptr_t)src_dev | (uintptr_t)dst_dev) & 15) != 0) return ENS_EINVAL;
+  const int rc = launch_stream_mix(src_dev, dst_dev, stride, n, nread, nwrite, (hipStream_t)stream);
+  if (rc) return rc;
+  HIPCHECK(hipGetLastError());
+  return ENS_OK;
+}
+
 int ens_last_hip_error(void) { return g_last_hip_error; }
 
 const char* ens_strerror(int code) {

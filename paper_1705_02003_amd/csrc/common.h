@@ -191,6 +191,8 @@ void launch_cheb_start(const double* V, const double* r, double* d, double* z, c
 void launch_final(double* x, const double* p0, const double* p1, const Members& m,
                   const Geometry& g, int groups, hipStream_t s);
 void launch_triad(const double* a, const double* b, double* c, double s, size_t n, hipStream_t st);
+int launch_stream_mix(const double* src, double* dst, size_t stride, size_t n, int nread, int nwrite,
+                      hipStream_t st);
 void launch_dot(const double* x, const double* y, int y_bcast, double* partial, const Geometry& g,
                 int groups, hipStream_t s);
 void launch_finish(const FinishArgs& a, hipStream_t s);

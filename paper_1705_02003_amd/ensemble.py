@@ -456,3 +456,15 @@ def stream_triad(a: torch.Tensor, b: torch.Tensor, c: torch.Tensor, scalar: floa
         raise ValueError("a, b, c must have the same number of elements")
     L.check(L.lib().ens_stream_triad(_p(a), _p(b), _p(c), float(scalar), a.numel(),
                                      _stream(a.device)), "ens_stream_triad")
+
+
+def stream_mix(src: torch.Tensor, dst: torch.Tensor, stride: int, n: int, nread: int,
+               nwrite: int) -> None:
+    """dst[w * stride + e] = sum_k src[k * stride + e] (ens_stream_mix);
+    asynchronous."""
+    _require_cuda(src, "src")
+    _require_cuda(dst, "dst")
+    if src.numel() < (nread - 1) * stride + n or dst.numel() < (nwrite - 1) * stride + n:
+        raise ValueError("src / dst too small for the requested streams")
+    L.check(L.lib().ens_stream_mix(_p(src), _p(dst), int(stride), int(n), int(nread), int(nwrite),
+                                   _stream(src.device)), "ens_stream_mix")

@@ -232,6 +232,12 @@ def test_layout_and_new_entry_points_without_gpu(L):
     assert lib.ens_stream_triad(a, C.c_void_p(4104), a, 1.0, 8, None) == L.ENS_EINVAL
     assert lib.ens_stream_triad(a, a, a, 1.0, 0, None) == L.ENS_EINVAL
     assert lib.ens_stream_triad(a, a, a, float("nan"), 8, None) == L.ENS_EINVAL
+    # stream mix: odd or zero n, stride below n, misaligned, an unsupported mix
+    assert lib.ens_stream_mix(a, a, 16, 7, 8, 3, None) == L.ENS_EINVAL
+    assert lib.ens_stream_mix(a, a, 16, 0, 8, 3, None) == L.ENS_EINVAL
+    assert lib.ens_stream_mix(a, a, 8, 16, 8, 3, None) == L.ENS_EINVAL
+    assert lib.ens_stream_mix(C.c_void_p(4104), a, 16, 16, 8, 3, None) == L.ENS_EINVAL
+    assert lib.ens_stream_mix(a, a, 16, 16, 4, 4, None) == L.ENS_ENOTSUP
     # batch: no items, too many items, a bad width, a too-small item workspace
     bws = C.c_void_p(4096)
     nb = lib.ens_batch_workspace_bytes(1)

@@ -418,3 +418,22 @@ def test_stream_triad_rejects_bad_arguments():
         ens.stream_triad(a[1:], a[1:], a[1:], 1.0)        # 8-byte aligned only
     with pytest.raises(L.EnsError):
         ens.stream_triad(a, a, a, float("inf"))
+
+
+@pytest.mark.parametrize("nread,nwrite,n", [(8, 3, 4098), (2, 1, 2), (3, 1, 1000), (1, 1, 64)])
+def test_stream_mix(nread, nwrite, n):
+    """dst_w = src_0 + src_1 + ... (summed in that order) for every output
+    stream; strides a few KiB past n."""
+    ens = E()
+    stride = ((n + 31) // 32) * 32 + 512
+    g = torch.Generator(device="cpu").manual_seed(n + nread)
+    src = torch.randn(nread * stride, generator=g, dtype=torch.float64).cuda()
+    dst = torch.full((nwrite * stride,), float("nan"), dtype=torch.float64, device="cuda")
+    ens.stream_mix(src, dst, stride, n, nread, nwrite)
+    torch.cuda.synchronize()
+    ref = torch.zeros(n, dtype=torch.float64, device="cuda")
+    for k in range(nread):
+        ref = ref + src[k * stride:k * stride + n]
+    for w in range(nwrite):
+        assert torch.equal(dst[w * stride:w * stride + n], ref)
+        assert torch.isnan(dst[w * stride + n:(w + 1) * stride]).all() if w + 1 < nwrite else True
