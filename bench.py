@@ -381,7 +381,9 @@ def table_mode(args) -> int:
 
     --dim 3: the same for the paper's own 3-D test problem (32^3 trilinear
     cells, d = 4, the paper's Test 1 settings: tau 1e-3, at most 2000 samples,
-    up to 8 levels, solver tolerance 1e-7), SU(S) from S copies of y = 0."""
+    up to 8 levels, solver tolerance 1e-7), SU(S) from S copies of y = 0;
+    with --test 2 the paper's Test 2 (a_hat(y) in {1, 100, 10} banded by
+    |y|, the same settings; Table 3's analogue)."""
     import numpy as np
     import torch
     import workloads
@@ -390,12 +392,12 @@ def table_mode(args) -> int:
     torch.cuda.set_device(0)
     S_list = tuple(int(v) for v in args.S_list.split(","))
     if args.dim == 3:
-        w = workloads.FE3D_32
-        prob = E.Problem(w.n, w.d, dim=3)
+        w = workloads.FE3D_32 if args.test == 1 else workloads.FE3D_32_TEST2
+        prob = E.Problem(w.n, w.d, w.eps_model, dim=3)
         opts = E.SolverOptions(rtol=w.rtol, max_iter=w.max_iter, full_stencil=FULL_STENCIL)
         res = uq.adaptive(prob, args.S, budget=2000, max_level=8, tau_rel=1e-3,
                           strategy="surrogate", opts=opts, perm_seed=1)
-        y0, workload = np.zeros(w.d), "adaptive-sg-fe3d-32cube-d4"
+        y0, workload = np.zeros(w.d), "adaptive-sg-" + w.name
     else:
         prob = E.Problem(N_GRID, D, 0, AMP)
         opts = E.SolverOptions(rtol=RTOL, max_iter=20000, full_stencil=FULL_STENCIL)
@@ -611,7 +613,11 @@ def cheb_mode(args) -> int:
     sel = sorted(set(int(v) for v in np.linspace(0, ng - 1, k).round()))
     opts = E.SolverOptions(precond="chebyshev", rtol=w.rtol, max_iter=w.max_iter, time_spmv=True,
                            full_stencil=FULL_STENCIL)
-    res = uq.nonadaptive(prob, S, ys, 2, opts, solve_groups=sel)
+    def progress(done, total):
+        if done % 8 == 0 or done == total:
+            print(f"[bench] {done}/{total} ensembles solved", flush=True)
+
+    res = uq.nonadaptive(prob, S, ys, 2, opts, solve_groups=sel, progress=progress)
     solved = [i for g in res.groups[sel] for i in g]
     real = sorted(set(solved))
     its = res.iters[real]
@@ -856,6 +862,9 @@ def main() -> int:
                          "else 1)")
     ap.add_argument("--dim", type=int, default=2, choices=(2, 3),
                     help="--mode table: the 2-D benchmark problem or the 3-D test problem")
+    ap.add_argument("--test", type=int, default=1, choices=(1, 2),
+                    help="--mode table --dim 3: the paper's Test 1 (a_hat = 1) or Test 2 "
+                         "(a_hat banded by |y|)")
     ap.add_argument("--full-stencil", action="store_true",
                     help="read all nine matrix values per row (no symmetric reuse)")
     ap.add_argument("--sequential", action="store_true",

@@ -90,17 +90,22 @@ extern "C" {
  *   a(x, y) = a_min + a_hat exp(sum_{k<d} sqrt(lambda_k) b_k(x) y'_k),
  * (lambda_k, b_k) the d largest eigenpairs of the covariance
  * sigma_0 exp(-|x - x'|_1 / delta), sigma_0 = sqrt(300), delta = 1/4, with
- * a_min = 0.1, a_hat = 1, a_y = a_z = 1; a is taken at each cube's centre.
+ * a_min = 0.1, a_y = a_z = 1; a is taken at each cube's centre.  a_hat:
+ * eps_model 0 = the paper's Test 1, a_hat = 1; eps_model 1 = its Test 2
+ * (Section 4, Test 2 equation), a_hat(y') = 1, 100 or 10 as |y'|_2 lies
+ * below sqrt(3)/4, in [sqrt(3)/4, sqrt(3)/2), or at or above sqrt(3)/2,
+ * decided on sum_k y'_k^2 (rounded products and sums, in index order)
+ * against 3/16 and 3/4.
  * The eigenpairs are products of 1-D ones (cos / sin about 1/2, frequencies
  * from the exponential kernel's transcendental equations), ordered by
  * decreasing lambda, ties by their 1-D mode indices (x, y, z).
  * N_r = n^3 rows (x fastest), 27 matrix slots 9 (dz+1) + 3 (dy+1) + (dx+1)
- * (13 = diagonal); eps_model and amp must be 0, 1 <= d <= 16.  The batched
- * solver takes the 2-D model only. */
+ * (13 = diagonal); eps_model 0 or 1 (the a_hat above), amp 0, 1 <= d <= 16.
+ * The batched solver takes the 2-D model only. */
 typedef struct {
   int32_t n;          /* interior points per dimension, 2 <= n            */
   int32_t d;          /* parameters per member, 2 <= d <= 16 (3-D: 1..16) */
-  int32_t eps_model;  /* 0 or 1 (3-D: 0)                                   */
+  int32_t eps_model;  /* 0 or 1 (3-D: 0 Test 1, 1 Test 2)                  */
   int32_t dim;        /* 0 or 2: the 2-D model; 3: the 3-D model          */
   double amp;         /* amplitude of the a(x) modes (finite, |amp| < 1; 3-D: 0) */
 } ens_problem;

@@ -11,7 +11,13 @@ cov(x, x') = sigma_0 exp(-||x - x'||_1 / delta).  Section 4: sigma_0 =
 sqrt(300), delta = 1/4, 32^3 cells, trilinear elements, N = 4.
 
 Readings (the paper leaves them open):
-  * a_min = 0.1, a_hat = 1, a_y = a_z = 1;
+  * a_min = 0.1, a_y = a_z = 1; a_hat = 1 (Test 1), or Test 2's a_hat(y)
+    (Section 4, Test 2 equation): 1 for r(y) < d/4, 100 for
+    d/4 <= r(y) < d/2, 10 for r(y) >= d/2, with d = sqrt(3) and
+    r(y) = ||y||_2 -- decided on r^2 = sum_i y_i^2 (products and sums each
+    rounded, in index order) against the exact d^2/16 = 3/16 and
+    d^2/4 = 3/4, so sparse-grid nodes on a band edge (dyadic coordinates,
+    exact squares) fall as the inequalities say;
   * a is evaluated at each element's centroid and held constant on the
     element; the element matrices are then integrated exactly;
   * f = 1 (the load vector entry of an interior node is h^3);
@@ -89,9 +95,27 @@ def kl_3d(N: int):
     return [(math.sqrt(lam), idx) for lam, idx in terms[:N]], m1
 
 
-def element_coefficients(y, m: int) -> np.ndarray:
+def a_hat(y, test: int = 1) -> float:
+    """The factor a_hat of eq. (diff-coeff): 1 in Test 1; in Test 2 the
+    banded value of the Test 2 equation by r(y) (the real part of a complex
+    y: a_hat is piecewise constant, so its complex-step derivative is 0)."""
+    if test == 1:
+        return A_HAT
+    r2 = 0.0
+    for v in np.real(np.asarray(y)).tolist():
+        r2 = r2 + v * v
+    if r2 < 3.0 / 16.0:
+        return 1.0
+    if r2 < 3.0 / 4.0:
+        return 100.0
+    return 10.0
+
+
+def element_coefficients(y, m: int, test: int = 1) -> np.ndarray:
     """a at the centroid of every cell, shape (m+1, m+1, m+1) indexed [ez, ey, ex]
-    (complex y gives complex a, for complex-step derivatives)."""
+    (complex y gives complex a, for complex-step derivatives); `test` 1 or 2
+    selects a_hat."""
+    ah = a_hat(y, test)
     y = np.asarray(y)
     if not np.iscomplexobj(y):
         y = y.astype(np.float64)
@@ -102,7 +126,7 @@ def element_coefficients(y, m: int) -> np.ndarray:
     for (sq, (p, q, r)), yn in zip(terms, y):
         bx, by, bz = phi_1d(m1[p], xc), phi_1d(m1[q], xc), phi_1d(m1[r], xc)
         g = g + sq * yn * (bz[:, None, None] * by[None, :, None] * bx[None, None, :])
-    return A_MIN + A_HAT * np.exp(g)
+    return A_MIN + ah * np.exp(g)
 
 
 # ------------------------------------------------------------ assembly
@@ -158,9 +182,9 @@ def rhs(m: int) -> np.ndarray:
     return np.full(m ** 3, h ** 3)
 
 
-def assemble(y, m: int):
-    """(A as CSR, b, diag(A)) for one sample."""
-    A = assemble_from_cells(element_coefficients(y, m), m)
+def assemble(y, m: int, test: int = 1):
+    """(A as CSR, b, diag(A)) for one sample (Test 1 or Test 2 coefficient)."""
+    A = assemble_from_cells(element_coefficients(y, m, test), m)
     return A, rhs(m), A.diagonal().copy()
 
 
@@ -179,10 +203,10 @@ def slot_values(A, m: int) -> np.ndarray:
     return out
 
 
-def param_indicator(y, m: int) -> float:
+def param_indicator(y, m: int, test: int = 1) -> float:
     """Section 3.2, eq. (pb-indicator): the supremum over the domain of
     lambda_max / lambda_min of A = diag(a, a_y, a_z), a held on each cube."""
-    ac = element_coefficients(y, m)
+    ac = element_coefficients(y, m, test)
     hi = np.maximum(np.maximum(ac, A_Y), A_Z)
     lo = np.minimum(np.minimum(ac, A_Y), A_Z)
     return float(np.max(hi / lo))
@@ -201,7 +225,7 @@ def qoi_weights(m: int) -> np.ndarray:
     return w
 
 
-def dA_bilinear(lam, u, y, m: int) -> np.ndarray:
+def dA_bilinear(lam, u, y, m: int, test: int = 1) -> np.ndarray:
     """lambda^T (dA/dy_j) u for j = 0..d-1.  Only a depends on y; on cube c,
     da_c/dy_j = a_hat exp(g_c) sqrt(lambda_j) b_j(x_c) = (a_c - a_min)
     sqrt(lambda_j) b_j(x_c), and the part of the cube matrix that a
@@ -212,7 +236,7 @@ def dA_bilinear(lam, u, y, m: int) -> np.ndarray:
     terms, m1 = kl_3d(len(y))
     h = 1.0 / (m + 1)
     xc = (np.arange(m + 1) + 0.5) * h
-    eg = element_coefficients(y, m) - A_MIN
+    eg = element_coefficients(y, m, test) - A_MIN
     Kc = element_matrix(1.0, 0.0, 0.0, h)
     Lp = np.zeros((m + 2,) * 3)
     Up = np.zeros((m + 2,) * 3)
@@ -230,20 +254,20 @@ def dA_bilinear(lam, u, y, m: int) -> np.ndarray:
     return out
 
 
-def qoi_and_grad(y, m: int):
+def qoi_and_grad(y, m: int, test: int = 1):
     """(Q, dQ/dy, u, lambda) with direct sparse solves (exact to round-off)."""
-    A, b, _ = assemble(y, m)
+    A, b, _ = assemble(y, m, test)
     w = qoi_weights(m)
     lu = spla.splu(A.tocsc())
     u = lu.solve(b)
     lam = lu.solve(w)
-    return float(w @ u), -dA_bilinear(lam, u, y, m), u, lam
+    return float(w @ u), -dA_bilinear(lam, u, y, m, test), u, lam
 
 
-def qoi_complex_step(y, m: int, j: int, h: float = 1e-30) -> float:
+def qoi_complex_step(y, m: int, j: int, h: float = 1e-30, test: int = 1) -> float:
     """dQ/dy_j = Im Q(y + i h e_j) / h with a complex sparse direct solve."""
     yc = np.asarray(y, dtype=np.complex128).copy()
     yc[j] += 1j * h
-    A = assemble_from_cells(element_coefficients(yc, m), m)
+    A = assemble_from_cells(element_coefficients(yc, m, test), m)
     u = spla.splu(A.tocsc()).solve(rhs(m).astype(np.complex128))
     return float(np.imag(qoi_weights(m) @ u)) / h

@@ -175,7 +175,7 @@ static int check_problem(const ens_problem* p) {
   if (is3d(p)) {
     if (p->n < 2 || p->n > 1024) return ENS_EINVAL;
     if (p->d < 1 || p->d > kMaxTerms) return ENS_EINVAL;
-    if (p->eps_model != 0 || p->amp != 0.0) return ENS_EINVAL;
+    if ((p->eps_model != 0 && p->eps_model != 1) || p->amp != 0.0) return ENS_EINVAL;
     return ENS_OK;
   }
   if (p->dim != 0 && p->dim != 2) return ENS_EINVAL;
@@ -662,6 +662,7 @@ int ens_assemble_ensemble(const ens_problem* prob, int32_t S, const double* y_ho
     f.m = prob->n;
     f.S = S;
     f.d = d;
+    f.test = prob->eps_model;
     f.nr = rows_of(prob);
     f.vstride = slot_stride(f.nr * S);
     for (int m0 = 0; m0 < S; m0 += mcmax) {
@@ -911,6 +912,7 @@ static int dqdy3(const ens_problem* prob, int32_t S, const double* y_dev, const 
   a.S = S;
   a.Sp = pow2ceil(S);
   a.d = prob->d;
+  a.test = prob->eps_model;
   a.ncell = (size_t)(prob->n + 1) * (prob->n + 1) * (prob->n + 1);
   // d <= 16 partial arrays of groups * Sp doubles must fit the partial buffer
   const int groups = (int)std::min<size_t>((a.ncell * a.Sp + kNT - 1) / kNT,

@@ -23,6 +23,7 @@ struct Fe3dAsmArgs {
   double* b;        // [N_r][S]
   int m, S, d;
   int m0, mc, mcp;  // first member, members, threads per row (power of two >= mc)
+  int test;         // coefficient a_hat: 0 Test 1 (1), 1 Test 2 (banded by |y|)
   size_t nr, vstride;
   Fe3dTerm term[kMaxTerms];
 };
@@ -34,6 +35,7 @@ struct Fe3dDqdyArgs {
   const double* lam;  // [N_r][S]
   double* partial;    // [d][groups][Sp]
   int m, S, Sp, d;    // Sp: member slots (power of two >= S); one thread per slot and cube
+  int test;           // as in Fe3dAsmArgs
   size_t ncell;       // (m+1)^3 cubes
   Fe3dTerm term[kMaxTerms];
 };
@@ -43,7 +45,7 @@ struct Fe3dDqdyArgs {
 struct IndArgs {
   const double* y;   // [S][d]
   double* partial;   // [groups][Sp] per-workgroup maxima
-  int dim, m, S, Sp, d, eps_model;
+  int dim, m, S, Sp, d, eps_model;   // 3-D: eps_model selects a_hat as Fe3dAsmArgs::test
   size_t ncell;      // 3-D: cubes (m+1)^3; 2-D: 1 (the ratio does not depend on x)
   Fe3dTerm term[kMaxTerms];
 };

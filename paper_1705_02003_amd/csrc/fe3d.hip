@@ -78,6 +78,19 @@ __device__ __forceinline__ double phi1(int kind, double w, double norm, double s
   return norm * (kind == 0 ? cos(u) : sin(u));
 }
 
+// The factor a_hat of eq. (diff-coeff): 1 in Test 1; in Test 2 (Section 4,
+// Test 2 equation) 1, 100 or 10 as r(y) = |y|_2 lies below d/4, between d/4
+// and d/2, or at or above d/2 (d = sqrt(3)), decided on r^2 = sum_n y_n^2
+// (each product and sum rounded, in index order) against the exact
+// d^2/16 = 3/16 and d^2/4 = 3/4.
+__device__ __forceinline__ double fe3d_ahat(const double* y, int d, int test) {
+#pragma clang fp contract(off)
+  if (test == 0) return kAhat;
+  double r2 = 0.0;
+  for (int n = 0; n < d; ++n) r2 = r2 + y[n] * y[n];
+  return r2 < 0.1875 ? 1.0 : (r2 < 0.75 ? 100.0 : 10.0);
+}
+
 }  // namespace
 
 int fe3d_setup(const ens_problem* p, Fe3dAsmArgs& a) {
@@ -131,6 +144,7 @@ __global__ __launch_bounds__(kNT) void fe3d_assemble_kernel(Fe3dAsmArgs a) {
   const size_t e = row * a.S + a.m0 + cl;
   const int i = (int)(row % m), j = (int)((row / m) % m), k = (int)(row / ((size_t)m * m));
   const double* y = ys + cl * a.d;
+  const double ahat = fe3d_ahat(y, a.d, a.test);
   const double h = 1.0 / (double)(m + 1);
 
   // a at the centres of the eight cubes around mesh node (i+1, j+1, k+1):
@@ -150,7 +164,7 @@ __global__ __launch_bounds__(kNT) void fe3d_assemble_kernel(Fe3dAsmArgs a) {
           const double bz = phi1(f.kind[2], f.w[2], f.norm[2], zc);
           g = g + (f.sq * y[n]) * ((bz * by) * bx);
         }
-        ac[cz][cy][cx] = kAmin + kAhat * exp(g);
+        ac[cz][cy][cx] = kAmin + ahat * exp(g);
       }
   const double kd = 1.0 / h, ko = -1.0 / h;               // K1 diagonal / off-diagonal
   const double md = (2.0 * h) / 6.0, mo = (1.0 * h) / 6.0;  // M1
@@ -194,6 +208,7 @@ __global__ __launch_bounds__(kNT) void indicator_kernel(IndArgs a) {
   const int Sp = a.Sp, t = threadIdx.x, s = t & (Sp - 1);
   const bool lane_ok = s < a.S;
   const double* y = a.y + (size_t)(lane_ok ? s : a.S - 1) * a.d;
+  const double ahat = (a.dim == 3) ? fe3d_ahat(y, a.d, a.eps_model) : 0.0;
   double hv[1] = {0.0};
   const size_t cpb = (size_t)(kNT / Sp);   // cubes per workgroup and pass
   const size_t stride = (size_t)gridDim.x * cpb;
@@ -212,7 +227,7 @@ __global__ __launch_bounds__(kNT) void indicator_kernel(IndArgs a) {
         const double bz = phi1(f.kind[2], f.w[2], f.norm[2], zc);
         g = g + (f.sq * y[n]) * ((bz * by) * bx);
       }
-      const double ac = kAmin + kAhat * exp(g);
+      const double ac = kAmin + ahat * exp(g);
       r = fmax(fmax(ac, kAy), kAz) / fmin(fmin(ac, kAy), kAz);
     } else {
       const double eps = (a.eps_model == 0) ? pow(10.0, -(1.0 + y[0])) : pow(10.0, -(1.5 + 1.5 * y[0]));
@@ -238,6 +253,7 @@ __global__ __launch_bounds__(kNT) void fe3d_dqdy_kernel(Fe3dDqdyArgs a) {
   const bool lane_ok = s0 < S;
   const int s = lane_ok ? s0 : S - 1;   // idle slots compute on a real member, add nothing
   const double* y = a.y + (size_t)s * a.d;
+  const double ahat = fe3d_ahat(y, a.d, a.test);
   const double h = 1.0 / (double)mc;
   const double kd = 1.0 / h, ko = -1.0 / h, md = (2.0 * h) / 6.0, mo = (1.0 * h) / 6.0;
   double acc[kMaxTerms];
@@ -284,7 +300,7 @@ __global__ __launch_bounds__(kNT) void fe3d_dqdy_kernel(Fe3dDqdyArgs a) {
         g = g + (f.sq * y[n]) * bj[n];
       }
     }
-    const double eg = kAhat * exp(g);
+    const double eg = ahat * exp(g);
 #pragma unroll
     for (int n = 0; n < kMaxTerms; ++n)
       if (n < a.d) acc[n] += eg * a.term[n].sq * bj[n] * B;

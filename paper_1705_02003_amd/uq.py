@@ -89,7 +89,8 @@ class _Workspaces:
         return self.streams[worker]
 
 
-def _solve_groups(prob, y_level, groups, opts, wss, device, spmv_acc, streams: int = 1):
+def _solve_groups(prob, y_level, groups, opts, wss, device, spmv_acc, streams: int = 1,
+                  progress=None):
     """Solve each group (an id array; its length is the ensemble width) and
     record per-sample counts and G(y) = ||u||^2.  With streams = K > 1, K
     host threads solve the groups round-robin, each on its own HIP stream
@@ -121,10 +122,10 @@ def _solve_groups(prob, y_level, groups, opts, wss, device, spmv_acc, streams: i
             for i in range(4):
                 spmv_acc[i] += acc[i]
         return iters, qoi, ens_iters
-    return _solve_serial(prob, y_level, groups, opts, wss, device, spmv_acc)
+    return _solve_serial(prob, y_level, groups, opts, wss, device, spmv_acc, progress)
 
 
-def _solve_serial(prob, y_level, groups, opts, wss, device, spmv_acc):
+def _solve_serial(prob, y_level, groups, opts, wss, device, spmv_acc, progress=None):
     iters = np.full(len(y_level), -1, np.int64)
     qoi = np.zeros(len(y_level))
     ens_iters = []
@@ -150,6 +151,8 @@ def _solve_serial(prob, y_level, groups, opts, wss, device, spmv_acc):
         spmv_acc[0] += st["spmv_ms"]
         spmv_acc[1] += st["spmv_timed"]
         spmv_acc[2] += st["spmv_timed"] * prob.rows * S
+        if progress is not None:
+            progress(len(ens_iters), len(groups))
     return iters, qoi, ens_iters
 
 
@@ -346,14 +349,15 @@ class NonAdaptiveResult:
 
 def nonadaptive(prob: E.Problem, S: int, y: np.ndarray, train_level: int,
                 opts: Optional[E.SolverOptions] = None, solve_groups: Optional[List[int]] = None,
-                device="cuda", streams: int = 1) -> NonAdaptiveResult:
+                device="cuda", streams: int = 1, progress=None) -> NonAdaptiveResult:
     """Surrogate grouping without adaptivity (paper, Section 5: pre-select
     samples, evaluate them, build the iteration surrogate, group the rest).
 
     The training set is the full sparse grid of total level ``train_level``,
     solved in generation order; its iteration counts define I^, which orders
     the samples ``y`` into ensembles of S.  ``solve_groups`` selects which of
-    the resulting ensembles are solved (all by default)."""
+    the resulting ensembles are solved (all by default).  ``progress(done,
+    total)`` is called after each solved ensemble (serial solves only)."""
     opts = opts or E.SolverOptions()
     wss = _Workspaces(prob, opts, device)
     lv, ix = G.full_grid(prob.d, train_level)
@@ -370,7 +374,8 @@ def nonadaptive(prob: E.Problem, S: int, y: np.ndarray, train_level: int,
     chosen = np.asarray([groups[k] for k in sel])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    iters, _, ens_iters = _solve_groups(prob, y, chosen, opts, wss, device, acc, streams)
+    iters, _, ens_iters = _solve_groups(prob, y, chosen, opts, wss, device, acc, streams,
+                                        progress)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     return NonAdaptiveResult(it_train, groups, pred, iters, ens_iters, dt, t_train,

@@ -332,7 +332,8 @@ def test_3d_model_descriptor_without_gpu(L):
         ws2 = lib.ens_pcg_workspace_bytes(C.byref(p2), C.byref(o), S)
         # five vectors of the slot stride beyond the same header
         assert ws - ws2 == 5 * 8 * (Ls - lib.ens_matrix_slot_stride(C.byref(p2), S))
-    for bad in (L.ens_problem(31, 4, 1, 3, 0.0), L.ens_problem(31, 4, 0, 3, 0.4),
+    assert lib.ens_matrix_slot_stride(C.byref(L.ens_problem(31, 4, 1, 3, 0.0)), 8) > 0   # Test 2
+    for bad in (L.ens_problem(31, 4, 2, 3, 0.0), L.ens_problem(31, 4, 0, 3, 0.4),
                 L.ens_problem(31, 0, 0, 3, 0.0), L.ens_problem(31, 17, 0, 3, 0.0),
                 L.ens_problem(1, 4, 0, 3, 0.0), L.ens_problem(1025, 4, 0, 3, 0.0),
                 L.ens_problem(31, 4, 0, 4, 0.0), L.ens_problem(31, 4, 0, 1, 0.0)):

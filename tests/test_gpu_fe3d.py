@@ -303,3 +303,69 @@ def test_param_indicator_matches_oracle(dim, m, S, d, eps_model):
     assert hm.shape == (150,)
     assert hm[149] == pytest.approx(ofe.param_indicator(many[149], m) if dim == 3
                                     else oprob.param_indicator(many[149], eps_model), rel=1e-13)
+
+
+def test2_samples(S, d, seed):
+    """Samples spread over Test 2's three bands of |y| (and two exactly on
+    the band edges, where the decision must follow the inequalities)."""
+    rng = np.random.default_rng(seed)
+    ys = rng.uniform(-1, 1, (S, d))
+    radii = np.array([0.2, 0.6, 1.2])
+    for s in range(min(S, 3)):            # one inside each band
+        ys[s] = ys[s] / np.linalg.norm(ys[s]) * radii[s]
+    if S > 4 and d == 4:
+        ys[3] = [0.25, 0.25, 0.25, 0.0]     # r = sqrt(3)/4 exactly: a_hat = 100
+        ys[4] = [0.5, 0.5, 0.5, 0.0]        # r = sqrt(3)/2 exactly: a_hat = 10
+    return ys
+
+
+@pytest.mark.parametrize("m,S,d,seed", [(6, 8, 4, 50), (5, 20, 4, 51), (7, 3, 2, 52)])
+def test_test2_assembly_solve_and_indicator(m, S, d, seed):
+    """Test 2's banded a_hat (eps_model 1): assembly of every member against
+    the oracle, counts and equal-count solutions against the oracle's PCG,
+    and the grouping indicator."""
+    log_case(test="fe3d-test2", m=m, S=S, d=d)
+    ens = E()
+    ys = test2_samples(S, d, seed)
+    prob = ens.Problem(m, d, 1, dim=3)
+    V, b = ens.assemble(prob, ys)
+    Vh = V.cpu().numpy()
+    for s in range(S):
+        A, _, dg = ofe.assemble(ys[s], m, test=2)
+        ref = ofe.slot_values(A, m)
+        err = np.abs(Vh[:, :, s] - ref).max(axis=0)
+        assert np.all(err <= 1e-13 * np.abs(dg)), (s, float((err / dg).max()))
+    res = ens.solve(prob, V, b, ens.SolverOptions(rtol=1e-7))
+    x = res.x.cpu().numpy()
+    for s in range(S):
+        A, bo, dg = ofe.assemble(ys[s], m, test=2)
+        _, I, st, _ = opcg.pcg(A, bo, dg, 1e-7, 20000)
+        assert st == CONVERGED and res.status[s] == CONVERGED
+        assert abs(int(res.iters[s]) - I) <= 1, (s, res.iters[s], I)
+        xe, _, _, _ = opcg.pcg(A, bo, dg, 0.0, int(res.iters[s]))
+        assert np.linalg.norm(x[:, s] - xe) <= 1e-9 * np.linalg.norm(xe)
+    h = ens.param_indicator(prob, ys)
+    for s in range(S):
+        assert h[s] == pytest.approx(ofe.param_indicator(ys[s], m, test=2), rel=1e-13)
+
+
+def test_test2_dqdy_and_adjoint():
+    log_case(test="fe3d-test2-adjoint")
+    ens = E()
+    m, S, d = 7, 8, 4
+    ys = test2_samples(S, d, 53)
+    prob = ens.Problem(m, d, 1, dim=3)
+    rng = np.random.default_rng(54)
+    U, Lm = rng.standard_normal((m ** 3, S)), rng.standard_normal((m ** 3, S))
+    g = ens.dqdy(prob, ys, to_dev(U), to_dev(Lm))
+    for s in range(S):
+        ref = -ofe.dA_bilinear(Lm[:, s], U[:, s], ys[s], m, test=2)
+        np.testing.assert_allclose(g[s], ref, rtol=1e-11, atol=1e-11 * np.abs(ref).max())
+    V, b = ens.assemble(prob, ys)
+    opts = ens.SolverOptions(rtol=1e-12)
+    u = ens.solve(prob, V, b, opts).x
+    _, gr, _, status = ens.adjoint_grad(prob, ys, V, u, ens.qoi_weights(m, dim=3), opts)
+    assert np.all(status == CONVERGED)
+    for s in range(S):
+        _, gref, _, _ = ofe.qoi_and_grad(ys[s], m, test=2)
+        assert np.max(np.abs(gr[s] - gref)) <= 1e-8 * np.max(np.abs(gref))

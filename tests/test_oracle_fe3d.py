@@ -183,3 +183,68 @@ def test_qoi_weights_window():
         inside = (x >= 0.4 - 1e-12) & (x <= 0.6 + 1e-12)
         assert np.array_equal(w > 0, inside[:, None, None] & inside[None, :, None] & inside[None, None, :])
         assert w.sum() == pytest.approx(1.0, rel=1e-14)
+
+
+def _band_exact(y):
+    """Test 2's band of y by exact rational arithmetic on the FP64 inputs:
+    r^2 = sum y_i^2 against d^2/16 = 3/16 and d^2/4 = 3/4 (d = sqrt(3))."""
+    from fractions import Fraction
+    r2 = sum(Fraction(float(v)) ** 2 for v in y)
+    return 1.0 if r2 < Fraction(3, 16) else (100.0 if r2 < Fraction(3, 4) else 10.0)
+
+
+def test_test2_a_hat_bands():
+    """a_hat(y) of the Test 2 equation: inside each band, exactly on both band
+    edges (dyadic sparse-grid coordinates, where the squares are exact), just
+    either side of the edges, and random points, against exact rational
+    arithmetic; Test 1 is a_hat = 1 everywhere."""
+    cases = [
+        ([0.0, 0.0, 0.0, 0.0], 1.0), ([0.3, -0.2, 0.1, 0.0], 1.0),
+        ([0.25, 0.25, 0.25, 0.0], 100.0),          # r = d/4 exactly: the middle band
+        ([0.25, -0.25, 0.0, 0.25], 100.0),
+        ([0.5, 0.0, 0.0, 0.0], 100.0), ([0.5, 0.5, 0.25, -0.25], 100.0),
+        ([0.5, 0.5, 0.5, 0.0], 10.0),              # r = d/2 exactly: the outer band
+        ([-0.5, 0.5, 0.0, -0.5], 10.0), ([1.0, 0.0, 0.0, 0.0], 10.0),
+        ([0.4330127, 0.0, 0.0, 0.0], 1.0),         # d/4 = 0.43301270189...
+        ([0.4330128, 0.0, 0.0, 0.0], 100.0),
+        ([0.8660254, 0.0, 0.0, 0.0], 100.0),       # d/2 = 0.86602540378...
+        ([0.8660255, 0.0, 0.0, 0.0], 10.0),
+    ]
+    for y, want in cases:
+        assert fe3d.a_hat(y, 2) == want, y
+        assert fe3d.a_hat(y, 1) == 1.0
+        assert _band_exact(y) == want
+    rng = np.random.default_rng(7)
+    for y in rng.uniform(-1, 1, (400, 4)):
+        assert fe3d.a_hat(y, 2) == _band_exact(y)
+        r = math.sqrt(float(np.sum(y ** 2)))
+        d = math.sqrt(3.0)
+        assert fe3d.a_hat(y, 2) == (1.0 if r < d / 4 else (100.0 if r < d / 2 else 10.0))
+
+
+@pytest.mark.parametrize("y,ah", [([0.1, -0.2, 0.1, 0.0], 1.0), ([0.5, 0.2, -0.3, 0.1], 100.0),
+                                  ([0.7, -0.6, 0.4, 0.3], 10.0)])
+def test_test2_field_and_matrix_scale_with_a_hat(y, ah):
+    """Test 2 only rescales the exponential part: a - a_min = a_hat (a_1 -
+    a_min) cell by cell, exactly, and the assembled matrix is that of the
+    rescaled cells."""
+    m = 6
+    a1 = fe3d.element_coefficients(y, m, 1)
+    a2 = fe3d.element_coefficients(y, m, 2)
+    assert fe3d.a_hat(y, 2) == ah
+    assert np.array_equal(a2 - fe3d.A_MIN, ah * (a1 - fe3d.A_MIN)) or \
+        np.max(np.abs((a2 - fe3d.A_MIN) - ah * (a1 - fe3d.A_MIN))) <= 1e-15 * np.max(np.abs(a2))
+    A2, _, _ = fe3d.assemble(y, m, 2)
+    ref = fe3d.assemble_from_cells(fe3d.A_MIN + ah * (a1 - fe3d.A_MIN), m)
+    assert abs(A2 - ref).max() <= 1e-14 * abs(ref).max()
+
+
+@pytest.mark.parametrize("y", [[0.5, 0.2, -0.3, 0.1], [0.7, -0.6, 0.4, 0.3]])
+def test_test2_adjoint_gradient_matches_complex_step(y):
+    """Inside a band a_hat is constant, so dQ/dy is the Test 1 form with the
+    band's factor; the adjoint form against a complex step."""
+    y = np.asarray(y)
+    m = 5
+    Q, g, _, _ = fe3d.qoi_and_grad(y, m, test=2)
+    cs = np.array([fe3d.qoi_complex_step(y, m, j, test=2) for j in range(len(y))])
+    assert np.max(np.abs(g - cs)) <= 1e-12 * np.max(np.abs(cs))

@@ -71,7 +71,14 @@ FE3D_32 = Workload("fe3d-32cube-d4", 31, 4, EPS_MODEL_MILD, 0.0, (32,),
                    PRECOND_CHEBYSHEV, 1e-7, 20000, 5, 512,
                    "3-D trilinear FE, log-normal KL diffusivity, Jacobi and Chebyshev-4")
 
-ALL = (SMALL, ADAPTIVE_512, CHEB_1024, BATCHED, ADJOINT_512, FE3D_32)
+# The paper's Test 2 (Section 4): the same problem with the discontinuous
+# factor a_hat(y) in {1, 100, 10} banded by |y| (selected by eps_model 1 in
+# the 3-D model).
+FE3D_32_TEST2 = Workload("fe3d-32cube-d4-test2", 31, 4, 1, 0.0, (32,),
+                         PRECOND_CHEBYSHEV, 1e-7, 20000, 5, 512,
+                         "3-D trilinear FE, Test 2: a_hat(y) banded by |y|")
+
+ALL = (SMALL, ADAPTIVE_512, CHEB_1024, BATCHED, ADJOINT_512, FE3D_32, FE3D_32_TEST2)
 
 
 def uniform_samples(seed: int, M: int, d: int) -> np.ndarray:
