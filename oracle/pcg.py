@@ -63,7 +63,8 @@ def chebyshev_apply(A, diag, r, lmax, ratio=CHEB_RATIO, degree=CHEB_DEGREE):
 def pcg(A, b, diag, rtol, max_iter, precond="jacobi", lmax=None):
     """Solve A x = b by PCG.  Returns (x, I, status, relres).
 
-    relres = ||r_I|| / ||b|| for the recurrence residual at exit.
+    relres = ||r_I|| / ||b|| for the recurrence residual at exit.  `precond`
+    is "jacobi", "chebyshev" or a callable v -> M^-1 v (an SPD operator).
     """
     n = b.shape[0]
     x = np.zeros(n)
@@ -75,6 +76,8 @@ def pcg(A, b, diag, rtol, max_iter, precond="jacobi", lmax=None):
         lmax = gershgorin_lmax(A, diag)
 
     def M(v):
+        if callable(precond):
+            return precond(v)
         if precond == "jacobi":
             return v / diag
         return chebyshev_apply(A, diag, v, lmax)
