@@ -71,6 +71,7 @@ extern "C" {
 
 #define ENS_PRECOND_JACOBI 0
 #define ENS_PRECOND_CHEBYSHEV 1
+#define ENS_PRECOND_MULTIGRID 2   /* 3-D model, n + 1 a power of two (ENS_ENOTSUP otherwise) */
 
 /* Problem descriptor.
  *
@@ -113,7 +114,7 @@ typedef struct {
 /* Solver options.  Zero-initialise, then set what you need; fields left 0
  * take the documented default. */
 typedef struct {
-  int32_t precond;      /* ENS_PRECOND_JACOBI (default) or _CHEBYSHEV          */
+  int32_t precond;      /* ENS_PRECOND_JACOBI (default), _CHEBYSHEV, _MULTIGRID */
   int32_t cheb_degree;  /* Chebyshev residual-polynomial degree, 2..8 (4)     */
   double cheb_ratio;    /* lambda_max / lambda_min of the Chebyshev interval (30) */
   double rtol;          /* relative residual tolerance (1e-8)                 */
@@ -194,8 +195,9 @@ size_t ens_pcg_workspace_bytes(const ens_problem* prob, const ens_opts* opts, in
  * x and r no longer change) while the others continue.  Preconditioner:
  * Jacobi (diagonal = slot 4 of V; 3-D: slot 13) or a Chebyshev polynomial in
  * D^-1 A over [lambda_max / cheb_ratio, lambda_max], lambda_max the member's
- * Gershgorin bound max_i sum_j |a_ij| / a_ii.  Both models; the 3-D model
- * ignores tile_lines and member_tile.
+ * Gershgorin bound max_i sum_j |a_ij| / a_ii, or (3-D model only) one
+ * geometric multigrid V-cycle per application (see ens_mg_apply).  Both
+ * models; the 3-D model ignores tile_lines and member_tile.
  * In:  V_dev [9][L] (3-D: [27][L]; symmetric positive definite per member),
  *      b_dev [N_r][S].
  * Out: x_dev [N_r][S] (overwritten); iters_host[S], status_host[S],
@@ -245,6 +247,32 @@ int ens_spmv(const ens_problem* prob, int32_t S, const double* V_dev,
 int ens_cheb_apply(const ens_problem* prob, const ens_opts* opts, int32_t S,
                    const double* V_dev, const double* r_dev, double* z_dev,
                    double* lmax_host, void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Apply the multigrid preconditioner once: z = V(r) per member, one V-cycle
+ * (paper, Section 4: CG preconditioned by a multigrid hierarchy with a
+ * degree-2 Chebyshev smoother on every level and a direct solve on the
+ * coarsest; here its geometric form on the 3-D model's structured mesh).
+ * Levels: n interior nodes per direction (n + 1 = 2^k cells, k >= 2), then
+ * (n - 1) / 2, ..., 1; prolongation P is trilinear interpolation, restriction
+ * P^T, the coarse operators the Galerkin products P^T A P (formed per member
+ * on the device, in the workspace).  Each level above the coarsest smooths
+ * its correction equation A x = b from x = 0 with the degree-2 Chebyshev
+ * polynomial in D^-1 A on [lambda_max / cheb_ratio, lambda_max] (lambda_max
+ * the level's Gershgorin bound), restricts the residual, adds the
+ * prolongated coarse correction and smooths the new residual with the same
+ * polynomial; the one-node coarsest level is solved exactly.  The V-cycle is
+ * symmetric positive definite, so it may precondition CG.
+ * opts: cheb_ratio (30 by default); precond and cheb_degree are ignored.
+ * In: V_dev [27][L] (3-D model; symmetric positive definite per member),
+ *     r_dev [N_r][S]; out: z_dev [N_r][S]; lmax_host[S] (may be NULL)
+ *     receives each member's fine-level Gershgorin bound.
+ * ws_dev / ws_bytes: at least ens_pcg_workspace_bytes() bytes for
+ * opts with precond = ENS_PRECOND_MULTIGRID (ENS_ENOMEM otherwise).
+ * Errors: ENS_ENOTSUP for the 2-D model or n + 1 not a power of two.
+ * Blocking (reads back lmax). */
+int ens_mg_apply(const ens_problem* prob, const ens_opts* opts, int32_t S,
+                 const double* V_dev, const double* r_dev, double* z_dev,
+                 double* lmax_host, void* ws_dev, size_t ws_bytes, void* stream);
 
 /* Per-member dot products out_host[s] = sum_r a[r][s] * b[r][s].  With
  * b_broadcast != 0, b_dev is a single vector [N_r] shared by all members.

@@ -13,7 +13,7 @@ ENS_EHIP = -3
 ENS_ENOTSUP = -4
 
 CONVERGED, MAX_ITER, BREAKDOWN, ZERO_RHS = 0, 1, 2, 3
-PRECOND_JACOBI, PRECOND_CHEBYSHEV = 0, 1
+PRECOND_JACOBI, PRECOND_CHEBYSHEV, PRECOND_MULTIGRID = 0, 1, 2
 FLAG_TIME_SPMV = 1
 FLAG_FULL_STENCIL = 2
 NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -61,6 +61,7 @@ SIGNATURES = {
     "ens_pcg_solve_noalloc": (C.c_int, [PP, OP, i32, vp, vp, vp, i32p, i32p, f64p, i32p, vp]),
     "ens_spmv": (C.c_int, [PP, i32, vp, vp, vp, vp]),
     "ens_cheb_apply": (C.c_int, [PP, OP, i32, vp, vp, vp, f64p, vp, sz, vp]),
+    "ens_mg_apply": (C.c_int, [PP, OP, i32, vp, vp, vp, f64p, vp, sz, vp]),
     "ens_member_dot": (C.c_int, [i32, i32, vp, vp, i32, f64p, vp, sz, vp]),
     "ens_adjoint_grad": (C.c_int, [PP, OP, i32, vp, vp, vp, vp, vp, f64p, i32p, i32p, vp, sz, vp]),
     "ens_dqdy": (C.c_int, [PP, i32, vp, vp, vp, f64p, vp, sz, vp]),

@@ -20,7 +20,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libens.so")
 
 ARCH = os.environ.get("ENS_OFFLOAD_ARCH", "gfx950")
-HIP_SOURCES = ["kernels.hip", "fe3d.hip", "adjoint.hip", "batch.hip", "calib.hip", "api.hip"]
+HIP_SOURCES = ["kernels.hip", "fe3d.hip", "multigrid.hip", "adjoint.hip", "batch.hip", "calib.hip", "api.hip"]
 CXX_SOURCES = ["sparse_grid.cpp"]
 
 

@@ -8,6 +8,7 @@
 
 #include "common.h"
 #include "fe3d.h"
+#include "multigrid.h"
 
 namespace ens {
 
@@ -210,7 +211,10 @@ static int resolve_opts(const ens_opts* o, Opts& r) {
   r.max_groups = o->max_groups;
   r.flags = o->flags;
   r.member_tile = o->member_tile;
-  if (r.precond != ENS_PRECOND_JACOBI && r.precond != ENS_PRECOND_CHEBYSHEV) return ENS_EINVAL;
+  if (r.precond != ENS_PRECOND_JACOBI && r.precond != ENS_PRECOND_CHEBYSHEV &&
+      r.precond != ENS_PRECOND_MULTIGRID)
+    return ENS_EINVAL;
+  if (r.precond == ENS_PRECOND_MULTIGRID) r.degree = kMgDegree;
   if (r.degree < 2 || r.degree > kMaxCheb) return ENS_EINVAL;
   if (!std::isfinite(r.ratio) || r.ratio <= 1.0) return ENS_EINVAL;
   if (!std::isfinite(r.rtol) || r.rtol < 0.0) return ENS_EINVAL;
@@ -225,6 +229,33 @@ static int resolve_opts(const ens_opts* o, Opts& r) {
     hipError_t e_ = (call);                  \
     if (e_ != hipSuccess) return set_hip_error(e_); \
   } while (0)
+
+// A solve's workspace: the Krylov vectors and per-member state (8 vectors
+// with a polynomial or multigrid preconditioner, 5 with Jacobi) and, for
+// multigrid, the coarse levels after them.
+static bool uses_poly(const Opts& o) { return o.precond != ENS_PRECOND_JACOBI; }
+
+static int check_precond(const ens_problem* prob, const Opts& o) {
+  if (o.precond != ENS_PRECOND_MULTIGRID) return ENS_OK;
+  int ms[kMgMaxLevels];
+  return (is3d(prob) && mg_levels(prob->n, ms) >= 2) ? ENS_OK : ENS_ENOTSUP;
+}
+
+static size_t solve_bytes(const ens_problem* prob, const Opts& o, int S) {
+  size_t b = workspace_bytes(rows_of(prob), S, uses_poly(o));
+  if (o.precond == ENS_PRECOND_MULTIGRID) b += mg_bytes(prob->n, S);
+  return b;
+}
+
+static Workspace carve_solve(void* base, const ens_problem* prob, const Opts& o, int S, MgHierarchy* H) {
+  const Workspace w = carve_workspace(base, rows_of(prob), S, uses_poly(o));
+  if (H) {
+    std::memset(H, 0, sizeof(*H));
+    if (o.precond == ENS_PRECOND_MULTIGRID)
+      mg_carve(static_cast<char*>(base) + workspace_bytes(rows_of(prob), S, true), prob->n, S, w.m.ctl, *H);
+  }
+  return w;
+}
 
 static void finish(const Workspace& w, const Geometry& g, int G, int kind, hipStream_t s,
                    double rtol = 0.0, int cheb_init = 0) {
@@ -278,6 +309,178 @@ static Geometry geometry_for(const ens_problem* prob, const Opts& o, int S) {
   Geometry g = make_geometry(prob->n, S, o.tile_lines, o.max_groups, o.member_tile);
   g.full = (o.flags & ENS_FLAG_FULL_STENCIL) ? 1 : 0;
   return g;
+}
+
+// ------------------------------------------------------------ multigrid
+// Level 0 of the V-cycle works in the solve's own vectors: its right-hand
+// side is the PCG residual r, its output z[1] (the direction source of the
+// next step), its smoother start d, z[0] (written by the residual update),
+// its residual aux and post-smoother output q (A p is not needed again until
+// the next product writes it).  Its smoother coefficients are the solve's
+// (the initialisation computes them with degree 2).
+static void mg_bind_fine(MgHierarchy& H, const double* V, const Workspace& w, const Geometry& g) {
+  MgLevel& f = H.lv[0];
+  f.g = g;
+  f.V = V;
+  f.b = w.r;
+  f.x = w.z[1];
+  f.res = w.aux;
+  f.d = w.d;
+  f.za = w.z[0];
+  f.zb = w.q;
+  f.mem = w.m;
+}
+
+// Coarse operators (Galerkin products, level by level) and each coarse
+// level's smoother bound and coefficients.
+static void mg_setup(const MgHierarchy& H, const Workspace& w, double ratio, hipStream_t s) {
+  for (int l = 0; l + 1 < H.L; ++l) {
+    const MgLevel& f = H.lv[l];
+    const MgLevel& c = H.lv[l + 1];
+    MgRapArgs ra;
+    std::memset(&ra, 0, sizeof(ra));
+    ra.Vf = f.V;
+    ra.Vc = const_cast<double*>(c.V);
+    ra.mc = c.m;
+    ra.S = c.g.S;
+    ra.Sp = c.g.Sp;
+    ra.nrc = c.g.nr;
+    ra.vstride_f = f.g.vstride;
+    ra.vstride_c = c.g.vstride;
+    launch_mg_rap(ra, s);
+    MgGershArgs ga;
+    std::memset(&ga, 0, sizeof(ga));
+    ga.V = c.V;
+    ga.partial = w.partial;
+    ga.S = c.g.S;
+    ga.Sp = c.g.Sp;
+    ga.nr = c.g.nr;
+    ga.vstride = c.g.vstride;
+    const int G = mg_groups(c.g.nr, c.g.Sp);
+    launch_mg_gersh(ga, G, s);
+    MgCoefArgs ca;
+    std::memset(&ca, 0, sizeof(ca));
+    ca.partial = w.partial;
+    ca.G = G;
+    ca.S = c.g.S;
+    ca.Sp = c.g.Sp;
+    ca.ratio = ratio;
+    ca.lmax = c.mem.lmax;
+    ca.cheb = c.mem.cheb;
+    launch_mg_coef(ca, s);
+  }
+}
+
+// x_l = V_l(b_l) for a level above the coarsest, whose pre-smoother start
+// (d, za) is in place: pre-smoothing, residual, restriction (starting the
+// next level's smoother, or solving the one-node coarsest level), the
+// coarse cycle, prolongation, the residual with the post-smoother's start,
+// post-smoothing.  The last x += zb is left to the caller.
+static void mg_cycle(const MgHierarchy& H, int l, hipStream_t s) {
+  const MgLevel& v = H.lv[l];
+  const MgLevel& c = H.lv[l + 1];
+  const int* done = v.mem.ctl + CTL_DONE;
+  StencilArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.V = v.V;
+  a.m = v.mem;
+  a.g = v.g;
+  a.r = v.b;
+  a.src = v.za;
+  a.d = v.d;
+  a.zout = v.x;
+  a.cheb_step = 1;
+  launch_fe3d<M_CHEB>(a, s);
+  std::memset(&a, 0, sizeof(a));
+  a.V = v.V;
+  a.m = v.mem;
+  a.g = v.g;
+  a.r = v.b;
+  a.src = v.x;
+  a.q = v.res;
+  launch_fe3d<M_RESID>(a, s);
+  MgTransferArgs t;
+  std::memset(&t, 0, sizeof(t));
+  t.fine_in = v.res;
+  t.coarse_out = const_cast<double*>(c.b);
+  t.Vc = c.V;
+  t.cheb = c.mem.cheb;
+  t.d = c.d;
+  t.z = c.za;
+  t.x = c.x;
+  t.done = done;
+  t.op = (l + 2 == H.L) ? MG_RESTRICT_SOLVE : MG_RESTRICT_START;
+  t.mc = c.m;
+  t.S = c.g.S;
+  t.Sp = c.g.Sp;
+  t.vstride_c = c.g.vstride;
+  launch_mg_transfer(t, s);
+  if (l + 2 < H.L) {
+    mg_cycle(H, l + 1, s);
+    MgVecArgs va;
+    std::memset(&va, 0, sizeof(va));
+    va.z = c.zb;
+    va.x = c.x;
+    va.done = done;
+    va.op = MG_ADD;
+    va.S = c.g.S;
+    va.Sp = c.g.Sp;
+    va.nr = c.g.nr;
+    va.vstride = c.g.vstride;
+    launch_mg_vec(va, s);
+  }
+  std::memset(&t, 0, sizeof(t));
+  t.coarse_in = c.x;
+  t.fine_x = v.x;
+  t.done = done;
+  t.op = MG_PROLONG;
+  t.mc = c.m;
+  t.S = c.g.S;
+  t.Sp = c.g.Sp;
+  launch_mg_transfer(t, s);
+  std::memset(&a, 0, sizeof(a));
+  a.V = v.V;
+  a.m = v.mem;
+  a.g = v.g;
+  a.r = v.b;
+  a.src = v.x;
+  a.q = v.res;
+  a.d = v.d;
+  a.zout = v.za;
+  a.cheb_init = 1;
+  launch_fe3d<M_RESID>(a, s);
+  std::memset(&a, 0, sizeof(a));
+  a.V = v.V;
+  a.m = v.mem;
+  a.g = v.g;
+  a.r = v.res;
+  a.src = v.za;
+  a.d = v.d;
+  a.zout = v.zb;
+  a.cheb_step = 1;
+  launch_fe3d<M_CHEB>(a, s);
+}
+
+// One V-cycle application z[1] = V(r) on level 0 (smoother started), the
+// last correction fused with the partial sums of r^T z, and the step's
+// rho (and beta) from them.
+static void mg_apply(const MgHierarchy& H, const Workspace& w, bool init, hipStream_t s) {
+  const MgLevel& f = H.lv[0];
+  mg_cycle(H, 0, s);
+  MgVecArgs va;
+  std::memset(&va, 0, sizeof(va));
+  va.z = f.zb;
+  va.x = f.x;
+  va.dot = f.b;
+  va.partial = w.partial;
+  va.done = w.m.ctl + CTL_DONE;
+  va.op = MG_ADD;
+  va.S = f.g.S;
+  va.Sp = f.g.Sp;
+  va.nr = f.g.nr;
+  va.vstride = f.g.vstride;
+  const int G = launch_mg_vec(va, s);
+  finish(w, f.g, G, F_CHEB, s, 0.0, init ? 1 : 0);
 }
 
 struct SolveOut {
@@ -371,10 +574,18 @@ enum PollMode { POLL_ASYNC = 0, POLL_SYNC = 1 };
 
 static int run_solve(const ens_problem* prob, const Opts& o, int S, const double* V, const double* b,
                      int b_bcast, double* x, const Workspace& w, hipStream_t s, SolveOut out,
-                     PollMode mode = POLL_ASYNC) {
-  const bool cheb = (o.precond == ENS_PRECOND_CHEBYSHEV);
+                     PollMode mode = POLL_ASYNC, const MgHierarchy* mgh = nullptr) {
+  const bool mg = (o.precond == ENS_PRECOND_MULTIGRID);
+  const bool cheb = uses_poly(o);   // Chebyshev or multigrid: smoother coefficients at init
   const Geometry g = geometry_for(prob, o, S);
   const int ge = init_groups(g);
+  MgHierarchy H;
+  if (mg) {
+    if (!mgh || mgh->L < 2) return ENS_EINVAL;
+    H = *mgh;
+    mg_bind_fine(H, V, w, g);
+    mg_setup(H, w, o.ratio, s);
+  }
 
   hipLaunchKernelGGL(clear_ctl_kernel, dim3(1), dim3(64), 0, s, w.m.ctl);
   InitArgs ia;
@@ -408,7 +619,13 @@ static int run_solve(const ens_problem* prob, const Opts& o, int S, const double
     launch_finish(f, s);
   }
   double* zfinal = nullptr;
-  if (cheb) zfinal = cheb_apply(V, w, g, o.degree, true, false, s);
+  if (mg) {
+    launch_cheb_start(V, w.r, w.d, w.z[0], w.m, g, ge, s);
+    mg_apply(H, w, true, s);
+    zfinal = w.z[1];
+  } else if (cheb) {
+    zfinal = cheb_apply(V, w, g, o.degree, true, false, s);
+  }
   HIPCHECK(hipGetLastError());
 
   const bool timing = (o.flags & ENS_FLAG_TIME_SPMV) != 0 && mode == POLL_ASYNC;
@@ -460,7 +677,7 @@ static int run_solve(const ens_problem* prob, const Opts& o, int S, const double
         ev_iter.push_back(it);
       }
       finish(w, g, g.groups, F_ALPHA, s);
-      if (cheb && g.dim == 2) {
+      if (cheb && !mg && g.dim == 2) {
         // the residual update fused with the first Chebyshev step; the
         // residual alternates between two buffers (w.r holds the initial one)
         double* r_in = (it & 1) ? w.r : w.aux;
@@ -495,7 +712,8 @@ static int run_solve(const ens_problem* prob, const Opts& o, int S, const double
         u.rtol = o.rtol;
         launch_update(u, cheb, ge, s);
         finish(w, g, ge, cheb ? F_UPDATE_C : F_UPDATE_J, s, o.rtol);
-        if (cheb) cheb_apply(V, w, g, o.degree, false, true, s);
+        if (mg) mg_apply(H, w, false, s);
+        else if (cheb) cheb_apply(V, w, g, o.degree, false, true, s);
       }
     }
     if (rc != ENS_OK) break;
@@ -740,8 +958,8 @@ size_t ens_matrix_slot_stride(const ens_problem* prob, int32_t S) {
 
 size_t ens_pcg_workspace_bytes(const ens_problem* prob, const ens_opts* opts, int32_t S) {
   Opts o;
-  if (check_problem(prob) || resolve_opts(opts, o) || !valid_S(S)) return 0;
-  return workspace_bytes(rows_of(prob), S, o.precond == ENS_PRECOND_CHEBYSHEV);
+  if (check_problem(prob) || resolve_opts(opts, o) || !valid_S(S) || check_precond(prob, o)) return 0;
+  return solve_bytes(prob, o, S);
 }
 
 int ens_pcg_solve(const ens_problem* prob, const ens_opts* opts, int32_t S, const double* V_dev,
@@ -754,11 +972,13 @@ int ens_pcg_solve(const ens_problem* prob, const ens_opts* opts, int32_t S, cons
   rc = resolve_opts(opts, o);
   if (rc) return rc;
   if (!valid_S(S) || !V_dev || !b_dev || !x_dev || !ws_dev) return ENS_EINVAL;
-  const bool cheb = o.precond == ENS_PRECOND_CHEBYSHEV;
-  if (ws_bytes < workspace_bytes(rows_of(prob), S, cheb)) return ENS_ENOMEM;
-  const Workspace w = carve_workspace(ws_dev, rows_of(prob), S, cheb);
+  rc = check_precond(prob, o);
+  if (rc) return rc;
+  if (ws_bytes < solve_bytes(prob, o, S)) return ENS_ENOMEM;
+  MgHierarchy H;
+  const Workspace w = carve_solve(ws_dev, prob, o, S, &H);
   SolveOut out{iters_host, status_host, relres_host, ens_iters_host, stats};
-  return run_solve(prob, o, S, V_dev, b_dev, 0, x_dev, w, (hipStream_t)stream, out);
+  return run_solve(prob, o, S, V_dev, b_dev, 0, x_dev, w, (hipStream_t)stream, out, POLL_ASYNC, &H);
 }
 
 int ens_pcg_solve_noalloc(const ens_problem* prob, const ens_opts* opts, int32_t S,
@@ -771,14 +991,16 @@ int ens_pcg_solve_noalloc(const ens_problem* prob, const ens_opts* opts, int32_t
   rc = resolve_opts(opts, o);
   if (rc) return rc;
   if (!valid_S(S) || !V_dev || !b_dev || !x_dev) return ENS_EINVAL;
-  const bool cheb = o.precond == ENS_PRECOND_CHEBYSHEV;
-  if (workspace_bytes(rows_of(prob), S, cheb) > kScratchBytes) return ENS_ENOMEM;
+  rc = check_precond(prob, o);
+  if (rc) return rc;
+  if (solve_bytes(prob, o, S) > kScratchBytes) return ENS_ENOMEM;
   void* base = nullptr;
   rc = scratch_for_current_device(&base);
   if (rc) return rc;
-  const Workspace w = carve_workspace(base, rows_of(prob), S, cheb);
+  MgHierarchy H;
+  const Workspace w = carve_solve(base, prob, o, S, &H);
   SolveOut out{iters_host, status_host, relres_host, ens_iters_host, nullptr};
-  return run_solve(prob, o, S, V_dev, b_dev, 0, x_dev, w, (hipStream_t)stream, out, POLL_SYNC);
+  return run_solve(prob, o, S, V_dev, b_dev, 0, x_dev, w, (hipStream_t)stream, out, POLL_SYNC, &H);
 }
 
 int ens_spmv(const ens_problem* prob, int32_t S, const double* V_dev, const double* p_dev,
@@ -851,6 +1073,71 @@ int ens_cheb_apply(const ens_problem* prob, const ens_opts* opts, int32_t S, con
   double* zf = cheb_apply(V_dev, w, g, o.degree, true, false, s);
   HIPCHECK(hipGetLastError());
   HIPCHECK(hipMemcpyAsync(z_dev, zf, sizeof(double) * g.nelem, hipMemcpyDeviceToDevice, s));
+  double lm[kMaxS];
+  HIPCHECK(hipMemcpyAsync(lm, w.m.lmax, sizeof(double) * S, hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  if (lmax_host) std::memcpy(lmax_host, lm, sizeof(double) * S);
+  return ENS_OK;
+}
+
+int ens_mg_apply(const ens_problem* prob, const ens_opts* opts, int32_t S, const double* V_dev,
+                 const double* r_dev, double* z_dev, double* lmax_host, void* ws_dev, size_t ws_bytes,
+                 void* stream) {
+  int rc = check_problem(prob);
+  if (rc) return rc;
+  ens_opts oo;
+  if (opts) oo = *opts;
+  else std::memset(&oo, 0, sizeof(oo));
+  oo.precond = ENS_PRECOND_MULTIGRID;
+  Opts o;
+  rc = resolve_opts(&oo, o);
+  if (rc) return rc;
+  if (!valid_S(S) || !V_dev || !r_dev || !z_dev || !ws_dev) return ENS_EINVAL;
+  rc = check_precond(prob, o);
+  if (rc) return rc;
+  if (ws_bytes < solve_bytes(prob, o, S)) return ENS_ENOMEM;
+  MgHierarchy H;
+  const Workspace w = carve_solve(ws_dev, prob, o, S, &H);
+  const Geometry g = geometry_for(prob, o, S);
+  hipStream_t s = (hipStream_t)stream;
+  mg_bind_fine(H, V_dev, w, g);
+  mg_setup(H, w, o.ratio, s);
+  hipLaunchKernelGGL(clear_ctl_kernel, dim3(1), dim3(64), 0, s, w.m.ctl);
+  InitArgs ia;
+  std::memset(&ia, 0, sizeof(ia));
+  ia.V = V_dev;
+  ia.b = r_dev;
+  ia.x = w.p[1];
+  ia.p0 = w.p[0];
+  ia.r = w.r;
+  ia.partial = w.partial;
+  ia.m = w.m;
+  ia.g = g;
+  ia.max_iter = 1;
+  ia.cheb = 1;
+  ia.cheb_degree = kMgDegree;
+  ia.cheb_ratio = o.ratio;
+  launch_init(ia, init_groups(g), s);
+  {
+    FinishArgs f;
+    std::memset(&f, 0, sizeof(f));
+    f.partial = w.partial;
+    f.G = init_groups(g);
+    f.kind = F_INIT;
+    f.m = w.m;
+    f.g = g;
+    f.cheb = 1;
+    f.cheb_degree = kMgDegree;
+    f.cheb_ratio = o.ratio;
+    f.max_iter = 1;
+    launch_finish(f, s);
+  }
+  // every member is preconditioned, whatever its residual
+  hipLaunchKernelGGL(clear_ctl_kernel, dim3(1), dim3(64), 0, s, w.m.ctl);
+  launch_cheb_start(V_dev, w.r, w.d, w.z[0], w.m, g, init_groups(g), s);
+  mg_apply(H, w, true, s);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipMemcpyAsync(z_dev, w.z[1], sizeof(double) * g.nelem, hipMemcpyDeviceToDevice, s));
   double lm[kMaxS];
   HIPCHECK(hipMemcpyAsync(lm, w.m.lmax, sizeof(double) * S, hipMemcpyDeviceToHost, s));
   HIPCHECK(hipStreamSynchronize(s));
@@ -1081,11 +1368,13 @@ int ens_adjoint_grad(const ens_problem* prob, const ens_opts* opts, int32_t S, c
     return ENS_EINVAL;
   rc = check_params(y_host, S, prob->d);
   if (rc) return rc;
-  const bool cheb = o.precond == ENS_PRECOND_CHEBYSHEV;
-  if (ws_bytes < workspace_bytes(rows_of(prob), S, cheb)) return ENS_ENOMEM;
-  const Workspace w = carve_workspace(ws_dev, rows_of(prob), S, cheb);
+  rc = check_precond(prob, o);
+  if (rc) return rc;
+  if (ws_bytes < solve_bytes(prob, o, S)) return ENS_ENOMEM;
+  MgHierarchy H;
+  const Workspace w = carve_solve(ws_dev, prob, o, S, &H);
   SolveOut out{iters_host, status_host, nullptr, nullptr, nullptr};
-  rc = run_solve(prob, o, S, V_dev, w_dev, 1, lambda_dev, w, (hipStream_t)stream, out);
+  rc = run_solve(prob, o, S, V_dev, w_dev, 1, lambda_dev, w, (hipStream_t)stream, out, POLL_ASYNC, &H);
   if (rc) return rc;
   rc = stage_params(w, y_host, S, prob->d, (hipStream_t)stream);
   if (rc) return rc;

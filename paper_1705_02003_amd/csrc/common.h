@@ -99,8 +99,9 @@ struct AsmArgs {
 // M_CHEB1: the residual update r -= alpha q fused with the first Chebyshev
 // step (the ring holds z_0 = D^-1 r / theta formed from r, q and the
 // diagonal; r is written to a second buffer, since neighbouring tiles still
-// read the old one)
-enum Mode { M_SPMV = 0, M_PCG_J = 1, M_PCG_Z = 2, M_CHEB = 3, M_CHEB1 = 4 };
+// read the old one).  M_RESID (3-D): q = r - A src, and with cheb_init the
+// smoother start d = zout = D^-1 q / theta.
+enum Mode { M_SPMV = 0, M_PCG_J = 1, M_PCG_Z = 2, M_CHEB = 3, M_CHEB1 = 4, M_RESID = 5 };
 
 struct StencilArgs {
   const double* V;

@@ -18,7 +18,9 @@
 //            q = A p with the partial sums of p^T q;
 //   M_SPMV:  q = A p;
 //   M_CHEB:  one Chebyshev step d = c1 d + c2 D^-1 (r - A z), z_out = z + d,
-//            on the last step with the partial sums of r^T z_out.
+//            on the last step with the partial sums of r^T z_out;
+//   M_RESID: the residual q = r - A x of a multigrid level, optionally with
+//            its smoother's start d = z_out = D^-1 q / theta.
 // The neighbours' values of the product come through the caches (a point's
 // 27 neighbours lie on three planes of the grid, all near in memory); of the
 // 27 matrix values of a row, the 14 of slots 13..26 are read and the other
@@ -490,6 +492,21 @@ void fe3d_stencil_kernel(StencilArgs a) {
 #pragma unroll
         for (int c = 0; c < VEC; ++c) acc[c] = fma(own[u][c], q[u][c], acc[c]);
         st<VEC>(a.q + e, q[u]);
+      } else if constexpr (MODE == M_RESID) {
+        double rr[VEC];
+        ld<VEC>(rr, a.r + e);
+#pragma unroll
+        for (int c = 0; c < VEC; ++c) rr[c] = rr[c] - q[u][c];
+        st<VEC>(a.q + e, rr);
+        if (a.cheb_init) {
+          double dg[VEC], zn[VEC];
+          ld<VEC>(dg, a.V + (size_t)g.cslot * vs + e);
+#pragma unroll
+          for (int c = 0; c < VEC; ++c)
+            zn[c] = (rr[c] / dg[c]) / gload(&a.m.cheb[(size_t)(sv + c) * kChebCoef]);
+          st<VEC>(a.d + e, zn);
+          st<VEC>(a.zout + e, zn);
+        }
       } else {  // M_CHEB
         // the step's coefficients and the diagonal are loaded again here
         // (cached) rather than held in registers across the sweep, which
@@ -551,5 +568,6 @@ template void launch_fe3d<M_SPMV>(const StencilArgs&, hipStream_t);
 template void launch_fe3d<M_PCG_J>(const StencilArgs&, hipStream_t);
 template void launch_fe3d<M_PCG_Z>(const StencilArgs&, hipStream_t);
 template void launch_fe3d<M_CHEB>(const StencilArgs&, hipStream_t);
+template void launch_fe3d<M_RESID>(const StencilArgs&, hipStream_t);
 
 }  // namespace ens

@@ -1,0 +1,108 @@
+// Geometric multigrid for the 3-D model (multigrid.hip): the level
+// hierarchy in the workspace, the kernels' arguments and launchers.
+#pragma once
+
+#include "common.h"
+
+namespace ens {
+
+constexpr int kMgMaxLevels = 12;   // n + 1 = 2^k cells, k <= 12
+constexpr double kMgRatio = 30.0;  // default lambda_max / lambda_min of the smoother
+constexpr int kMgDegree = 2;       // smoother degree
+
+// One level of the V-cycle: its operator (27 slots) and vectors, and the
+// per-member smoother coefficients (Members::cheb, Members::lmax; every
+// other member field of a coarse level is unused; ctl is the solve's).
+struct MgLevel {
+  int m;          // interior nodes per direction
+  Geometry g;     // 3-D geometry of m^3 rows (full 27-value reads on coarse levels)
+  const double* V;
+  const double* b;  // right-hand side of the level's correction equation
+  double* x;        // the level's V-cycle output
+  double* res;      // residual b - A x
+  double* d;        // smoother increment
+  double* za;       // smoother iterate (started by the caller)
+  double* zb;       // post-smoother output
+  Members mem;
+};
+
+struct MgHierarchy {
+  int L;   // levels, fine first; level L - 1 has one node and is solved exactly
+  MgLevel lv[kMgMaxLevels];
+};
+
+// nodes per direction of each level (n, (n - 1) / 2, ..., 1); 0 if n + 1 is
+// not a power of two >= 2 or there would be more than kMgMaxLevels levels
+int mg_levels(int n, int* ms);
+// bytes of the coarse levels (1 .. L - 1) for an ensemble of S members
+size_t mg_bytes(int n, int S);
+// carve the coarse levels from `base` (mg_bytes(n, S) bytes); level 0's
+// fields are left for the caller
+void mg_carve(void* base, int n, int S, const int* ctl, MgHierarchy& H);
+
+struct MgRapArgs {
+  const double* Vf;  // fine operator, 27 slots of stride vstride_f
+  double* Vc;        // coarse operator, 27 slots of stride vstride_c
+  int mc, S, Sp;     // coarse nodes per direction, members, member slots
+  size_t nrc, vstride_f, vstride_c;
+};
+
+struct MgGershArgs {
+  const double* V;   // 27 slots
+  double* partial;   // [groups][Sp] per-workgroup maxima of sum_j |a_ij| / a_ii
+  int S, Sp;
+  size_t nr, vstride;
+};
+
+struct MgCoefArgs {
+  const double* partial;  // MgGershArgs::partial
+  int G, S, Sp;
+  double ratio;
+  double* lmax;   // [Sp]
+  double* cheb;   // [Sp][kChebCoef]: theta, then c1, c2 of the one step of degree 2
+};
+
+enum MgTransfer { MG_RESTRICT = 0, MG_RESTRICT_START = 1, MG_RESTRICT_SOLVE = 2, MG_PROLONG = 3 };
+
+struct MgTransferArgs {
+  const double* fine_in;   // restriction: the fine residual
+  double* coarse_out;      // restriction: the coarse right-hand side
+  const double* coarse_in; // prolongation: the coarse correction
+  double* fine_x;          // prolongation: the fine iterate, corrected in place
+  const double* Vc;        // restriction with start or solve: the coarse operator (diagonal slot)
+  const double* cheb;      // restriction with start: the coarse smoother's theta per member
+  double* d;               // restriction with start: d = z = D^-1 b / theta
+  double* z;
+  double* x;               // restriction with solve: x = b / a (one node)
+  const int* done;
+  int op;                  // MgTransfer
+  int mc, S, Sp;
+  size_t vstride_c;
+};
+
+enum MgVecOp { MG_ADD = 0, MG_SOLVE = 1 };
+
+// MG_ADD: x += z; MG_SOLVE: x = b / diag (a level of one node).  With `dot`
+// the partial sums of dot^T x (the PCG residual against the
+// preconditioned one) per workgroup and member slot.
+struct MgVecArgs {
+  const double* b;
+  const double* z;
+  const double* V;   // MG_SOLVE: the diagonal slot 13
+  double* x;
+  const double* dot;
+  double* partial;   // [groups][Sp]
+  const int* done;
+  int op, S, Sp;
+  size_t nr, vstride;
+};
+
+void launch_mg_rap(const MgRapArgs& a, hipStream_t s);
+void launch_mg_gersh(const MgGershArgs& a, int groups, hipStream_t s);
+void launch_mg_coef(const MgCoefArgs& a, hipStream_t s);
+void launch_mg_transfer(const MgTransferArgs& a, hipStream_t s);
+// returns the workgroups launched (the partial sums' G)
+int launch_mg_vec(const MgVecArgs& a, hipStream_t s);
+int mg_groups(size_t nr, int Sp);
+
+}  // namespace ens

@@ -1,0 +1,339 @@
+// Geometric multigrid V-cycle for the 3-D model, a CG preconditioner of the
+// kind the paper's numerical tests use (Section 4: CG with a multigrid
+// hierarchy, a degree-2 Chebyshev smoother on every level and a direct solve
+// on the coarsest).  On the structured trilinear mesh of n + 1 = 2^k cells
+// per direction the levels halve the cells down to 2 (one interior node,
+// solved exactly); prolongation P is trilinear interpolation, restriction
+// its transpose, and the coarse operators are the Galerkin products P^T A P,
+// formed per member on the device.  The smoothing steps and residuals run in
+// the 3-D product kernel (fe3d.hip); this file holds the Galerkin product,
+// the smoothers' spectral bounds and coefficients, the grid transfers and
+// the level-wise vector kernels.
+//
+// Layout as everywhere: member innermost, X[r * S + s], V[k * L + r * S + s]
+// with the 27 slots k = 9 (dk + 1) + 3 (dj + 1) + (di + 1).  One thread per
+// (node, member slot): Sp = 2^ceil(log2 S) slots per node, kNT / Sp nodes
+// per workgroup and pass; slots s >= S do nothing.  Every kernel that runs
+// inside a solve returns at once when the solve's done flag is up.
+#include <algorithm>
+#include <cstring>
+
+#include "device.h"
+#include "multigrid.h"
+
+namespace ens {
+
+namespace {
+
+// interpolation weight of fine node i from coarse node I (1-based, one
+// direction): 1 at i = 2I, 1/2 at i = 2I -+ 1, else 0
+__device__ __forceinline__ double w1(int i, int I) {
+  const int t = i - 2 * I;
+  return t == 0 ? 1.0 : ((t == 1 || t == -1) ? 0.5 : 0.0);
+}
+
+__device__ __forceinline__ double wt(int t) { return t == 0 ? 1.0 : 0.5; }
+
+struct Lane {
+  size_t p, pstride;   // first node, node stride of the grid-strided loop
+  int s;               // member slot
+  bool ok;             // s < S
+};
+
+__device__ __forceinline__ Lane lane_of(int Sp, int S) {
+  Lane l;
+  const int t = threadIdx.x, per = kNT / Sp;
+  l.s = t % Sp;
+  l.ok = l.s < S;
+  l.p = (size_t)blockIdx.x * per + t / Sp;
+  l.pstride = (size_t)gridDim.x * per;
+  return l;
+}
+
+__device__ __forceinline__ bool is_done(const int* done) { return done && gload(done) != 0; }
+
+}  // namespace
+
+// ------------------------------------------------------------ Galerkin product
+// Ac(I, I + delta) = sum over fine nodes i = 2I + f and their neighbours
+// j = i + e of w(f) A(i, j) w(f + e - 2 delta), f, e, delta in {-1, 0, 1}^3,
+// w the product of the per-direction weights (1 at offset 0, 1/2 at +-1).
+// Coarse neighbours outside the grid get 0, as the fine slots of neighbours
+// outside do (those fine values are 0 and add nothing).  One thread per
+// (coarse node, member); the 27 sums stay in registers (the loops that index
+// them are unrolled).
+__global__ __launch_bounds__(kNT) void mg_rap_kernel(MgRapArgs a) {
+  const int mc = a.mc, mf = 2 * mc + 1, S = a.S;
+  const Lane l = lane_of(a.Sp, S);
+  if (!l.ok) return;
+  for (size_t pc = l.p; pc < a.nrc; pc += l.pstride) {
+    const int I = (int)(pc % mc) + 1, J = (int)((pc / mc) % mc) + 1, K = (int)(pc / ((size_t)mc * mc)) + 1;
+    double acc[27];
+#pragma unroll
+    for (int k = 0; k < 27; ++k) acc[k] = 0.0;
+    for (int fz = -1; fz <= 1; ++fz)
+      for (int fy = -1; fy <= 1; ++fy)
+        for (int fx = -1; fx <= 1; ++fx) {
+          // fine node 2I + f is always interior: 1 <= 2I + f <= 2 mc + 1
+          const double wi = wt(fx) * wt(fy) * wt(fz);
+          const size_t rf = ((size_t)(2 * K + fz - 1) * mf + (2 * J + fy - 1)) * mf + (2 * I + fx - 1);
+          for (int ez = -1; ez <= 1; ++ez)
+            for (int ey = -1; ey <= 1; ++ey)
+              for (int ex = -1; ex <= 1; ++ex) {
+                const int slot = 9 * (ez + 1) + 3 * (ey + 1) + (ex + 1);
+                const double v = gload(&a.Vf[(size_t)slot * a.vstride_f + rf * S + l.s]);
+                if (v == 0.0) continue;
+                const double wv = wi * v;
+                const int rx = fx + ex, ry = fy + ey, rz = fz + ez;   // j - 2I, in [-2, 2]
+#pragma unroll
+                for (int dz = -1; dz <= 1; ++dz) {
+#pragma unroll
+                  for (int dy = -1; dy <= 1; ++dy) {
+#pragma unroll
+                    for (int dx = -1; dx <= 1; ++dx) {
+                      const int tx = rx - 2 * dx, ty = ry - 2 * dy, tz = rz - 2 * dz;
+                      const bool near = tx >= -1 && tx <= 1 && ty >= -1 && ty <= 1 && tz >= -1 && tz <= 1;
+                      const double wj = wt(tx) * wt(ty) * wt(tz);
+                      const int k = 9 * (dz + 1) + 3 * (dy + 1) + (dx + 1);
+                      acc[k] = near ? fma(wv, wj, acc[k]) : acc[k];
+                    }
+                  }
+                }
+              }
+        }
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int k = 9 * (dz + 1) + 3 * (dy + 1) + (dx + 1);
+          const bool in = I + dx >= 1 && I + dx <= mc && J + dy >= 1 && J + dy <= mc && K + dz >= 1 &&
+                          K + dz <= mc;
+          gstore(&a.Vc[(size_t)k * a.vstride_c + pc * S + l.s], in ? acc[k] : 0.0);
+        }
+  }
+}
+
+// ------------------------------------------------------------ smoother bounds
+// Per member the Gershgorin bound max_i sum_j |a_ij| / a_ii of D^-1 A on a
+// level, as per-workgroup maxima.
+__global__ __launch_bounds__(kNT) void mg_gersh_kernel(MgGershArgs a) {
+  __shared__ double red[kWaves * 64];
+  const Lane l = lane_of(a.Sp, a.S);
+  double acc[1] = {0.0};
+  for (size_t p = l.p; l.ok && p < a.nr; p += l.pstride) {
+    const size_t e = p * a.S + l.s;
+    double rs = 0.0;
+#pragma unroll
+    for (int k = 0; k < 27; ++k) rs += fabs(gload(&a.V[(size_t)k * a.vstride + e]));
+    acc[0] = fmax(acc[0], rs / gload(&a.V[(size_t)13 * a.vstride + e]));
+  }
+  group_max<1>(acc, a.Sp, red);
+  put_partial<1>(a.partial, a.Sp, a.Sp, acc);
+}
+
+// lambda_max per member and the coefficients of the degree-2 smoother on
+// [lambda_max / ratio, lambda_max] (theta, delta the interval's centre and
+// half-width, sigma = theta / delta, rho0 = 1 / sigma, rho1 = 1 / (2 sigma -
+// rho0); the one step uses rho1 rho0 and 2 rho1 / delta); idle slots get
+// theta = 1 and zero steps.
+__global__ __launch_bounds__(kFinNT) void mg_coef_kernel(MgCoefArgs a) {
+  __shared__ double fin[kFinNT];
+  const int t = threadIdx.x;
+  const double lmax = final_max(a.partial, a.G, a.Sp, fin);
+  if (t >= a.Sp) return;
+  double* cf = a.cheb + (size_t)t * kChebCoef;
+  if (t >= a.S) {
+    gstore(&a.lmax[t], 0.0);
+    gstore(&cf[0], 1.0);
+    for (int k = 1; k < kChebCoef; ++k) gstore(&cf[k], 0.0);
+    return;
+  }
+  const double lmin = lmax / a.ratio;
+  const double theta = (lmax + lmin) / 2.0;
+  const double delta = (lmax - lmin) / 2.0;
+  const double sigma1 = theta / delta;
+  const double rho0 = 1.0 / sigma1;
+  const double rho1 = 1.0 / (2.0 * sigma1 - rho0);
+  gstore(&a.lmax[t], lmax);
+  gstore(&cf[0], theta);
+  gstore(&cf[1], rho1 * rho0);
+  gstore(&cf[2], 2.0 * rho1 / delta);
+  for (int k = 3; k < kChebCoef; ++k) gstore(&cf[k], 0.0);
+}
+
+// ------------------------------------------------------------ grid transfer
+// Restriction b_c(I) = sum_f w(f) res(2I + f), one thread per (coarse node,
+// member).  MG_RESTRICT_START also starts the coarse pre-smoother,
+// d = z = D_c^-1 b_c / theta; MG_RESTRICT_SOLVE solves the one-node coarsest
+// level, x = b_c / a.
+__global__ __launch_bounds__(kNT) void mg_restrict_kernel(MgTransferArgs a) {
+  if (is_done(a.done)) return;
+  const int mc = a.mc, mf = 2 * mc + 1, S = a.S;
+  const size_t nrc = (size_t)mc * mc * mc;
+  const Lane l = lane_of(a.Sp, S);
+  if (!l.ok) return;
+  const double th = (a.op == MG_RESTRICT_START) ? gload(&a.cheb[(size_t)l.s * kChebCoef]) : 1.0;
+  for (size_t pc = l.p; pc < nrc; pc += l.pstride) {
+    const int I = (int)(pc % mc) + 1, J = (int)((pc / mc) % mc) + 1, K = (int)(pc / ((size_t)mc * mc)) + 1;
+    double acc = 0.0;
+    for (int fz = -1; fz <= 1; ++fz)
+      for (int fy = -1; fy <= 1; ++fy)
+#pragma unroll
+        for (int fx = -1; fx <= 1; ++fx) {
+          const size_t rf = ((size_t)(2 * K + fz - 1) * mf + (2 * J + fy - 1)) * mf + (2 * I + fx - 1);
+          acc = fma(wt(fx) * wt(fy) * wt(fz), gload(&a.fine_in[rf * S + l.s]), acc);
+        }
+    const size_t e = pc * S + l.s;
+    gstore(&a.coarse_out[e], acc);
+    if (a.op == MG_RESTRICT_START) {
+      const double z = (acc / gload(&a.Vc[(size_t)13 * a.vstride_c + e])) / th;
+      gstore(&a.d[e], z);
+      gstore(&a.z[e], z);
+    } else if (a.op == MG_RESTRICT_SOLVE) {
+      gstore(&a.x[e], acc / gload(&a.Vc[(size_t)13 * a.vstride_c + e]));
+    }
+  }
+}
+
+// Prolongation and correction x_f(i) += sum_I w(i - 2I) x_c(I) over the up
+// to eight coarse nodes I in [floor(i / 2), ceil(i / 2)]^3 (1-based), one
+// thread per (fine node, member).
+__global__ __launch_bounds__(kNT) void mg_prolong_kernel(MgTransferArgs a) {
+  if (is_done(a.done)) return;
+  const int mc = a.mc, mf = 2 * mc + 1, S = a.S;
+  const size_t nrf = (size_t)mf * mf * mf;
+  const Lane l = lane_of(a.Sp, S);
+  if (!l.ok) return;
+  for (size_t pf = l.p; pf < nrf; pf += l.pstride) {
+    const int i = (int)(pf % mf) + 1, j = (int)((pf / mf) % mf) + 1, k = (int)(pf / ((size_t)mf * mf)) + 1;
+    double acc = 0.0;
+    for (int cz = k / 2; cz <= (k + 1) / 2; ++cz)
+      for (int cy = j / 2; cy <= (j + 1) / 2; ++cy)
+        for (int cx = i / 2; cx <= (i + 1) / 2; ++cx) {
+          if (cx < 1 || cx > mc || cy < 1 || cy > mc || cz < 1 || cz > mc) continue;
+          const size_t pc = ((size_t)(cz - 1) * mc + (cy - 1)) * mc + (cx - 1);
+          acc = fma(w1(i, cx) * w1(j, cy) * w1(k, cz), gload(&a.coarse_in[pc * S + l.s]), acc);
+        }
+    const size_t e = pf * S + l.s;
+    gstore(&a.fine_x[e], gload(&a.fine_x[e]) + acc);
+  }
+}
+
+// ------------------------------------------------------------ level vectors
+// MG_ADD: x += z; MG_SOLVE: x = b / diag; with `dot` the per-workgroup
+// partial sums of dot^T x per member slot.
+__global__ __launch_bounds__(kNT) void mg_vec_kernel(MgVecArgs a) {
+  __shared__ double red[kWaves * 64];
+  if (is_done(a.done)) return;
+  const Lane l = lane_of(a.Sp, a.S);
+  double acc[1] = {0.0};
+  for (size_t p = l.p; l.ok && p < a.nr; p += l.pstride) {
+    const size_t e = p * a.S + l.s;
+    double x;
+    if (a.op == MG_ADD) x = gload(&a.x[e]) + gload(&a.z[e]);
+    else x = gload(&a.b[e]) / gload(&a.V[(size_t)13 * a.vstride + e]);
+    gstore(&a.x[e], x);
+    if (a.dot) acc[0] = fma(gload(&a.dot[e]), x, acc[0]);
+  }
+  if (a.dot) {
+    group_reduce<1>(acc, a.Sp, red);
+    put_partial<1>(a.partial, a.Sp, a.Sp, acc);
+  }
+}
+
+// ------------------------------------------------------------ hierarchy
+int mg_levels(int n, int* ms) {
+  if (n < 1 || ((n + 1) & n) != 0) return 0;
+  int L = 0, m = n;
+  while (true) {
+    if (L == kMgMaxLevels) return 0;
+    ms[L++] = m;
+    if (m == 1) break;
+    m = (m - 1) / 2;
+  }
+  return L;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+static size_t mg_header_bytes() {
+  return align256(sizeof(double) * (size_t)kMgMaxLevels * kMaxS * (kChebCoef + 1));
+}
+// the coarse level's 27 slots and six vectors
+static size_t mg_level_doubles(int m, int S) {
+  const size_t nr = (size_t)m * m * m;
+  return slot_stride(nr * S) * (27 + 6);
+}
+
+size_t mg_bytes(int n, int S) {
+  int ms[kMgMaxLevels];
+  const int L = mg_levels(n, ms);
+  if (L == 0) return 0;
+  size_t b = mg_header_bytes();
+  for (int l = 1; l < L; ++l) b += sizeof(double) * mg_level_doubles(ms[l], S);
+  return b;
+}
+
+void mg_carve(void* base, int n, int S, const int* ctl, MgHierarchy& H) {
+  int ms[kMgMaxLevels];
+  H.L = mg_levels(n, ms);
+  double* hd = static_cast<double*>(base);
+  char* p = static_cast<char*>(base) + mg_header_bytes();
+  for (int l = 0; l < H.L; ++l) {
+    MgLevel& v = H.lv[l];
+    std::memset(&v, 0, sizeof(v));
+    v.m = ms[l];
+    v.g = make_geometry3(ms[l], S);
+    if (l == 0) continue;
+    v.g.full = 1;   // the Galerkin products are used as computed
+    v.mem.cheb = hd + (size_t)l * kMaxS * kChebCoef;
+    v.mem.lmax = hd + (size_t)kMgMaxLevels * kMaxS * kChebCoef + (size_t)l * kMaxS;
+    v.mem.ctl = const_cast<int*>(ctl);
+    double* q = reinterpret_cast<double*>(p);
+    const size_t vs = v.g.vstride;
+    v.V = q;
+    double* vec = q + 27 * vs;
+    v.b = vec;
+    v.x = vec + vs;
+    v.res = vec + 2 * vs;
+    v.d = vec + 3 * vs;
+    v.za = vec + 4 * vs;
+    v.zb = vec + 5 * vs;
+    p += sizeof(double) * mg_level_doubles(ms[l], S);
+  }
+}
+
+// ------------------------------------------------------------ launchers
+int mg_groups(size_t nr, int Sp) {
+  const size_t per = (size_t)(kNT / Sp);
+  return (int)std::min<size_t>(std::max<size_t>((nr + per - 1) / per, 1), 1024);
+}
+
+void launch_mg_rap(const MgRapArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(mg_rap_kernel, dim3(mg_groups(a.nrc, a.Sp)), dim3(kNT), 0, s, a);
+}
+
+void launch_mg_gersh(const MgGershArgs& a, int groups, hipStream_t s) {
+  hipLaunchKernelGGL(mg_gersh_kernel, dim3(groups), dim3(kNT), 0, s, a);
+}
+
+void launch_mg_coef(const MgCoefArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(mg_coef_kernel, dim3(1), dim3(kFinNT), 0, s, a);
+}
+
+void launch_mg_transfer(const MgTransferArgs& a, hipStream_t s) {
+  const size_t mc = (size_t)a.mc, mf = 2 * mc + 1;
+  if (a.op == MG_PROLONG)
+    hipLaunchKernelGGL(mg_prolong_kernel, dim3(mg_groups(mf * mf * mf, a.Sp)), dim3(kNT), 0, s, a);
+  else
+    hipLaunchKernelGGL(mg_restrict_kernel, dim3(mg_groups(mc * mc * mc, a.Sp)), dim3(kNT), 0, s, a);
+}
+
+int launch_mg_vec(const MgVecArgs& a, hipStream_t s) {
+  const int G = mg_groups(a.nr, a.Sp);
+  hipLaunchKernelGGL(mg_vec_kernel, dim3(G), dim3(kNT), 0, s, a);
+  return G;
+}
+
+}  // namespace ens

@@ -44,7 +44,7 @@ class Problem:
 
 @dataclass
 class SolverOptions:
-    precond: str = "jacobi"       # "jacobi" or "chebyshev"
+    precond: str = "jacobi"       # "jacobi", "chebyshev" or "multigrid" (3-D, n + 1 = 2^k)
     cheb_degree: int = 4
     cheb_ratio: float = 30.0
     rtol: float = 1e-8
@@ -57,7 +57,8 @@ class SolverOptions:
     full_stencil: bool = False    # read all nine matrix values (no symmetric reuse)
 
     def c(self) -> L.ens_opts:
-        pre = {"jacobi": L.PRECOND_JACOBI, "chebyshev": L.PRECOND_CHEBYSHEV}[self.precond]
+        pre = {"jacobi": L.PRECOND_JACOBI, "chebyshev": L.PRECOND_CHEBYSHEV,
+               "multigrid": L.PRECOND_MULTIGRID}[self.precond]
         return L.ens_opts(pre, self.cheb_degree, float(self.cheb_ratio), float(self.rtol),
                           self.max_iter, self.poll_every, self.tile_lines, self.max_groups,
                           (L.FLAG_TIME_SPMV if self.time_spmv else 0)
@@ -264,6 +265,25 @@ def cheb_apply(prob: Problem, V: torch.Tensor, r: torch.Tensor,
     return z, lmax
 
 
+def mg_apply(prob: Problem, V: torch.Tensor, r: torch.Tensor,
+             opts: Optional[SolverOptions] = None, ws: Optional[torch.Tensor] = None):
+    """z = V(r), one multigrid V-cycle (3-D model, n + 1 a power of two);
+    returns (z, fine-level lambda_max per member)."""
+    opts = opts or SolverOptions(precond="multigrid")
+    S = _ensemble_width(r)
+    _require_matrix(V, prob, S)
+    _require_cuda(r, "r", (prob.rows, S))
+    if ws is None:
+        ws = workspace(prob, S, SolverOptions(precond="multigrid"), r.device)
+    z = torch.empty_like(r)
+    lmax = np.zeros(S, np.float64)
+    pc, oc = prob.c(), opts.c()
+    L.check(L.lib().ens_mg_apply(C.byref(pc), C.byref(oc), S, _p(V), _p(r), _p(z),
+                                 lmax.ctypes.data_as(L.f64p), _p(ws), ws.numel(),
+                                 _stream(r.device)), "ens_mg_apply")
+    return z, lmax
+
+
 def member_dot(a: torch.Tensor, b: torch.Tensor, ws: Optional[torch.Tensor] = None) -> np.ndarray:
     """Per-member dot products; b may be (N_r, S) or a shared (N_r,) vector."""
     S = _ensemble_width(a)
@@ -369,7 +389,7 @@ class BatchResult(NamedTuple):
 
 
 def batch_solve(items, opts: Optional[SolverOptions] = None, batch_ws: Optional[torch.Tensor] = None,
-                max_wave_bytes: Optional[float] = None):
+                max_wave_bytes="auto"):
     """Solve several ensembles together (ens_batch_solve).
 
     ``items``: sequence of dicts with keys ``prob`` (Problem), ``V``, ``b`` and
@@ -379,9 +399,15 @@ def batch_solve(items, opts: Optional[SolverOptions] = None, batch_ws: Optional[
     ``max_wave_bytes``: solve the ensembles in waves instead of all at once,
     smallest first: ensembles sorted by the bytes one CG iteration moves
     (120 B per member-row) and packed greedily into waves of at most that
-    many bytes (a larger ensemble forms a wave of its own).  The total time
-    stays about the same, but the small ensembles retire early.  A result's
-    ``seconds`` then counts from the start of the first wave."""
+    many bytes (a larger ensemble forms a wave of its own).  The small
+    ensembles retire early.  "auto" (the default) takes the autotuner's wave
+    size (``autotune.tune_wave``), None solves all ensembles in one batch.
+    A result's ``seconds`` then counts from the start of the first wave."""
+    if isinstance(max_wave_bytes, str):
+        if max_wave_bytes != "auto":
+            raise ValueError("max_wave_bytes: a number of bytes, 'auto' or None")
+        from . import autotune
+        max_wave_bytes = autotune.tune_wave()["wave_bytes"] if len(items) > 1 else None
     if max_wave_bytes is not None and len(items) > 1:
         cost = [120 * it["prob"].rows * _ensemble_width(it["b"]) for it in items]
         order = sorted(range(len(items)), key=lambda i: (cost[i], i))
@@ -398,7 +424,7 @@ def batch_solve(items, opts: Optional[SolverOptions] = None, batch_ws: Optional[
         t0 = time.perf_counter()
         for wv in waves:
             start = time.perf_counter() - t0
-            for i, r in zip(wv, batch_solve([items[i] for i in wv], opts, batch_ws)):
+            for i, r in zip(wv, batch_solve([items[i] for i in wv], opts, batch_ws, None)):
                 out[i] = r._replace(seconds=start + r.seconds)
         return out
     opts = opts or SolverOptions()

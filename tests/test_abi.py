@@ -387,3 +387,50 @@ def test_non_finite_parameters_rejected_before_device_work(L, bad):
     # n = 2: no interior node lies in [0.4, 0.6] (5 i in [6, 9] has no solution)
     assert lib.ens_qoi_weights(C.byref(L.ens_problem(2, 4, 0, 2, 0.4)), C.c_void_p(256),
                                None) == L.ENS_EINVAL
+
+
+def test_multigrid_descriptor_without_gpu(L):
+    """ENS_PRECOND_MULTIGRID: the workspace adds the coarse levels (a header of
+    per-level smoother coefficients, then per level 27 matrix slots and six
+    vectors of the level's slot stride); the 2-D model and grids with n + 1
+    not a power of two are refused before any device work."""
+    lib = L.lib()
+    o = L.ens_opts()
+    o.precond = L.PRECOND_MULTIGRID
+    oc = L.ens_opts()
+    oc.precond = L.PRECOND_CHEBYSHEV
+
+    def stride(m, S):
+        return ((m ** 3 * S + 31) // 32) * 32 + 512
+
+    for n, S in ((15, 8), (31, 32), (3, 1), (63, 64)):
+        p = L.ens_problem(n, 4, 0, 3, 0.0)
+        ws = lib.ens_pcg_workspace_bytes(C.byref(p), C.byref(o), S)
+        wc = lib.ens_pcg_workspace_bytes(C.byref(p), C.byref(oc), S)
+        levels, m = [], n
+        while m > 1:
+            m = (m - 1) // 2
+            levels.append(m)
+        head = ((8 * 12 * 64 * (2 * 8 + 2 + 1) + 255) // 256) * 256
+        assert ws - wc == head + sum(8 * 33 * stride(m, S) for m in levels), (n, S)
+    a = C.c_void_p(4096)
+    for bad in (L.ens_problem(10, 4, 0, 3, 0.0), L.ens_problem(31, 4, 0, 2, 0.4),
+                L.ens_problem(16, 4, 0, 3, 0.0)):
+        assert lib.ens_pcg_workspace_bytes(C.byref(bad), C.byref(o), 8) == 0
+        assert lib.ens_pcg_solve(C.byref(bad), C.byref(o), 8, a, a, a, None, None, None, None, None,
+                                 a, 1 << 40, None) == L.ENS_ENOTSUP
+        assert lib.ens_pcg_solve_noalloc(C.byref(bad), C.byref(o), 8, a, a, a, None, None, None, None,
+                                         None) == L.ENS_ENOTSUP
+        assert lib.ens_mg_apply(C.byref(bad), None, 8, a, a, a, None, a, 1 << 40, None) == L.ENS_ENOTSUP
+    p = L.ens_problem(15, 4, 0, 3, 0.0)
+    assert lib.ens_mg_apply(C.byref(p), None, 8, a, a, a, None, a, 16, None) == L.ENS_ENOMEM
+    assert lib.ens_mg_apply(C.byref(p), None, 65, a, a, a, None, a, 1 << 40, None) == L.ENS_EINVAL
+    # the batched solver is Jacobi-only
+    items = (L.ens_batch_item * 1)()
+    it = items[0]
+    it.prob = L.ens_problem(16, 4, 0, 2, 0.4)
+    it.S = 8
+    it.V_dev = it.b_dev = it.x_dev = it.ws_dev = 4096
+    it.ws_bytes = 1 << 40
+    nb = lib.ens_batch_workspace_bytes(1)
+    assert lib.ens_batch_solve(C.byref(o), 1, items, a, nb, None) == L.ENS_ENOTSUP

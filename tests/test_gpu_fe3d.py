@@ -305,7 +305,7 @@ def test_param_indicator_matches_oracle(dim, m, S, d, eps_model):
                                     else oprob.param_indicator(many[149], eps_model), rel=1e-13)
 
 
-def test2_samples(S, d, seed):
+def banded_samples(S, d, seed):
     """Samples spread over Test 2's three bands of |y| (and two exactly on
     the band edges, where the decision must follow the inequalities)."""
     rng = np.random.default_rng(seed)
@@ -326,7 +326,7 @@ def test_test2_assembly_solve_and_indicator(m, S, d, seed):
     and the grouping indicator."""
     log_case(test="fe3d-test2", m=m, S=S, d=d)
     ens = E()
-    ys = test2_samples(S, d, seed)
+    ys = banded_samples(S, d, seed)
     prob = ens.Problem(m, d, 1, dim=3)
     V, b = ens.assemble(prob, ys)
     Vh = V.cpu().numpy()
@@ -353,7 +353,7 @@ def test_test2_dqdy_and_adjoint():
     log_case(test="fe3d-test2-adjoint")
     ens = E()
     m, S, d = 7, 8, 4
-    ys = test2_samples(S, d, 53)
+    ys = banded_samples(S, d, 53)
     prob = ens.Problem(m, d, 1, dim=3)
     rng = np.random.default_rng(54)
     U, Lm = rng.standard_normal((m ** 3, S)), rng.standard_normal((m ** 3, S))
