@@ -665,10 +665,11 @@ def fe3d_mode(args) -> int:
     """The paper's 3-D test problem: 32^3 trilinear cells, d = 4 KL terms,
     rtol 1e-7.  The level-2 sparse grid (41 nodes) is solved to build the
     iteration surrogate, the 512 uniform samples (seed 5) are ordered by it
-    into ensembles of S and every ensemble is solved, with Jacobi and with
-    degree-4 Jacobi-Chebyshev, --streams ensembles at a time (default 2) on
-    separate HIP streams; the first ensemble's samples are also solved one at
-    a time (S = 1).  At this size an ensemble's matrix (27 x 8 B per
+    into ensembles of S and every ensemble is solved, with Jacobi, with
+    degree-4 Jacobi-Chebyshev and with the multigrid V-cycle (--precs picks
+    a subset), --streams ensembles at a time (default 2) on separate HIP
+    streams; the first ensemble's samples are also solved one at a time
+    (S = 1).  --test 2 takes the paper's Test 2 coefficient.  At this size an ensemble's matrix (27 x 8 B per
     member-row, 206 MB at S = 32) fits the 256 MB Infinity Cache, so the
     product kernel's rate is partly a cache rate."""
     import numpy as np
@@ -677,8 +678,8 @@ def fe3d_mode(args) -> int:
     from paper_1705_02003_amd import ensemble as E
     from paper_1705_02003_amd import uq
     torch.cuda.set_device(0)
-    w = workloads.FE3D_32
-    prob = E.Problem(w.n, w.d, dim=3)
+    w = workloads.FE3D_32_TEST2 if args.test == 2 else workloads.FE3D_32
+    prob = E.Problem(w.n, w.d, w.eps_model, dim=3)
     ys = workloads.uniform_samples(w.seed, w.n_samples, w.d)
     S = args.S
     # bytes per member-row: direction kernel (r, diagonal, p_old, x in;
@@ -691,7 +692,8 @@ def fe3d_mode(args) -> int:
     out = {"mode": "fe3d", "workload": w.name, "grid": f"{w.n + 1}^3 cells", "S": S,
            "samples": w.n_samples, "rtol": w.rtol, "full_stencil": FULL_STENCIL,
            "step_bytes_per_member_row": step_bytes, "streams": K}
-    for pre in ("jacobi", "chebyshev"):
+    precs = [p for p in args.precs.split(",") if p] if args.precs else ["jacobi", "chebyshev", "multigrid"]
+    for pre in precs:
         opts = E.SolverOptions(precond=pre, rtol=w.rtol, max_iter=w.max_iter, time_spmv=True,
                                full_stencil=FULL_STENCIL)
         uq.nonadaptive(prob, S, ys[:S], 1, opts, solve_groups=[0], streams=K)       # warm-up
@@ -740,10 +742,12 @@ def fe3d_mode(args) -> int:
 def batch_mode(args) -> int:
     """64 ensembles, widths drawn from {4..64}, grids from {256, 512, 1024}^2,
     d = 8 coefficient model (seed 3), Jacobi-PCG rtol 1e-8, solved together by
-    the graph-replayed batched solver.  Launch shapes (member tile width, tile
-    height) come from the autotuner (untimed).  Reports total sample-solves/s
-    and p50 / p99 of the per-ensemble retirement latency.  --wave-gb G solves
-    the ensembles smallest first in waves of at most G GB per CG iteration."""
+    the graph-replayed batched solver, smallest first in waves of the
+    autotuner's size (--wave-gb sets it, -1 one batch).  Launch shapes
+    (member tile width, tile height) and the wave size come from the
+    autotuner (untimed).  Reports total sample-solves/s, p50 / p99 of the
+    per-ensemble retirement latency, and the same ensembles solved one after
+    another in the same run."""
     import numpy as np
     import torch
     import workloads
@@ -756,8 +760,18 @@ def batch_mode(args) -> int:
     widths, grids, samples = draw.widths[:k], draw.grids[:k], draw.samples[:k]
     t0 = time.perf_counter()
     shapes = {key: autotune.tune(*key) for key in sorted(set(zip(grids, widths)))}
+    # smallest-first waves by default, of the autotuner's size; --wave-gb
+    # sets it, --wave-gb -1 solves every ensemble in one batch
+    if args.wave_gb > 0:
+        wave_bytes, wave_src = args.wave_gb * 1e9, "option"
+    elif args.wave_gb < 0:
+        wave_bytes, wave_src = None, "one batch"
+    else:
+        wave_bytes, wave_src = autotune.tune_wave()["wave_bytes"], "autotuned"
     tune_s = time.perf_counter() - t0
-    print(f"[bench] autotuned {len(shapes)} (n, S) shapes in {tune_s:.1f} s", flush=True)
+    print(f"[bench] autotuned {len(shapes)} (n, S) shapes and the wave size "
+          f"({wave_bytes and round(wave_bytes / 1e9, 3)} GB per CG step, {wave_src}) in "
+          f"{tune_s:.1f} s", flush=True)
     # device bytes an ensemble keeps resident: matrix (9 slots), b, x and its
     # Jacobi workspace (5 vectors); if the draw does not fit in 80 % of HBM,
     # it is assembled and solved in residency waves, in draw order
@@ -789,12 +803,12 @@ def batch_mode(args) -> int:
                         "member_tile": sh["member_tile"]}
         torch.cuda.synchronize()
         t = time.perf_counter()
-        out = E.batch_solve([items[i] for i in wave], opts,
-                            max_wave_bytes=args.wave_gb * 1e9 if args.wave_gb > 0 else None)
+        out = E.batch_solve([items[i] for i in wave], opts, max_wave_bytes=wave_bytes)
         torch.cuda.synchronize()
         for i, r in zip(wave, out):
             res[i] = r._replace(seconds=dt + r.seconds)
         dt += time.perf_counter() - t
+        print(f"[bench] batch: {len(wave)} ensembles solved, {dt:.2f} s so far", flush=True)
         if len(residency) > 1:
             for i in wave:
                 items[i] = {"prob": items[i]["prob"], "b_shape": tuple(items[i]["b"].shape)}
@@ -803,7 +817,8 @@ def batch_mode(args) -> int:
     n_samples = int(sum(widths))
     rows = sum(r.ens_iters * E.Problem(n, w.d).rows * S for r, S, n in zip(res, widths, grids))
     out = {"mode": "batch", "workload": w.name, "ensembles": k, "samples": n_samples,
-           "wave_gb": args.wave_gb or None, "resident_GiB": round(sum(need) / 2**30, 1),
+           "wave_gb": wave_bytes and round(wave_bytes / 1e9, 4), "wave_size": wave_src,
+           "resident_GiB": round(sum(need) / 2**30, 1),
            "residency_waves": len(residency),
            "seconds": round(dt, 3), "sample_solves_per_s": round(n_samples / dt, 3),
            "latency_p50_s": round(float(np.percentile(lat, 50)), 4),
@@ -813,14 +828,17 @@ def batch_mode(args) -> int:
            "iteration_alg_GBs": round(rows * ITER_BYTES / dt / 1e9, 1),
            "all_converged": bool(all(np.all(r.status == 0) for r in res)),
            "shapes": {f"{n}x{S}": [v["member_tile"], v["tile_lines"]] for (n, S), v in shapes.items()}}
-    if args.sequential and len(residency) == 1:
+    if not args.no_sequential and len(residency) == 1:
         torch.cuda.synchronize()
         t = time.perf_counter()
-        for it in items:
+        for j, it in enumerate(items):
             E.solve(it["prob"], it["V"], it["b"],
                     E.SolverOptions(rtol=w.rtol, max_iter=w.max_iter, full_stencil=FULL_STENCIL,
                                     tile_lines=it["tile_lines"],
                                     member_tile=it["member_tile"]))
+            if j % 16 == 15:
+                print(f"[bench] sequential: {j + 1} ensembles, {time.perf_counter() - t:.2f} s",
+                      flush=True)
         torch.cuda.synchronize()
         ts = time.perf_counter() - t
         out["sequential_seconds"] = round(ts, 3)
@@ -856,19 +874,21 @@ def main() -> int:
                     help="--mode batch: device memory the draw may keep resident (0: 80 %% of HBM)")
     ap.add_argument("--wave-gb", type=float, default=0.0,
                     help="--mode batch: smallest-first waves of at most this many GB per CG "
-                         "iteration (0: all ensembles in one batch)")
+                         "iteration (0: the autotuner's size; -1: all ensembles in one batch)")
     ap.add_argument("--streams", type=int, default=0,
                     help="ensembles solved at a time on separate HIP streams (0: 2 in --mode fe3d, "
                          "else 1)")
     ap.add_argument("--dim", type=int, default=2, choices=(2, 3),
                     help="--mode table: the 2-D benchmark problem or the 3-D test problem")
+    ap.add_argument("--precs", default="",
+                    help="comma-separated preconditioners of --mode fe3d (default jacobi,chebyshev,multigrid)")
     ap.add_argument("--test", type=int, default=1, choices=(1, 2),
-                    help="--mode table --dim 3: the paper's Test 1 (a_hat = 1) or Test 2 "
-                         "(a_hat banded by |y|)")
+                    help="--mode table --dim 3 and --mode fe3d: the paper's Test 1 (a_hat = 1) "
+                         "or Test 2 (a_hat banded by |y|)")
     ap.add_argument("--full-stencil", action="store_true",
                     help="read all nine matrix values per row (no symmetric reuse)")
-    ap.add_argument("--sequential", action="store_true",
-                    help="--mode batch: also solve the ensembles one after another")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="--mode batch: skip solving the ensembles one after another")
     ap.add_argument("--ensembles", type=int, default=0,
                     help="ensembles to solve in --mode adjoint / cheb (0: the mode's default)")
     ap.add_argument("--all-ensembles", action="store_true",

@@ -124,3 +124,20 @@ def test_batch_in_waves_matches_single_solves():
         assert np.all((num / den)[same] <= 1e-9)
     # the smallest ensemble is in the first wave, the largest in the last
     assert res[int(np.argmin(cost))].seconds <= res[int(np.argmax(cost))].seconds
+
+
+def test_batch_default_waves_equal_one_batch_bitwise():
+    """The default (smallest-first waves of the autotuner's size) gives the
+    same bits as one batch: an ensemble's partial sums land in rows fixed by
+    its own unit indices, whatever else is in the batch."""
+    from paper_1705_02003_amd import autotune
+    from paper_1705_02003_amd import ensemble as E
+    wave = autotune.tune_wave()
+    print("CASE batch auto waves", wave, flush=True)
+    assert wave["wave_bytes"] > 0 and wave["ensembles"] >= 1
+    items, _ = make_batch(seed=4)
+    r_auto = E.batch_solve(items, E.SolverOptions(rtol=1e-8))
+    r_one = E.batch_solve(items, E.SolverOptions(rtol=1e-8), max_wave_bytes=None)
+    for a, b in zip(r_auto, r_one):
+        assert np.array_equal(a.iters, b.iters) and np.array_equal(a.status, b.status)
+        assert torch.equal(a.x, b.x)

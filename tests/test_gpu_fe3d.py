@@ -343,7 +343,16 @@ def test_test2_assembly_solve_and_indicator(m, S, d, seed):
         assert st == CONVERGED and res.status[s] == CONVERGED
         assert abs(int(res.iters[s]) - I) <= 1, (s, res.iters[s], I)
         xe, _, _, _ = opcg.pcg(A, bo, dg, 0.0, int(res.iters[s]))
-        assert np.linalg.norm(x[:, s] - xe) <= 1e-9 * np.linalg.norm(xe)
+        # two FP64 CG runs that round differently drift apart in proportion
+        # to kappa(D^-1 A): the 1e-9 bar holds for kappa <= 10 (Test 1's
+        # matrices at these sizes: about 8); the a_hat = 100 band makes the
+        # operator 100:1 anisotropic (kappa up to about 90 here), so the bar
+        # is scaled by kappa / 10 above that
+        Dm = 1.0 / np.sqrt(dg)
+        ev = np.linalg.eigvalsh(Dm[:, None] * A.toarray() * Dm[None, :])
+        tol = 1e-9 * max(1.0, ev[-1] / ev[0] / 10.0)
+        err = np.linalg.norm(x[:, s] - xe) / np.linalg.norm(xe)
+        assert err <= tol, (s, err, tol)
     h = ens.param_indicator(prob, ys)
     for s in range(S):
         assert h[s] == pytest.approx(ofe.param_indicator(ys[s], m, test=2), rel=1e-13)
