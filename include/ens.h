@@ -145,6 +145,11 @@ typedef struct {
    values of slots 13..26 are read per row and slot s < 13 of row P is taken
    as slot 26 - s of the neighbour row P + offset(s); with the flag all 27. */
 #define ENS_FLAG_FULL_STENCIL 2
+/* Multigrid: run every level of the V-cycle with its own kernel launches.
+   By default the coarse levels of at most 7^3 nodes run as one launch, one
+   workgroup per member holding those levels in LDS; both give the same
+   bits.  The per-level form is kept for verification. */
+#define ENS_FLAG_MG_LEVELWISE 4
 
 /* Optional statistics of one solve. */
 typedef struct {

@@ -16,6 +16,7 @@ CONVERGED, MAX_ITER, BREAKDOWN, ZERO_RHS = 0, 1, 2, 3
 PRECOND_JACOBI, PRECOND_CHEBYSHEV, PRECOND_MULTIGRID = 0, 1, 2
 FLAG_TIME_SPMV = 1
 FLAG_FULL_STENCIL = 2
+FLAG_MG_LEVELWISE = 4
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
 i32 = C.c_int32

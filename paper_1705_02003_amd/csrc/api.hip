@@ -399,6 +399,9 @@ static void mg_cycle(const MgHierarchy& H, int l, hipStream_t s) {
   a.src = v.x;
   a.q = v.res;
   launch_fe3d<M_RESID>(a, s);
+  // the coarse tail (levels of at most 7^3 nodes, down to the one-node
+  // level) in one launch, unless the next level is already the last
+  const bool tail = !H.levelwise && c.m <= kMgTailNodes && l + 2 < H.L && H.L - (l + 1) <= kMgTailLevels;
   MgTransferArgs t;
   std::memset(&t, 0, sizeof(t));
   t.fine_in = v.res;
@@ -409,13 +412,29 @@ static void mg_cycle(const MgHierarchy& H, int l, hipStream_t s) {
   t.z = c.za;
   t.x = c.x;
   t.done = done;
-  t.op = (l + 2 == H.L) ? MG_RESTRICT_SOLVE : MG_RESTRICT_START;
+  t.op = tail ? MG_RESTRICT : ((l + 2 == H.L) ? MG_RESTRICT_SOLVE : MG_RESTRICT_START);
   t.mc = c.m;
   t.S = c.g.S;
   t.Sp = c.g.Sp;
   t.vstride_c = c.g.vstride;
   launch_mg_transfer(t, s);
-  if (l + 2 < H.L) {
+  if (tail) {
+    MgTailArgs ta;
+    std::memset(&ta, 0, sizeof(ta));
+    ta.nlev = H.L - (l + 1);
+    for (int j = 0; j < ta.nlev; ++j) {
+      const MgLevel& q = H.lv[l + 1 + j];
+      ta.lv[j].V = q.V;
+      ta.lv[j].cheb = q.mem.cheb;
+      ta.lv[j].vstride = q.g.vstride;
+      ta.lv[j].m = q.m;
+    }
+    ta.b = c.b;
+    ta.x = c.x;
+    ta.done = done;
+    ta.S = c.g.S;
+    launch_mg_tail(ta, s);
+  } else if (l + 2 < H.L) {
     mg_cycle(H, l + 1, s);
     MgVecArgs va;
     std::memset(&va, 0, sizeof(va));
@@ -583,6 +602,7 @@ static int run_solve(const ens_problem* prob, const Opts& o, int S, const double
   if (mg) {
     if (!mgh || mgh->L < 2) return ENS_EINVAL;
     H = *mgh;
+    H.levelwise = (o.flags & ENS_FLAG_MG_LEVELWISE) ? 1 : 0;
     mg_bind_fine(H, V, w, g);
     mg_setup(H, w, o.ratio, s);
   }
@@ -1100,6 +1120,7 @@ int ens_mg_apply(const ens_problem* prob, const ens_opts* opts, int32_t S, const
   const Workspace w = carve_solve(ws_dev, prob, o, S, &H);
   const Geometry g = geometry_for(prob, o, S);
   hipStream_t s = (hipStream_t)stream;
+  H.levelwise = (o.flags & ENS_FLAG_MG_LEVELWISE) ? 1 : 0;
   mg_bind_fine(H, V_dev, w, g);
   mg_setup(H, w, o.ratio, s);
   hipLaunchKernelGGL(clear_ctl_kernel, dim3(1), dim3(64), 0, s, w.m.ctl);
@@ -1305,7 +1326,12 @@ static int dqdy_staged(const ens_problem* prob, int32_t S, const double* u_dev,
   a.u = u_dev;
   a.lam = lambda_dev;
   a.partial = w.partial;
+  // one member per thread (Sp threads per point): the form's per-point
+  // temporaries then fit four waves per SIMD, where two members per thread
+  // fit two (the kernel is bound by load latency, not bandwidth)
   a.g = g;
+  a.g.vec = 1;
+  a.g.tpp = g.Sp;
   a.d = prob->d;
   a.eps_model = prob->eps_model;
   a.amp = prob->amp;

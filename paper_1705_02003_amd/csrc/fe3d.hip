@@ -522,7 +522,9 @@ void fe3d_stencil_kernel(StencilArgs a) {
         }
 #pragma unroll
         for (int c = 0; c < VEC; ++c) {
-          dd[c] = c1[c] * dd[c] + c2[c] * ((rr[c] - q[u][c]) / dg[c]);
+          // explicit fma: the same rounding in every instantiation (and in
+          // the multigrid tail kernel, which repeats this step)
+          dd[c] = fma(c1[c], dd[c], c2[c] * ((rr[c] - q[u][c]) / dg[c]));
           zn[c] = own[u][c] + dd[c];
           if (a.cheb_last) acc[c] = fma(rr[c], zn[c], acc[c]);
         }

@@ -28,6 +28,7 @@ struct MgLevel {
 
 struct MgHierarchy {
   int L;   // levels, fine first; level L - 1 has one node and is solved exactly
+  int levelwise;   // 1: no fused coarse tail (every level with its own launches)
   MgLevel lv[kMgMaxLevels];
 };
 
@@ -97,7 +98,31 @@ struct MgVecArgs {
   size_t nr, vstride;
 };
 
+// The coarse end of the V-cycle in one launch: levels of at most
+// kMgTailNodes nodes per direction (7, 3, 1 or 3, 1), one workgroup per
+// member holding the levels' operators and vectors in LDS.  Input: the
+// first tail level's right-hand side; output: its V-cycle result x (the
+// post-smoother's correction already added).  The operations and their
+// order are those of the per-level kernels.
+constexpr int kMgTailNodes = 7;
+constexpr int kMgTailLevels = 3;
+struct MgTailLevel {
+  const double* V;     // 27 slots of stride vstride
+  const double* cheb;  // [Sp][kChebCoef]: theta, c1, c2
+  size_t vstride;
+  int m;
+};
+struct MgTailArgs {
+  MgTailLevel lv[kMgTailLevels];
+  int nlev;            // tail levels (the last has one node)
+  const double* b;     // [m0^3][S]
+  double* x;           // [m0^3][S]
+  const int* done;
+  int S;
+};
+
 void launch_mg_rap(const MgRapArgs& a, hipStream_t s);
+void launch_mg_tail(const MgTailArgs& a, hipStream_t s);
 void launch_mg_gersh(const MgGershArgs& a, int groups, hipStream_t s);
 void launch_mg_coef(const MgCoefArgs& a, hipStream_t s);
 void launch_mg_transfer(const MgTransferArgs& a, hipStream_t s);

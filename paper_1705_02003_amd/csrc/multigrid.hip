@@ -57,11 +57,16 @@ __device__ __forceinline__ bool is_done(const int* done) { return done && gload(
 // ------------------------------------------------------------ Galerkin product
 // Ac(I, I + delta) = sum over fine nodes i = 2I + f and their neighbours
 // j = i + e of w(f) A(i, j) w(f + e - 2 delta), f, e, delta in {-1, 0, 1}^3,
-// w the product of the per-direction weights (1 at offset 0, 1/2 at +-1).
-// Coarse neighbours outside the grid get 0, as the fine slots of neighbours
-// outside do (those fine values are 0 and add nothing).  One thread per
-// (coarse node, member); the 27 sums stay in registers (the loops that index
-// them are unrolled).
+// w the product of the per-direction weights (1 at offset 0, 1/2 at +-1,
+// 0 beyond).  Per direction only 13 of the 27 (f, e, delta) triples have
+// |f + e - 2 delta| <= 1, so 13^3 = 2197 of the 19683 products are nonzero:
+// every loop below is unrolled, which makes f, e, delta and the weights
+// compile-time constants and drops the zero terms.  Coarse neighbours
+// outside the grid get 0, as the fine slots of neighbours outside do (those
+// fine values are 0 and add nothing).  One thread per (coarse node,
+// member); a fine row's 27 values are loaded together, one fine row at a
+// time (the empty asm with a memory clobber keeps the compiler from hoisting
+// the next row's loads, which would exhaust the registers).
 __global__ __launch_bounds__(kNT) void mg_rap_kernel(MgRapArgs a) {
   const int mc = a.mc, mf = 2 * mc + 1, S = a.S;
   const Lane l = lane_of(a.Sp, S);
@@ -71,35 +76,38 @@ __global__ __launch_bounds__(kNT) void mg_rap_kernel(MgRapArgs a) {
     double acc[27];
 #pragma unroll
     for (int k = 0; k < 27; ++k) acc[k] = 0.0;
+#pragma unroll
     for (int fz = -1; fz <= 1; ++fz)
+#pragma unroll
       for (int fy = -1; fy <= 1; ++fy)
+#pragma unroll
         for (int fx = -1; fx <= 1; ++fx) {
           // fine node 2I + f is always interior: 1 <= 2I + f <= 2 mc + 1
-          const double wi = wt(fx) * wt(fy) * wt(fz);
           const size_t rf = ((size_t)(2 * K + fz - 1) * mf + (2 * J + fy - 1)) * mf + (2 * I + fx - 1);
+          double v[27];
+#pragma unroll
+          for (int k = 0; k < 27; ++k) v[k] = gload(&a.Vf[(size_t)k * a.vstride_f + rf * S + l.s]);
+#pragma unroll
           for (int ez = -1; ez <= 1; ++ez)
+#pragma unroll
             for (int ey = -1; ey <= 1; ++ey)
+#pragma unroll
               for (int ex = -1; ex <= 1; ++ex) {
-                const int slot = 9 * (ez + 1) + 3 * (ey + 1) + (ex + 1);
-                const double v = gload(&a.Vf[(size_t)slot * a.vstride_f + rf * S + l.s]);
-                if (v == 0.0) continue;
-                const double wv = wi * v;
-                const int rx = fx + ex, ry = fy + ey, rz = fz + ez;   // j - 2I, in [-2, 2]
+                const int k = 9 * (ez + 1) + 3 * (ey + 1) + (ex + 1);
 #pragma unroll
-                for (int dz = -1; dz <= 1; ++dz) {
+                for (int dz = -1; dz <= 1; ++dz)
 #pragma unroll
-                  for (int dy = -1; dy <= 1; ++dy) {
+                  for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
                     for (int dx = -1; dx <= 1; ++dx) {
-                      const int tx = rx - 2 * dx, ty = ry - 2 * dy, tz = rz - 2 * dz;
-                      const bool near = tx >= -1 && tx <= 1 && ty >= -1 && ty <= 1 && tz >= -1 && tz <= 1;
-                      const double wj = wt(tx) * wt(ty) * wt(tz);
-                      const int k = 9 * (dz + 1) + 3 * (dy + 1) + (dx + 1);
-                      acc[k] = near ? fma(wv, wj, acc[k]) : acc[k];
+                      const int tx = fx + ex - 2 * dx, ty = fy + ey - 2 * dy, tz = fz + ez - 2 * dz;
+                      if (tx < -1 || tx > 1 || ty < -1 || ty > 1 || tz < -1 || tz > 1) continue;
+                      const double w = (wt(fx) * wt(fy) * wt(fz)) * (wt(tx) * wt(ty) * wt(tz));
+                      const int c = 9 * (dz + 1) + 3 * (dy + 1) + (dx + 1);
+                      acc[c] = fma(w, v[k], acc[c]);
                     }
-                  }
-                }
               }
+          asm volatile("" ::: "memory");
         }
 #pragma unroll
     for (int dz = -1; dz <= 1; ++dz)
@@ -243,6 +251,186 @@ __global__ __launch_bounds__(kNT) void mg_vec_kernel(MgVecArgs a) {
   }
 }
 
+// ------------------------------------------------------------ coarse tail
+// One workgroup per member s runs the V-cycle of the tail levels (at most 7^3
+// nodes, then 3^3, then 1) with each level's 27 operator slots and its
+// vectors b, x, res, d, za in LDS ([slot][row] and [row], row = (k m + j) m +
+// i); phases are separated by barriers.  Every operation is the per-level
+// kernels' own, in their order: the 27-term product in slot order starting
+// with a product (neighbours outside the grid count zero), the Chebyshev
+// step dd = c1 d + c2 (r - q) / diag, z = src + dd, the residual with its
+// optional start z = (res / diag) / theta, the restriction over fz, fy, fx,
+// the prolongation over cz, cy, cx, and x + (za + dd) for the post-smoother's
+// correction; so the results are the same bits.
+constexpr int kMgTailPool = 32 * (343 + 27 + 1);   // 27 slots + 5 vectors per node
+
+namespace {
+
+struct TailLv {
+  double *A, *b, *x, *res, *d, *za;
+  int m, nr;
+  double th, c1, c2;
+};
+
+__device__ __forceinline__ double tail_apply(const TailLv& L, const double* p, int r) {
+  const int m = L.m, i = r % m, j = (r / m) % m, k = r / (m * m);
+  double q = 0.0;
+#pragma unroll
+  for (int dk = -1; dk <= 1; ++dk)
+#pragma unroll
+    for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+      for (int di = -1; di <= 1; ++di) {
+        const int slot = 9 * (dk + 1) + 3 * (dj + 1) + (di + 1);
+        const bool in = (unsigned)(i + di) < (unsigned)m && (unsigned)(j + dj) < (unsigned)m &&
+                        (unsigned)(k + dk) < (unsigned)m;
+        const double pv = in ? p[r + (dk * m + dj) * m + di] : 0.0;
+        const double v = L.A[slot * L.nr + r];
+        q = (slot == 0) ? v * pv : fma(v, pv, q);
+      }
+  return q;
+}
+
+// one Chebyshev step from src (d in place): out = src + dd, or x += src + dd
+__device__ __forceinline__ void tail_cheb(const TailLv& L, const double* rv, const double* src, double* out,
+                                          bool accumulate) {
+  for (int r = threadIdx.x; r < L.nr; r += kNT) {
+    const double q = tail_apply(L, src, r);
+    const double dd = fma(L.c1, L.d[r], L.c2 * ((rv[r] - q) / L.A[13 * L.nr + r]));
+    L.d[r] = dd;
+    const double zn = src[r] + dd;
+    if (accumulate) L.x[r] = L.x[r] + zn;
+    else out[r] = zn;
+  }
+}
+
+// res = b - A x, with `start` also d = za = (res / diag) / theta
+__device__ __forceinline__ void tail_resid(const TailLv& L, bool start) {
+  for (int r = threadIdx.x; r < L.nr; r += kNT) {
+    const double rr = L.b[r] - tail_apply(L, L.x, r);
+    L.res[r] = rr;
+    if (start) {
+      const double z = (rr / L.A[13 * L.nr + r]) / L.th;
+      L.d[r] = z;
+      L.za[r] = z;
+    }
+  }
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(kNT) void mg_tail_kernel(MgTailArgs a) {
+  __shared__ double pool[kMgTailPool];
+  if (is_done(a.done)) return;
+  const int s = blockIdx.x, t = threadIdx.x, S = a.S, nlev = a.nlev;
+  // the loops over levels are unrolled, so L[] stays in registers
+  TailLv L[kMgTailLevels];
+  double* p = pool;
+#pragma unroll
+  for (int j = 0; j < kMgTailLevels; ++j) {
+    TailLv& v = L[j];
+    const int m = j < nlev ? a.lv[j].m : 1;
+    v.m = m;
+    v.nr = m * m * m;
+    v.A = p;
+    v.b = p + 27 * v.nr;
+    v.x = v.b + v.nr;
+    v.res = v.x + v.nr;
+    v.d = v.res + v.nr;
+    v.za = v.d + v.nr;
+    p += 32 * v.nr;
+    v.th = v.c1 = v.c2 = 0.0;
+    if (j < nlev) {
+      const double* cf = a.lv[j].cheb + (size_t)s * kChebCoef;
+      v.th = gload(&cf[0]);
+      v.c1 = gload(&cf[1]);
+      v.c2 = gload(&cf[2]);
+    }
+  }
+  // stage the operators and the first level's right-hand side
+#pragma unroll
+  for (int j = 0; j < kMgTailLevels; ++j) {
+    if (j >= nlev) break;
+    const TailLv& v = L[j];
+    const double* V = a.lv[j].V;
+    const size_t vs = a.lv[j].vstride;
+    for (int idx = t; idx < 27 * v.nr; idx += kNT) {
+      const int slot = idx / v.nr, r = idx - slot * v.nr;
+      v.A[idx] = gload(&V[(size_t)slot * vs + (size_t)r * S + s]);
+    }
+  }
+  for (int r = t; r < L[0].nr; r += kNT) L[0].b[r] = gload(&a.b[(size_t)r * S + s]);
+  __syncthreads();
+  {
+    const TailLv& v = L[0];
+    for (int r = t; r < v.nr; r += kNT) {
+      const double z = (v.b[r] / v.A[13 * v.nr + r]) / v.th;
+      v.d[r] = z;
+      v.za[r] = z;
+    }
+  }
+  __syncthreads();
+  // down: pre-smoothing, residual, restriction (starting the next level's
+  // smoother, or solving the one-node last level)
+#pragma unroll
+  for (int j = 0; j + 1 < kMgTailLevels; ++j) {
+    if (j + 1 >= nlev) break;
+    const TailLv& v = L[j];
+    tail_cheb(v, v.b, v.za, v.x, false);
+    __syncthreads();
+    tail_resid(v, false);
+    __syncthreads();
+    const TailLv& c = L[j + 1];
+    const int mc = c.m, mf = v.m;
+    for (int pc = t; pc < c.nr; pc += kNT) {
+      const int I = pc % mc + 1, J = (pc / mc) % mc + 1, K = pc / (mc * mc) + 1;
+      double acc = 0.0;
+      for (int fz = -1; fz <= 1; ++fz)
+        for (int fy = -1; fy <= 1; ++fy)
+#pragma unroll
+          for (int fx = -1; fx <= 1; ++fx) {
+            const int rf = ((2 * K + fz - 1) * mf + (2 * J + fy - 1)) * mf + (2 * I + fx - 1);
+            acc = fma(wt(fx) * wt(fy) * wt(fz), v.res[rf], acc);
+          }
+      c.b[pc] = acc;
+      if (j + 2 == nlev) {
+        c.x[pc] = acc / c.A[13 * c.nr + pc];
+      } else {
+        const double z = (acc / c.A[13 * c.nr + pc]) / c.th;
+        c.d[pc] = z;
+        c.za[pc] = z;
+      }
+    }
+    __syncthreads();
+  }
+  // up: prolongation, residual with the post-smoother's start, post-smoothing
+#pragma unroll
+  for (int j = kMgTailLevels - 2; j >= 0; --j) {
+    if (j + 1 >= nlev) continue;
+    const TailLv& v = L[j];
+    const TailLv& c = L[j + 1];
+    const int mc = c.m, mf = v.m;
+    for (int pf = t; pf < v.nr; pf += kNT) {
+      const int i = pf % mf + 1, jj = (pf / mf) % mf + 1, k = pf / (mf * mf) + 1;
+      double acc = 0.0;
+      for (int cz = k / 2; cz <= (k + 1) / 2; ++cz)
+        for (int cy = jj / 2; cy <= (jj + 1) / 2; ++cy)
+          for (int cx = i / 2; cx <= (i + 1) / 2; ++cx) {
+            if (cx < 1 || cx > mc || cy < 1 || cy > mc || cz < 1 || cz > mc) continue;
+            const int pc = ((cz - 1) * mc + (cy - 1)) * mc + (cx - 1);
+            acc = fma(w1(i, cx) * w1(jj, cy) * w1(k, cz), c.x[pc], acc);
+          }
+      v.x[pf] = v.x[pf] + acc;
+    }
+    __syncthreads();
+    tail_resid(v, true);
+    __syncthreads();
+    tail_cheb(v, v.res, v.za, nullptr, true);
+    __syncthreads();
+  }
+  for (int r = t; r < L[0].nr; r += kNT) gstore(&a.x[(size_t)r * S + s], L[0].x[r]);
+}
+
 // ------------------------------------------------------------ hierarchy
 int mg_levels(int n, int* ms) {
   if (n < 1 || ((n + 1) & n) != 0) return 0;
@@ -312,6 +500,10 @@ int mg_groups(size_t nr, int Sp) {
 
 void launch_mg_rap(const MgRapArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(mg_rap_kernel, dim3(mg_groups(a.nrc, a.Sp)), dim3(kNT), 0, s, a);
+}
+
+void launch_mg_tail(const MgTailArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(mg_tail_kernel, dim3(a.S), dim3(kNT), 0, s, a);
 }
 
 void launch_mg_gersh(const MgGershArgs& a, int groups, hipStream_t s) {

@@ -55,6 +55,7 @@ class SolverOptions:
     time_spmv: bool = False
     member_tile: int = 0          # members per stencil tile, 0: the whole ensemble
     full_stencil: bool = False    # read all nine matrix values (no symmetric reuse)
+    mg_levelwise: bool = False    # multigrid: one launch per level operation (no fused coarse tail)
 
     def c(self) -> L.ens_opts:
         pre = {"jacobi": L.PRECOND_JACOBI, "chebyshev": L.PRECOND_CHEBYSHEV,
@@ -62,7 +63,8 @@ class SolverOptions:
         return L.ens_opts(pre, self.cheb_degree, float(self.cheb_ratio), float(self.rtol),
                           self.max_iter, self.poll_every, self.tile_lines, self.max_groups,
                           (L.FLAG_TIME_SPMV if self.time_spmv else 0)
-                          | (L.FLAG_FULL_STENCIL if self.full_stencil else 0),
+                          | (L.FLAG_FULL_STENCIL if self.full_stencil else 0)
+                          | (L.FLAG_MG_LEVELWISE if self.mg_levelwise else 0),
                           int(self.member_tile))
 
 
@@ -388,6 +390,38 @@ class BatchResult(NamedTuple):
     seconds: float           # device time from the batch start to this ensemble's retirement
 
 
+def plan_waves(items, max_wave_bytes: float):
+    """The waves of ``batch_solve``: item indices sorted by the bytes one CG
+    iteration moves (120 B per member-row; ties by index) and packed greedily
+    into waves of at most ``max_wave_bytes`` (a larger ensemble forms a wave
+    of its own)."""
+    cost = [120 * it["prob"].rows * _ensemble_width(it["b"]) for it in items]
+    order = sorted(range(len(items)), key=lambda i: (cost[i], i))
+    waves, cur, tot = [], [], 0
+    for i in order:
+        if cur and tot + cost[i] > max_wave_bytes:
+            waves.append(cur)
+            cur, tot = [], 0
+        cur.append(i)
+        tot += cost[i]
+    waves.append(cur)
+    return waves
+
+
+def _solve_as_batch_item(it, opts: Optional[SolverOptions], start: float) -> "BatchResult":
+    """One batch item through the single-ensemble solver; ``seconds`` is
+    ``start`` plus the solve's wall time (it blocks until the counts are
+    known)."""
+    from dataclasses import replace
+    o = replace(opts or SolverOptions(), tile_lines=int(it.get("tile_lines", 0)),
+                member_tile=int(it.get("member_tile", 0)))
+    t = time.perf_counter()
+    r = solve(it["prob"], it["V"], it["b"], o, x=it.get("x"), ws=it.get("ws"))
+    torch.cuda.synchronize()
+    return BatchResult(r.x, r.iters, r.status, r.relres, int(r.ens_iters),
+                       start + time.perf_counter() - t)
+
+
 def batch_solve(items, opts: Optional[SolverOptions] = None, batch_ws: Optional[torch.Tensor] = None,
                 max_wave_bytes="auto"):
     """Solve several ensembles together (ens_batch_solve).
@@ -402,28 +436,26 @@ def batch_solve(items, opts: Optional[SolverOptions] = None, batch_ws: Optional[
     many bytes (a larger ensemble forms a wave of its own).  The small
     ensembles retire early.  "auto" (the default) takes the autotuner's wave
     size (``autotune.tune_wave``), None solves all ensembles in one batch.
-    A result's ``seconds`` then counts from the start of the first wave."""
+    A result's ``seconds`` then counts from the start of the first wave.  A
+    wave of one ensemble is solved by the single-ensemble solver (``solve``,
+    with the item's launch shape), which is faster than a batch of one:
+    the batched kernels' unit tables and per-step graph cost it 2-4 % at
+    512^2 and up to a third on small grids."""
     if isinstance(max_wave_bytes, str):
         if max_wave_bytes != "auto":
             raise ValueError("max_wave_bytes: a number of bytes, 'auto' or None")
         from . import autotune
         max_wave_bytes = autotune.tune_wave()["wave_bytes"] if len(items) > 1 else None
     if max_wave_bytes is not None and len(items) > 1:
-        cost = [120 * it["prob"].rows * _ensemble_width(it["b"]) for it in items]
-        order = sorted(range(len(items)), key=lambda i: (cost[i], i))
-        waves, cur, tot = [], [], 0
-        for i in order:
-            if cur and tot + cost[i] > max_wave_bytes:
-                waves.append(cur)
-                cur, tot = [], 0
-            cur.append(i)
-            tot += cost[i]
-        waves.append(cur)
+        waves = plan_waves(items, max_wave_bytes)
         out = [None] * len(items)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for wv in waves:
             start = time.perf_counter() - t0
+            if len(wv) == 1:
+                out[wv[0]] = _solve_as_batch_item(items[wv[0]], opts, start)
+                continue
             for i, r in zip(wv, batch_solve([items[i] for i in wv], opts, batch_ws, None)):
                 out[i] = r._replace(seconds=start + r.seconds)
         return out

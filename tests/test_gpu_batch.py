@@ -126,18 +126,33 @@ def test_batch_in_waves_matches_single_solves():
     assert res[int(np.argmin(cost))].seconds <= res[int(np.argmax(cost))].seconds
 
 
-def test_batch_default_waves_equal_one_batch_bitwise():
-    """The default (smallest-first waves of the autotuner's size) gives the
-    same bits as one batch: an ensemble's partial sums land in rows fixed by
-    its own unit indices, whatever else is in the batch."""
+@pytest.mark.parametrize("wave_gb", [None, 0.002])
+def test_batch_default_waves_bitwise(wave_gb):
+    """Smallest-first waves (the autotuner's size, and a size small enough
+    to leave several ensembles alone in their waves): an ensemble in a wave
+    of several gives the same bits as in one batch (its partial sums land in
+    rows fixed by its own unit indices, whatever else is in the batch), and
+    an ensemble alone in its wave the bits of its single solve."""
     from paper_1705_02003_amd import autotune
     from paper_1705_02003_amd import ensemble as E
     wave = autotune.tune_wave()
-    print("CASE batch auto waves", wave, flush=True)
+    print("CASE batch auto waves", wave, wave_gb, flush=True)
     assert wave["wave_bytes"] > 0 and wave["ensembles"] >= 1
     items, _ = make_batch(seed=4)
-    r_auto = E.batch_solve(items, E.SolverOptions(rtol=1e-8))
-    r_one = E.batch_solve(items, E.SolverOptions(rtol=1e-8), max_wave_bytes=None)
-    for a, b in zip(r_auto, r_one):
+    opts = E.SolverOptions(rtol=1e-8)
+    wb = wave["wave_bytes"] if wave_gb is None else wave_gb * 1e9
+    waves = E.plan_waves(items, wb)
+    assert sorted(i for w in waves for i in w) == list(range(len(items)))
+    r_auto = E.batch_solve(items, opts, max_wave_bytes="auto" if wave_gb is None else wb)
+    r_one = E.batch_solve(items, opts, max_wave_bytes=None)
+    alone = {w[0] for w in waves if len(w) == 1}
+    if wave_gb is not None:
+        assert len(alone) >= 2 and any(len(w) > 1 for w in waves)
+    for i, (a, b) in enumerate(zip(r_auto, r_one)):
+        if i in alone:
+            from dataclasses import replace
+            o = replace(opts, tile_lines=items[i]["tile_lines"],
+                        member_tile=items[i].get("member_tile", 0))
+            b = E.solve(items[i]["prob"], items[i]["V"], items[i]["b"], o)
         assert np.array_equal(a.iters, b.iters) and np.array_equal(a.status, b.status)
         assert torch.equal(a.x, b.x)

@@ -86,7 +86,7 @@ def test_widths_jacobi_match_oracle(n, S, d, eps_model, amp, kw):
     P = np.random.default_rng(S).standard_normal((n * n, S))
     q = ens.spmv(prob, V, torch.tensor(P, device="cuda")).cpu().numpy()
     for s in (0, S // 2, S - 1):
-        A = oprob.to_csr(Vh[:, :, s], n)
+        A = oprob.to_csr(oprob.stencil_values(ys[s], n, eps_model, amp), n)
         assert np.max(np.abs(q[:, s] - A @ P[:, s])) <= 1e-13 * np.abs(A).sum(axis=1).max() * np.abs(P[:, s]).max()
     res = ens.solve(prob, V, b, ens.SolverOptions(rtol=1e-8, **kw))
     worst = check_members(res, ys, n, eps_model, amp, 1e-8)
@@ -107,10 +107,10 @@ def test_widths_chebyshev_match_oracle(n, S, kw):
     z = z.cpu().numpy()
     Vh = V.cpu().numpy()
     for s in (0, S - 1):
-        A = oprob.to_csr(Vh[:, :, s], n)
-        lm = opcg.gershgorin_lmax(A, Vh[4, :, s])
-        assert lmax[s] == pytest.approx(lm, rel=1e-15)
-        ref = opcg.chebyshev_apply(A, Vh[4, :, s], R[:, s], lm)
+        A, _, dg = oprob.assemble(ys[s], n, 1, 0.45)
+        lm = opcg.gershgorin_lmax(A, dg)
+        assert lmax[s] == pytest.approx(lm, rel=1e-14)
+        ref = opcg.chebyshev_apply(A, dg, R[:, s], lm)
         assert np.linalg.norm(z[:, s] - ref) <= 1e-13 * np.linalg.norm(ref)
     res = ens.solve(prob, V, b, ens.SolverOptions(precond="chebyshev", rtol=1e-8, **kw))
     worst = check_members(res, ys, n, 1, 0.45, 1e-8, "chebyshev")
