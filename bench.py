@@ -634,31 +634,41 @@ def cheb_mode(args) -> int:
            "fused_alg_GBs": round(rows * FUSED_BYTES / (us * 1e-6) / 1e9, 1),
            "iteration_alg_GBs": round(sum(res.ens_iters) * rows * CHEB_ITER_BYTES / res.solve_seconds / 1e9, 1)}
     if len(real) == w.n_samples:
-        # Every sample solved: the cost of other groupings of the same samples
-        # follows from the recorded counts (a member's count does not depend
-        # on its companions), eqs. (Rl), (R); their time is predicted from the
-        # measured time per ensemble iteration.
-        from paper_1705_02003_amd import grouping as G
-        its_all = res.iters
-        per_iter = res.solve_seconds / float(sum(res.ens_iters))
-        hind = E.param_indicator_samples(prob, ys)
-        orders = {"surrogate": None,
-                  "random": list(np.random.default_rng(w.seed).permutation(w.n_samples)),
-                  "natural": list(range(w.n_samples)),
-                  "param": sorted(range(w.n_samples), key=lambda i: (hind[i], i)),
-                  "its": sorted(range(w.n_samples), key=lambda i: (its_all[i], i))}
-        table = {}
-        for name, order in orders.items():
-            groups = res.groups if name == "surrogate" else G.chunk(order, S)
-            tot = G.ensemble_iteration_total(groups, its_all)
-            table[name] = {"sum_ensemble_iters": tot, "R": round(G.cost_ratio(groups, its_all, S), 4),
-                           "seconds": round(res.solve_seconds, 2) if name == "surrogate"
-                           else round(tot * per_iter, 2)}
-        out["grouping"] = table
-        out["grouping_note"] = ("seconds measured for the surrogate grouping (the solved one); for "
-                                "the others Sum K_e times the measured seconds per ensemble iteration")
+        out["grouping"] = grouping_costs(res, prob, ys, S, w.seed)
+        out["grouping_note"] = GROUPING_NOTE
     print(json.dumps(out), flush=True)
     return 0
+
+
+GROUPING_NOTE = ("seconds measured for the surrogate grouping (the solved one); for the others "
+                 "Sum K_e times the measured seconds per ensemble iteration")
+
+
+def grouping_costs(res, prob, ys, S: int, seed: int) -> dict:
+    """Every sample of a non-adaptive run solved: the cost of other
+    groupings of the same samples follows from the recorded counts (a
+    member's count does not depend on its companions), eqs. (Rl), (R); their
+    time is predicted from the measured time per ensemble iteration."""
+    import numpy as np
+    from paper_1705_02003_amd import ensemble as E
+    from paper_1705_02003_amd import grouping as G
+    M = len(ys)
+    its_all = res.iters
+    per_iter = res.solve_seconds / float(sum(res.ens_iters))
+    hind = E.param_indicator_samples(prob, ys)
+    orders = {"surrogate": None,
+              "random": list(np.random.default_rng(seed).permutation(M)),
+              "natural": list(range(M)),
+              "param": sorted(range(M), key=lambda i: (hind[i], i)),
+              "its": sorted(range(M), key=lambda i: (its_all[i], i))}
+    table = {}
+    for name, order in orders.items():
+        groups = res.groups if name == "surrogate" else G.chunk(order, S)
+        tot = G.ensemble_iteration_total(groups, its_all)
+        table[name] = {"sum_ensemble_iters": tot, "R": round(G.cost_ratio(groups, its_all, S), 4),
+                       "seconds": round(res.solve_seconds, 3) if name == "surrogate"
+                       else round(tot * per_iter, 3)}
+    return table
 
 
 def fe3d_mode(args) -> int:
@@ -704,7 +714,8 @@ def fe3d_mode(args) -> int:
         r = {"sample_solves_per_s": round(len(ys) / res.solve_seconds, 2),
              "solve_seconds": round(res.solve_seconds, 3),
              "iters": [int(its.min()), int(its.max())], "sum_ens_iters": int(sum(res.ens_iters)),
-             "R": round(S * sum(res.ens_iters) / float(its.sum()), 4)}
+             "R": round(S * sum(res.ens_iters) / float(its.sum()), 4),
+             "grouping": {k: v["R"] for k, v in grouping_costs(res, prob, ys, S, w.seed).items()}}
         if K == 1:
             # (with concurrent ensembles the timed launches overlap others' work)
             r["step_avg_us"] = round(us, 2)

@@ -58,7 +58,6 @@ __device__ __forceinline__ void reduce_group(double (&v)[VEC], int tpp, double* 
 
 }  // namespace
 
-constexpr int kMaxD = 16;
 
 // Tiles of kAsmTX x kAsmTY grid points, grid-strided over the workgroups.
 // Per tile the mode tables sin(k pi I h) at the tile's node columns and rows
@@ -70,8 +69,11 @@ constexpr int kMaxD = 16;
 //   cC sC + cE sE + cW sW + cN sN + cS sS,   sX = sin(k pi x1) sin(k pi x2) at X,
 // its factor amp / k^2 applied once to the workgroup's sum.  The same
 // products give a = 1 + sum_k (amp y_{k+1} / k^2) sX at the five nodes for
-// the anisotropy derivatives.
-template <int VEC>
+// the anisotropy derivatives.  NM = d - 2 is a template parameter: the
+// mode loops unroll to exactly NM and the accumulators hold exactly d
+// values per member, which keeps the register count at the occupancy the
+// loads need (a runtime mode count held all 16 accumulators and 14 modes).
+template <int VEC, int NM>
 __global__ __launch_bounds__(kNT) void dqdy_kernel(DqdyArgs a) {
   __shared__ double red[kWaves * 64 * 2];
   __shared__ double sI[kMaxModes][kAsmTX + 2];
@@ -80,13 +82,14 @@ __global__ __launch_bounds__(kNT) void dqdy_kernel(DqdyArgs a) {
   __shared__ double wk[kMaxModes];          // amp / k^2
   __shared__ double coef[9][kMaxS];         // per member slot: K entries and their derivatives
   const Geometry& g = a.g;
-  const int S = g.S, n = g.n, tpp = g.tpp, t = threadIdx.x, d = a.d, nm = a.d - 2;
+  constexpr int D = NM + 2;
+  const int S = g.S, n = g.n, tpp = g.tpp, t = threadIdx.x, d = D, nm = NM;
   const int sv = (t % tpp) * VEC;
   const bool lane_ok = sv < S;
   const int svl = lane_ok ? sv : S - VEC;   // idle slots compute on real members, add nothing
   if (t < nm) wk[t] = a.amp / (double)((t + 1) * (t + 1));
   for (int x = t; x < S * nm; x += kNT) {
-    const int m = x / nm, k = x % nm;
+    const int m = x / (NM > 0 ? NM : 1), k = x % (NM > 0 ? NM : 1);
     wy[m][k] = (a.amp * a.y[(size_t)m * d + k + 2]) / (double)((k + 1) * (k + 1));
   }
 
@@ -123,9 +126,15 @@ __global__ __launch_bounds__(kNT) void dqdy_kernel(DqdyArgs a) {
 #pragma unroll
       for (int r = 0; r < 3; ++r) dk[q][r][c] = coef[3 + 3 * q + r][m];
   }
-  double acc[kMaxD][VEC];
+  // the member's mode weights amp y_{k+1} / k^2, fixed for the thread
+  double wyr[NM > 0 ? NM : 1][VEC];
 #pragma unroll
-  for (int q = 0; q < kMaxD; ++q)
+  for (int k = 0; k < NM; ++k)
+#pragma unroll
+    for (int c = 0; c < VEC; ++c) wyr[k][c] = wy[svl + c][k];
+  double acc[D][VEC];
+#pragma unroll
+  for (int q = 0; q < D; ++q)
 #pragma unroll
     for (int c = 0; c < VEC; ++c) acc[q][c] = 0.0;
 
@@ -199,27 +208,25 @@ __global__ __launch_bounds__(kNT) void dqdy_kernel(DqdyArgs a) {
 #pragma unroll
       for (int c = 0; c < VEC; ++c) aC[c] = aE[c] = aW[c] = aN[c] = aS[c] = 1.0;
 #pragma unroll
-      for (int k = 0; k < kMaxModes; ++k) {
-        if (k < nm) {
-          const double sIm = sI[k][qi - 1], sIc = sI[k][qi], sIp = sI[k][qi + 1];
-          const double sJm = sJ[k][qj - 1], sJc = sJ[k][qj], sJp = sJ[k][qj + 1];
-          const double pC = sJc * sIc, pE = sJc * sIp, pW = sJc * sIm;
-          const double pN = sJp * sIc, pS = sJm * sIc;
+      for (int k = 0; k < NM; ++k) {
+        const double sIm = sI[k][qi - 1], sIc = sI[k][qi], sIp = sI[k][qi + 1];
+        const double sJm = sJ[k][qj - 1], sJc = sJ[k][qj], sJp = sJ[k][qj + 1];
+        const double pC = sJc * sIc, pE = sJc * sIp, pW = sJc * sIm;
+        const double pN = sJp * sIc, pS = sJm * sIc;
 #pragma unroll
-          for (int c = 0; c < VEC; ++c) {
-            const double w = wy[svl + c][k];
-            aC[c] = fma(w, pC, aC[c]);
-            aE[c] = fma(w, pE, aE[c]);
-            aW[c] = fma(w, pW, aW[c]);
-            aN[c] = fma(w, pN, aN[c]);
-            aS[c] = fma(w, pS, aS[c]);
-            double v = cC[c] * pC;
-            v = fma(cE[c], pE, v);
-            v = fma(cW[c], pW, v);
-            v = fma(cN[c], pN, v);
-            v = fma(cS[c], pS, v);
-            acc[k + 2][c] += v;
-          }
+        for (int c = 0; c < VEC; ++c) {
+          const double w = wyr[k][c];
+          aC[c] = fma(w, pC, aC[c]);
+          aE[c] = fma(w, pE, aE[c]);
+          aW[c] = fma(w, pW, aW[c]);
+          aN[c] = fma(w, pN, aN[c]);
+          aS[c] = fma(w, pS, aS[c]);
+          double v = cC[c] * pC;
+          v = fma(cE[c], pE, v);
+          v = fma(cW[c], pW, v);
+          v = fma(cN[c], pN, v);
+          v = fma(cS[c], pS, v);
+          acc[k + 2][c] += v;
         }
       }
 #pragma unroll
@@ -234,14 +241,13 @@ __global__ __launch_bounds__(kNT) void dqdy_kernel(DqdyArgs a) {
   }
   // the modes' factor amp / k^2
 #pragma unroll
-  for (int k = 0; k < kMaxModes; ++k)
-    if (k < nm)
+  for (int k = 0; k < NM; ++k)
 #pragma unroll
-      for (int c = 0; c < VEC; ++c) acc[k + 2][c] *= wk[k];
+    for (int c = 0; c < VEC; ++c) acc[k + 2][c] *= wk[k];
   const size_t ps = (size_t)gridDim.x * g.Sp;
 #pragma unroll
-  for (int q = 0; q < kMaxD; ++q) {
-    if (q < d) {
+  for (int q = 0; q < D; ++q) {
+    {
       double v[VEC];
 #pragma unroll
       for (int c = 0; c < VEC; ++c) v[c] = acc[q][c];
@@ -254,9 +260,31 @@ __global__ __launch_bounds__(kNT) void dqdy_kernel(DqdyArgs a) {
   }
 }
 
+template <int NM>
+static void launch_dqdy_nm(const DqdyArgs& a, int groups, hipStream_t s) {
+  if (a.g.vec == 2) hipLaunchKernelGGL((dqdy_kernel<2, NM>), dim3(groups), dim3(kNT), 0, s, a);
+  else hipLaunchKernelGGL((dqdy_kernel<1, NM>), dim3(groups), dim3(kNT), 0, s, a);
+}
+
+// d - 2 sine modes, 0 .. kMaxModes (the caller has checked the range)
 void launch_dqdy(const DqdyArgs& a, int groups, hipStream_t s) {
-  if (a.g.vec == 2) hipLaunchKernelGGL(dqdy_kernel<2>, dim3(groups), dim3(kNT), 0, s, a);
-  else hipLaunchKernelGGL(dqdy_kernel<1>, dim3(groups), dim3(kNT), 0, s, a);
+  switch (a.d - 2) {
+    case 0: launch_dqdy_nm<0>(a, groups, s); break;
+    case 1: launch_dqdy_nm<1>(a, groups, s); break;
+    case 2: launch_dqdy_nm<2>(a, groups, s); break;
+    case 3: launch_dqdy_nm<3>(a, groups, s); break;
+    case 4: launch_dqdy_nm<4>(a, groups, s); break;
+    case 5: launch_dqdy_nm<5>(a, groups, s); break;
+    case 6: launch_dqdy_nm<6>(a, groups, s); break;
+    case 7: launch_dqdy_nm<7>(a, groups, s); break;
+    case 8: launch_dqdy_nm<8>(a, groups, s); break;
+    case 9: launch_dqdy_nm<9>(a, groups, s); break;
+    case 10: launch_dqdy_nm<10>(a, groups, s); break;
+    case 11: launch_dqdy_nm<11>(a, groups, s); break;
+    case 12: launch_dqdy_nm<12>(a, groups, s); break;
+    case 13: launch_dqdy_nm<13>(a, groups, s); break;
+    default: launch_dqdy_nm<14>(a, groups, s); break;
+  }
 }
 
 }  // namespace ens

@@ -1326,12 +1326,7 @@ static int dqdy_staged(const ens_problem* prob, int32_t S, const double* u_dev,
   a.u = u_dev;
   a.lam = lambda_dev;
   a.partial = w.partial;
-  // one member per thread (Sp threads per point): the form's per-point
-  // temporaries then fit four waves per SIMD, where two members per thread
-  // fit two (the kernel is bound by load latency, not bandwidth)
   a.g = g;
-  a.g.vec = 1;
-  a.g.tpp = g.Sp;
   a.d = prob->d;
   a.eps_model = prob->eps_model;
   a.amp = prob->amp;
