@@ -383,7 +383,8 @@ def table_mode(args) -> int:
     cells, d = 4, the paper's Test 1 settings: tau 1e-3, at most 2000 samples,
     up to 8 levels, solver tolerance 1e-7), SU(S) from S copies of y = 0;
     with --test 2 the paper's Test 2 (a_hat(y) in {1, 100, 10} banded by
-    |y|, the same settings; Table 3's analogue)."""
+    |y|, the same settings; Table 3's analogue); --precond picks the
+    preconditioner (Jacobi by default; multigrid is the paper's kind)."""
     import numpy as np
     import torch
     import workloads
@@ -394,7 +395,8 @@ def table_mode(args) -> int:
     if args.dim == 3:
         w = workloads.FE3D_32 if args.test == 1 else workloads.FE3D_32_TEST2
         prob = E.Problem(w.n, w.d, w.eps_model, dim=3)
-        opts = E.SolverOptions(rtol=w.rtol, max_iter=w.max_iter, full_stencil=FULL_STENCIL)
+        opts = E.SolverOptions(precond=args.precond, rtol=w.rtol, max_iter=w.max_iter,
+                               full_stencil=FULL_STENCIL)
         res = uq.adaptive(prob, args.S, budget=2000, max_level=8, tau_rel=1e-3,
                           strategy="surrogate", opts=opts, perm_seed=1)
         y0, workload = np.zeros(w.d), "adaptive-sg-" + w.name
@@ -482,6 +484,9 @@ def kernel_mode(args) -> int:
     import torch
     import workloads
     from paper_1705_02003_amd import ensemble as E
+    if args.precond == "multigrid":
+        print("--mode kernel runs the 2-D model: --precond jacobi or chebyshev", file=sys.stderr)
+        return 2
     torch.cuda.set_device(0)
     n = args.grid
     if args.precond == "chebyshev":
@@ -679,9 +684,10 @@ def fe3d_mode(args) -> int:
     degree-4 Jacobi-Chebyshev and with the multigrid V-cycle (--precs picks
     a subset), --streams ensembles at a time (default 2) on separate HIP
     streams; the first ensemble's samples are also solved one at a time
-    (S = 1).  --test 2 takes the paper's Test 2 coefficient.  At this size an ensemble's matrix (27 x 8 B per
-    member-row, 206 MB at S = 32) fits the 256 MB Infinity Cache, so the
-    product kernel's rate is partly a cache rate."""
+    (S = 1).  --test 2 takes the paper's Test 2 coefficient.  At this size
+    an ensemble's matrix (27 x 8 B per member-row, 206 MB at S = 32) fits
+    the 256 MB Infinity Cache, so the product kernel's rate is partly a
+    cache rate."""
     import numpy as np
     import torch
     import workloads
@@ -878,8 +884,8 @@ def main() -> int:
                          "copy, for hardware-counter runs")
     ap.add_argument("--iters", type=int, default=100, help="iterations in --mode kernel")
     ap.add_argument("--grid", type=int, default=N_GRID, help="grid size n in --mode kernel")
-    ap.add_argument("--precond", choices=["jacobi", "chebyshev"], default="jacobi",
-                    help="preconditioner in --mode kernel")
+    ap.add_argument("--precond", choices=["jacobi", "chebyshev", "multigrid"], default="jacobi",
+                    help="preconditioner in --mode kernel (jacobi, chebyshev) and --mode table --dim 3")
     ap.add_argument("--S-list", default="4,8,16,32,64", help="ensemble widths in --mode table")
     ap.add_argument("--resident-gb", type=float, default=0.0,
                     help="--mode batch: device memory the draw may keep resident (0: 80 %% of HBM)")
