@@ -314,10 +314,9 @@ static Geometry geometry_for(const ens_problem* prob, const Opts& o, int S) {
 // ------------------------------------------------------------ multigrid
 // Level 0 of the V-cycle works in the solve's own vectors: its right-hand
 // side is the PCG residual r, its output z[1] (the direction source of the
-// next step), its smoother start d, z[0] (written by the residual update),
-// its residual aux and post-smoother output q (A p is not needed again until
-// the next product writes it).  Its smoother coefficients are the solve's
-// (the initialisation computes them with degree 2).
+// next step), its smoother start d, z[0] (written by the residual update)
+// and its residual aux.  Its smoother coefficients are the solve's (the
+// initialisation computes them with degree 2).
 static void mg_bind_fine(MgHierarchy& H, const double* V, const Workspace& w, const Geometry& g) {
   MgLevel& f = H.lv[0];
   f.g = g;
@@ -327,7 +326,6 @@ static void mg_bind_fine(MgHierarchy& H, const double* V, const Workspace& w, co
   f.res = w.aux;
   f.d = w.d;
   f.za = w.z[0];
-  f.zb = w.q;
   f.mem = w.m;
 }
 
@@ -375,8 +373,10 @@ static void mg_setup(const MgHierarchy& H, const Workspace& w, double ratio, hip
 // (d, za) is in place: pre-smoothing, residual, restriction (starting the
 // next level's smoother, or solving the one-node coarsest level), the
 // coarse cycle, prolongation, the residual with the post-smoother's start,
-// post-smoothing.  The last x += zb is left to the caller.
-static void mg_cycle(const MgHierarchy& H, int l, hipStream_t s) {
+// and post-smoothing with its result added to x in place (on level 0 with
+// the partial sums of dotv^T x into `partial`).
+static void mg_cycle(const MgHierarchy& H, int l, hipStream_t s, const double* dotv = nullptr,
+                     double* partial = nullptr) {
   const MgLevel& v = H.lv[l];
   const MgLevel& c = H.lv[l + 1];
   const int* done = v.mem.ctl + CTL_DONE;
@@ -436,17 +436,6 @@ static void mg_cycle(const MgHierarchy& H, int l, hipStream_t s) {
     launch_mg_tail(ta, s);
   } else if (l + 2 < H.L) {
     mg_cycle(H, l + 1, s);
-    MgVecArgs va;
-    std::memset(&va, 0, sizeof(va));
-    va.z = c.zb;
-    va.x = c.x;
-    va.done = done;
-    va.op = MG_ADD;
-    va.S = c.g.S;
-    va.Sp = c.g.Sp;
-    va.nr = c.g.nr;
-    va.vstride = c.g.vstride;
-    launch_mg_vec(va, s);
   }
   std::memset(&t, 0, sizeof(t));
   t.coarse_in = c.x;
@@ -475,31 +464,20 @@ static void mg_cycle(const MgHierarchy& H, int l, hipStream_t s) {
   a.r = v.res;
   a.src = v.za;
   a.d = v.d;
-  a.zout = v.zb;
+  a.x = v.x;
+  a.dotv = dotv;
+  a.partial = partial;
   a.cheb_step = 1;
-  launch_fe3d<M_CHEB>(a, s);
+  launch_fe3d<M_CHEBX>(a, s);
 }
 
 // One V-cycle application z[1] = V(r) on level 0 (smoother started), the
-// last correction fused with the partial sums of r^T z, and the step's
-// rho (and beta) from them.
+// post-smoother's correction fused with the partial sums of r^T z, and the
+// step's rho (and beta) from them.
 static void mg_apply(const MgHierarchy& H, const Workspace& w, bool init, hipStream_t s) {
   const MgLevel& f = H.lv[0];
-  mg_cycle(H, 0, s);
-  MgVecArgs va;
-  std::memset(&va, 0, sizeof(va));
-  va.z = f.zb;
-  va.x = f.x;
-  va.dot = f.b;
-  va.partial = w.partial;
-  va.done = w.m.ctl + CTL_DONE;
-  va.op = MG_ADD;
-  va.S = f.g.S;
-  va.Sp = f.g.Sp;
-  va.nr = f.g.nr;
-  va.vstride = f.g.vstride;
-  const int G = launch_mg_vec(va, s);
-  finish(w, f.g, G, F_CHEB, s, 0.0, init ? 1 : 0);
+  mg_cycle(H, 0, s, f.b, w.partial);
+  finish(w, f.g, f.g.groups, F_CHEB, s, 0.0, init ? 1 : 0);
 }
 
 struct SolveOut {

@@ -20,7 +20,10 @@
 //   M_CHEB:  one Chebyshev step d = c1 d + c2 D^-1 (r - A z), z_out = z + d,
 //            on the last step with the partial sums of r^T z_out;
 //   M_RESID: the residual q = r - A x of a multigrid level, optionally with
-//            its smoother's start d = z_out = D^-1 q / theta.
+//            its smoother's start d = z_out = D^-1 q / theta;
+//   M_CHEBX: a multigrid post-smoother's Chebyshev step added to the
+//            level's x in place, optionally with the partial sums of
+//            dotv^T x.
 // The neighbours' values of the product come through the caches (a point's
 // 27 neighbours lie on three planes of the grid, all near in memory); of the
 // 27 matrix values of a row, the 14 of slots 13..26 are read and the other
@@ -507,14 +510,18 @@ void fe3d_stencil_kernel(StencilArgs a) {
           st<VEC>(a.d + e, zn);
           st<VEC>(a.zout + e, zn);
         }
-      } else {  // M_CHEB
+      } else {  // M_CHEB, M_CHEBX
         // the step's coefficients and the diagonal are loaded again here
         // (cached) rather than held in registers across the sweep, which
         // keeps the kernel at three waves per SIMD without spilling
-        double rr[VEC], dd[VEC], zn[VEC], dg[VEC], c1[VEC], c2[VEC];
+        double rr[VEC], dd[VEC], zn[VEC], dg[VEC], c1[VEC], c2[VEC], xv[VEC], dv[VEC];
         ld<VEC>(rr, a.r + e);
         ld<VEC>(dd, a.d + e);
         ld<VEC>(dg, a.V + (size_t)g.cslot * vs + e);
+        if constexpr (MODE == M_CHEBX) {
+          ld<VEC>(xv, a.x + e);
+          if (a.dotv) ld<VEC>(dv, a.dotv + e);
+        }
 #pragma unroll
         for (int c = 0; c < VEC; ++c) {
           c1[c] = gload(&a.m.cheb[(size_t)(sv + c) * kChebCoef + 2 * a.cheb_step - 1]);
@@ -526,10 +533,19 @@ void fe3d_stencil_kernel(StencilArgs a) {
           // the multigrid tail kernel, which repeats this step)
           dd[c] = fma(c1[c], dd[c], c2[c] * ((rr[c] - q[u][c]) / dg[c]));
           zn[c] = own[u][c] + dd[c];
-          if (a.cheb_last) acc[c] = fma(rr[c], zn[c], acc[c]);
+          if constexpr (MODE == M_CHEBX) {
+            xv[c] = xv[c] + zn[c];
+            if (a.dotv) acc[c] = fma(dv[c], xv[c], acc[c]);
+          } else if (a.cheb_last) {
+            acc[c] = fma(rr[c], zn[c], acc[c]);
+          }
         }
-        st<VEC>(a.d + e, dd);
-        st<VEC>(a.zout + e, zn);
+        if constexpr (MODE == M_CHEBX) {
+          st<VEC>(a.x + e, xv);
+        } else {
+          st<VEC>(a.d + e, dd);
+          st<VEC>(a.zout + e, zn);
+        }
       }
     }
   }
@@ -538,6 +554,11 @@ void fe3d_stencil_kernel(StencilArgs a) {
     put_partial<VEC>(a.partial, g.Sp, tpp, acc);
   } else if constexpr (MODE == M_CHEB) {
     if (a.cheb_last) {
+      group_reduce<VEC>(acc, tpp, red);
+      put_partial<VEC>(a.partial, g.Sp, tpp, acc);
+    }
+  } else if constexpr (MODE == M_CHEBX) {
+    if (a.dotv) {
       group_reduce<VEC>(acc, tpp, red);
       put_partial<VEC>(a.partial, g.Sp, tpp, acc);
     }
@@ -571,5 +592,6 @@ template void launch_fe3d<M_PCG_J>(const StencilArgs&, hipStream_t);
 template void launch_fe3d<M_PCG_Z>(const StencilArgs&, hipStream_t);
 template void launch_fe3d<M_CHEB>(const StencilArgs&, hipStream_t);
 template void launch_fe3d<M_RESID>(const StencilArgs&, hipStream_t);
+template void launch_fe3d<M_CHEBX>(const StencilArgs&, hipStream_t);
 
 }  // namespace ens

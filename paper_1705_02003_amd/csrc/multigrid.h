@@ -22,7 +22,6 @@ struct MgLevel {
   double* res;      // residual b - A x
   double* d;        // smoother increment
   double* za;       // smoother iterate (started by the caller)
-  double* zb;       // post-smoother output
   Members mem;
 };
 
@@ -81,23 +80,6 @@ struct MgTransferArgs {
   size_t vstride_c;
 };
 
-enum MgVecOp { MG_ADD = 0, MG_SOLVE = 1 };
-
-// MG_ADD: x += z; MG_SOLVE: x = b / diag (a level of one node).  With `dot`
-// the partial sums of dot^T x (the PCG residual against the
-// preconditioned one) per workgroup and member slot.
-struct MgVecArgs {
-  const double* b;
-  const double* z;
-  const double* V;   // MG_SOLVE: the diagonal slot 13
-  double* x;
-  const double* dot;
-  double* partial;   // [groups][Sp]
-  const int* done;
-  int op, S, Sp;
-  size_t nr, vstride;
-};
-
 // The coarse end of the V-cycle in one launch: levels of at most
 // kMgTailNodes nodes per direction (7, 3, 1 or 3, 1), one workgroup per
 // member holding the levels' operators and vectors in LDS.  Input: the
@@ -126,8 +108,6 @@ void launch_mg_tail(const MgTailArgs& a, hipStream_t s);
 void launch_mg_gersh(const MgGershArgs& a, int groups, hipStream_t s);
 void launch_mg_coef(const MgCoefArgs& a, hipStream_t s);
 void launch_mg_transfer(const MgTransferArgs& a, hipStream_t s);
-// returns the workgroups launched (the partial sums' G)
-int launch_mg_vec(const MgVecArgs& a, hipStream_t s);
 int mg_groups(size_t nr, int Sp);
 
 }  // namespace ens

@@ -8,7 +8,7 @@
 // formed per member on the device.  The smoothing steps and residuals run in
 // the 3-D product kernel (fe3d.hip); this file holds the Galerkin product,
 // the smoothers' spectral bounds and coefficients, the grid transfers and
-// the level-wise vector kernels.
+// the coarse levels' V-cycle in one launch.
 //
 // Layout as everywhere: member innermost, X[r * S + s], V[k * L + r * S + s]
 // with the 27 slots k = 9 (dk + 1) + 3 (dj + 1) + (di + 1).  One thread per
@@ -229,28 +229,6 @@ __global__ __launch_bounds__(kNT) void mg_prolong_kernel(MgTransferArgs a) {
   }
 }
 
-// ------------------------------------------------------------ level vectors
-// MG_ADD: x += z; MG_SOLVE: x = b / diag; with `dot` the per-workgroup
-// partial sums of dot^T x per member slot.
-__global__ __launch_bounds__(kNT) void mg_vec_kernel(MgVecArgs a) {
-  __shared__ double red[kWaves * 64];
-  if (is_done(a.done)) return;
-  const Lane l = lane_of(a.Sp, a.S);
-  double acc[1] = {0.0};
-  for (size_t p = l.p; l.ok && p < a.nr; p += l.pstride) {
-    const size_t e = p * a.S + l.s;
-    double x;
-    if (a.op == MG_ADD) x = gload(&a.x[e]) + gload(&a.z[e]);
-    else x = gload(&a.b[e]) / gload(&a.V[(size_t)13 * a.vstride + e]);
-    gstore(&a.x[e], x);
-    if (a.dot) acc[0] = fma(gload(&a.dot[e]), x, acc[0]);
-  }
-  if (a.dot) {
-    group_reduce<1>(acc, a.Sp, red);
-    put_partial<1>(a.partial, a.Sp, a.Sp, acc);
-  }
-}
-
 // ------------------------------------------------------------ coarse tail
 // One workgroup per member s runs the V-cycle of the tail levels (at most 7^3
 // nodes, then 3^3, then 1) with each level's 27 operator slots and its
@@ -319,10 +297,15 @@ __device__ __forceinline__ void tail_resid(const TailLv& L, bool start) {
 
 }  // namespace
 
+// Workgroups go round-robin over the eight XCDs, and a cache line holds 16
+// consecutive members: with 8 or more members, workgroup b takes member
+// (b mod 8) ceil(S / 8) + b / 8, so each XCD stages a run of consecutive
+// members and fetches their shared lines once.
 __global__ __launch_bounds__(kNT) void mg_tail_kernel(MgTailArgs a) {
   __shared__ double pool[kMgTailPool];
-  if (is_done(a.done)) return;
-  const int s = blockIdx.x, t = threadIdx.x, S = a.S, nlev = a.nlev;
+  const int b = blockIdx.x, t = threadIdx.x, S = a.S, nlev = a.nlev;
+  const int s = (S >= 8) ? (b & 7) * ((S + 7) >> 3) + (b >> 3) : b;
+  if (s >= S || is_done(a.done)) return;
   // the loops over levels are unrolled, so L[] stays in registers
   TailLv L[kMgTailLevels];
   double* p = pool;
@@ -448,10 +431,10 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 static size_t mg_header_bytes() {
   return align256(sizeof(double) * (size_t)kMgMaxLevels * kMaxS * (kChebCoef + 1));
 }
-// the coarse level's 27 slots and six vectors
+// the coarse level's 27 slots and five vectors
 static size_t mg_level_doubles(int m, int S) {
   const size_t nr = (size_t)m * m * m;
-  return slot_stride(nr * S) * (27 + 6);
+  return slot_stride(nr * S) * (27 + 5);
 }
 
 size_t mg_bytes(int n, int S) {
@@ -487,7 +470,6 @@ void mg_carve(void* base, int n, int S, const int* ctl, MgHierarchy& H) {
     v.res = vec + 2 * vs;
     v.d = vec + 3 * vs;
     v.za = vec + 4 * vs;
-    v.zb = vec + 5 * vs;
     p += sizeof(double) * mg_level_doubles(ms[l], S);
   }
 }
@@ -503,7 +485,8 @@ void launch_mg_rap(const MgRapArgs& a, hipStream_t s) {
 }
 
 void launch_mg_tail(const MgTailArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(mg_tail_kernel, dim3(a.S), dim3(kNT), 0, s, a);
+  const int blocks = (a.S >= 8) ? 8 * ((a.S + 7) / 8) : a.S;
+  hipLaunchKernelGGL(mg_tail_kernel, dim3(blocks), dim3(kNT), 0, s, a);
 }
 
 void launch_mg_gersh(const MgGershArgs& a, int groups, hipStream_t s) {
@@ -522,10 +505,5 @@ void launch_mg_transfer(const MgTransferArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(mg_restrict_kernel, dim3(mg_groups(mc * mc * mc, a.Sp)), dim3(kNT), 0, s, a);
 }
 
-int launch_mg_vec(const MgVecArgs& a, hipStream_t s) {
-  const int G = mg_groups(a.nr, a.Sp);
-  hipLaunchKernelGGL(mg_vec_kernel, dim3(G), dim3(kNT), 0, s, a);
-  return G;
-}
 
 }  // namespace ens

@@ -391,7 +391,7 @@ def test_non_finite_parameters_rejected_before_device_work(L, bad):
 
 def test_multigrid_descriptor_without_gpu(L):
     """ENS_PRECOND_MULTIGRID: the workspace adds the coarse levels (a header of
-    per-level smoother coefficients, then per level 27 matrix slots and six
+    per-level smoother coefficients, then per level 27 matrix slots and five
     vectors of the level's slot stride); the 2-D model and grids with n + 1
     not a power of two are refused before any device work."""
     lib = L.lib()
@@ -412,7 +412,7 @@ def test_multigrid_descriptor_without_gpu(L):
             m = (m - 1) // 2
             levels.append(m)
         head = ((8 * 12 * 64 * (2 * 8 + 2 + 1) + 255) // 256) * 256
-        assert ws - wc == head + sum(8 * 33 * stride(m, S) for m in levels), (n, S)
+        assert ws - wc == head + sum(8 * 32 * stride(m, S) for m in levels), (n, S)
     a = C.c_void_p(4096)
     for bad in (L.ens_problem(10, 4, 0, 3, 0.0), L.ens_problem(31, 4, 0, 2, 0.4),
                 L.ens_problem(16, 4, 0, 3, 0.0)):
