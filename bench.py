@@ -408,7 +408,9 @@ def table_mode(args) -> int:
         y0, workload = np.array([-1.0, 0.0, 0.0, 0.0]), "adaptive-sg-512x512-d4"
     print(f"[bench] adaptive run: levels {[l.n_samples for l in res.levels]}, "
           f"E[G] by level {[l.qoi_mean for l in res.levels]}", flush=True)
-    curve = su_rows(prob, opts, (1, 2, 4, 8, 16, 32, 64), y0)
+    # SU at every width the varying-width grouping may choose from (any S
+    # from 1 to 64 runs; these 15 cover the curve), the fixed widths included
+    curve = su_rows(prob, opts, (1, 2, 3, 4, 6, 8, 12, 16, 20, 24, 32, 40, 48, 56, 64), y0)
     su = {r["S"]: r["SU"] for r in curve}
     print(f"[bench] SU(S): {su}", flush=True)
     # seconds per ensemble iteration at each width, from the same curve

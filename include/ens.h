@@ -425,7 +425,7 @@ int ens_sg_expectation(int32_t d, int32_t M, const int32_t* node_level,
  * combinatorial optimisation from a per-size performance model and the cost
  * surrogate).  Input: pred [M], the predicted iteration count of each sample
  * (a prediction below 1 counts as 1); the allowed widths [n_widths]
- * (ascending, distinct powers of two in [1, 64], n_widths <= 7) and
+ * (ascending, distinct, in [1, 64]: any ensemble width the solver takes) and
  * iter_seconds [n_widths], the time of one ensemble iteration at each width.
  * The samples are ordered by ascending (pred, id) and the order is cut into
  * consecutive groups; group g has a width w_g and holds 1..w_g real samples

@@ -343,10 +343,10 @@ int ens_group_variable(int32_t M, const double* pred, int32_t n_widths, const in
   if (M < 1 || !pred || !widths || !iter_seconds || !order_out || !group_width_out ||
       !group_count_out || !n_groups_out || !cost_out)
     return ENS_EINVAL;
-  if (n_widths < 1 || n_widths > 7) return ENS_EINVAL;
+  if (n_widths < 1 || n_widths > 64) return ENS_EINVAL;
   for (int w = 0; w < n_widths; ++w) {
     const int32_t s = widths[w];
-    if (s < 1 || s > 64 || (s & (s - 1)) != 0) return ENS_EINVAL;
+    if (s < 1 || s > 64) return ENS_EINVAL;
     if (w > 0 && s <= widths[w - 1]) return ENS_EINVAL;
     if (!std::isfinite(iter_seconds[w]) || !(iter_seconds[w] > 0.0)) return ENS_EINVAL;
   }

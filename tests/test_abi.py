@@ -302,13 +302,19 @@ def test_group_variable_bit_exact_with_oracle(L, M, seed):
     g_o, c_o = sg.group_variable(pred, sub, [ts[2], ts[4], ts[6]])
     g_c, c_c = grouping.group_variable(pred, sub, [ts[2], ts[4], ts[6]])
     assert [list(g) for g in g_c] == g_o and c_c == c_o
+    # any widths the solver takes (not only powers of two), up to all 64
+    for wl in ([3, 5, 20, 48], list(range(1, 65))):
+        tw = [w / (1.0 + 3.5 * (1.0 - np.exp(-w / 12.0))) for w in wl]
+        g_o, c_o = sg.group_variable(pred, wl, tw)
+        g_c, c_c = grouping.group_variable(pred, wl, tw)
+        assert [list(g) for g in g_c] == g_o and c_c == c_o
 
 
 def test_group_variable_rejects_bad_arguments(L):
     from paper_1705_02003_amd import grouping
     pred = np.ones(5)
-    for widths, ts in (([3], [1.0]), ([4, 2], [1.0, 1.0]), ([128], [1.0]), ([1], [0.0]),
-                       ([1], [np.inf]), ([1, 1], [1.0, 1.0]), ([], [])):
+    for widths, ts in (([0], [1.0]), ([4, 2], [1.0, 1.0]), ([128], [1.0]), ([65], [1.0]),
+                       ([1], [0.0]), ([1], [np.inf]), ([1, 1], [1.0, 1.0]), ([], [])):
         with pytest.raises(RuntimeError):
             grouping.group_variable(pred, widths, ts)
     with pytest.raises(RuntimeError):
