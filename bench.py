@@ -41,15 +41,16 @@ HBM_PEAK_GBS = 8000.0
 # values (C, E, N, NE, NW; the other four are the neighbours' by symmetry),
 # r, p_old, x and writes p, q, x: 11 FP64 words (15 with --full-stencil,
 # which reads all nine).  A Jacobi-PCG iteration adds the update kernel's
-# 4 words.  A Jacobi-Chebyshev-4 iteration is 40 words (56 with nine): the
+# 4 words.  A Jacobi-Chebyshev-4 iteration is 37 words (53 with nine): the
 # fused PCG step (11), the residual update fused with the first Chebyshev
-# step (reads r, q, diagonal and four more matrix values, writes r, d, z:
-# 10), the second step (five matrix values, z, r, d; writes d, z: 10) and
-# the last (the same without writing d: 9).
+# step (reads r, q, diagonal and four more matrix values, writes r, z: 9),
+# the second step (five matrix values, z_1, r; writes z_2: 8; the increment
+# is formed from the iterates, not stored) and the last (five matrix
+# values, z_2, r, z_1; writes z_3: 9).
 FULL_STENCIL = False
 FUSED_BYTES = 11 * 8
 ITER_BYTES = 15 * 8
-CHEB_ITER_BYTES = 40 * 8
+CHEB_ITER_BYTES = 37 * 8
 
 
 def set_byte_model(full: bool) -> None:
@@ -58,7 +59,7 @@ def set_byte_model(full: bool) -> None:
     extra = 4 if full else 0
     FUSED_BYTES = (11 + extra) * 8
     ITER_BYTES = (15 + extra) * 8
-    CHEB_ITER_BYTES = (40 + 4 * extra) * 8
+    CHEB_ITER_BYTES = (37 + 4 * extra) * 8
 
 
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "stencil_pcg_512x512_S32_traffic.json")

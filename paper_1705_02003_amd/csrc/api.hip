@@ -272,13 +272,17 @@ static void finish(const Workspace& w, const Geometry& g, int G, int kind, hipSt
 }
 
 // One preconditioner application z = p(D^-1 A) D^-1 r: the start step
-// d = z = D^-1 r / theta (already done by the caller when `started`), then
-// degree-1 stencil steps ping-ponging z.  Returns the buffer holding z.
+// z_0 = D^-1 r / theta (already done by the caller when `started`), then
+// degree-1 stencil steps; z_k is in w.z[k & 1].  The 3-D steps keep the
+// increment in w.d (the start writes d = z_0); the 2-D steps form it from
+// the iterates, from the third step on reading z_{k-2} from the buffer that
+// z_k then overwrites.  Returns the buffer holding z.
 static double* cheb_apply(const double* V, const Workspace& w, const Geometry& g, int degree,
                           bool init, bool started, hipStream_t s, const double* r = nullptr,
                           int first_step = 1) {
   if (!r) r = w.r;
-  if (!started) launch_cheb_start(V, r, w.d, w.z[0], w.m, g, init_groups(g), s);
+  if (!started)
+    launch_cheb_start(V, r, g.dim == 3 ? w.d : nullptr, w.z[0], w.m, g, init_groups(g), s);
   for (int k = first_step; k < degree; ++k) {
     StencilArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -286,6 +290,7 @@ static double* cheb_apply(const double* V, const Workspace& w, const Geometry& g
     a.r = r;
     a.src = w.z[(k - 1) & 1];
     a.zout = w.z[k & 1];
+    a.zprev = k >= 3 ? w.z[k & 1] : nullptr;
     a.d = w.d;
     a.partial = w.partial;
     a.m = w.m;
@@ -686,7 +691,6 @@ static int run_solve(const ens_problem* prob, const Opts& o, int S, const double
         c.r = r_in;
         c.q_in = w.q;
         c.r_out = r_out;
-        c.d = w.d;
         c.zout = w.z[1];
         c.partial = w.partial;
         c.m = w.m;

@@ -114,8 +114,9 @@ struct StencilArgs {
   double* pnew;        // new direction (PCG)
   double* q;           // A p (PCG, SPMV)
   double* x;           // solution, deferred update (PCG)
-  double* d;           // Chebyshev increment
+  double* d;           // Chebyshev increment (3-D model; the 2-D sweep stores none)
   double* zout;        // Chebyshev output z
+  const double* zprev; // 2-D Chebyshev step k >= 3: z_{k-2}, read at the own point (may be zout)
   const double* q_in;  // M_CHEB1: A p of the current step
   double* r_out;       // M_CHEB1: the updated residual
   double* partial;     // [groups][Sp]; M_CHEB1: [2][groups][Sp] (r^T z on a last step, r^T r)

@@ -246,8 +246,8 @@ struct TileView {
   double* pnew;
   double* q;
   double* x;
-  double* d;
   double* zout;
+  const double* zprev;  // M_CHEB from the third step on: z_{k-2} (may be zout)
   const double* q_in;   // M_CHEB1
   double* r_out;        // M_CHEB1
   int n, S;        // grid size, ensemble width (row stride of every vector)
@@ -256,7 +256,7 @@ struct TileView {
   int tpp;         // threads per grid point (a power of two)
   int tx, ty, nchunk;
   size_t nelem, vstride;   // elements per vector; from one matrix slot to the next
-  int cheb_last;
+  int cheb_step, cheb_last;
 };
 
 // One tile of the fused sweep: tx grid points of one line chunk times ty
@@ -269,9 +269,14 @@ struct TileView {
 // product is taken from the ring and the mode's fused updates follow:
 //   M_PCG_*: store p and q = A p, accumulate p^T q, apply the deferred
 //            x += alpha_prev p_old;
-//   M_CHEB:  one Chebyshev step d = c1 d + c2 D^-1 (r - A z), z += d, and
-//            on the last step accumulate r^T z (and do not store d, which no
-//            later step reads);
+//   M_CHEB:  one Chebyshev step z_k = z_{k-1} + d_k with
+//            d_k = c1 d_{k-1} + c2 D^-1 (r - A z_{k-1}), and on the last step
+//            accumulate r^T z_k.  The increment is not stored: d_0 = z_0 is
+//            the ring value itself, d_1 = z_1 - z_0 with z_0 = D^-1 r / theta
+//            formed again from r and the diagonal the step reads anyway, and
+//            from the third step on d_{k-1} = z_{k-1} - z_{k-2} with z_{k-2}
+//            read at the own point (ZPREV; z_k may overwrite it in place).
+//            `aprev` carries theta;
 //   M_CHEB1: the residual update and the first Chebyshev step in one sweep:
 //            the ring value is z_0 = (r - alpha q) / diag / theta, and per own
 //            point r' = r - alpha q is stored (to r_out), r'^T r' accumulated,
@@ -286,7 +291,7 @@ struct TileView {
 // previous line are exchanged through `sym` (LDS, 2 x 3 lines of kRing
 // doubles).  The products are formed in the same order as the nine-value
 // sweep, so on a bitwise-symmetric matrix both give the same bits.
-template <int VEC, int MODE, bool SYM>
+template <int VEC, int MODE, bool SYM, bool ZPREV = false>
 __device__ __forceinline__ void stencil_tile(const TileView& a, int tile, double (*ring)[kRing],
                                              double* sym,
                                              const double (&beta)[VEC], const double (&aprev)[VEC],
@@ -431,7 +436,7 @@ __device__ __forceinline__ void stencil_tile(const TileView& a, int tile, double
     }
   }
   for (int j = j0; j < j1; ++j) {
-    // This line's matrix values (and x, or the Chebyshev r and d), the next
+    // This line's matrix values (and x, or the Chebyshev r and z_{k-2}), the next
     // ring line's inputs and the halo values are all issued before any is
     // used: the line costs one memory round trip.
     const size_t rj = (size_t)j * line_stride;
@@ -446,7 +451,7 @@ __device__ __forceinline__ void stencil_tile(const TileView& a, int tile, double
     if constexpr (PCG) ld<VEC>(xv, a.x + e);
     if constexpr (MODE == M_CHEB) {
       ld<VEC>(rr, a.r + e);
-      ld<VEC>(dd, a.d + e);
+      if constexpr (ZPREV) ld<VEC>(dd, a.zprev + e);
     }
     double o0[VEC], o1[VEC], o2[VEC];
     fill_load(row(j + 1) + col, o0, o1, o2);
@@ -547,21 +552,21 @@ __device__ __forceinline__ void stencil_tile(const TileView& a, int tile, double
       }
       if (own_s) {
         st<VEC>(a.r_out + e, cur_pold);
-        if (!a.cheb_last) st<VEC>(a.d + e, dn);
         st<VEC>(a.zout + e, zn);
       }
     } else {  // M_CHEB
       double zn[VEC];
 #pragma unroll
       for (int c = 0; c < VEC; ++c) {
-        dd[c] = c1[c] * dd[c] + c2[c] * ((rr[c] - q[c]) / vk[4][c]);
-        zn[c] = cur_val[c] + dd[c];
+        double dp;   // d_{k-1}
+        if constexpr (ZPREV) dp = cur_val[c] - dd[c];
+        else if (a.cheb_step == 1) dp = cur_val[c];
+        else dp = cur_val[c] - (rr[c] / vk[4][c]) / aprev[c];
+        const double dn = c1[c] * dp + c2[c] * ((rr[c] - q[c]) / vk[4][c]);
+        zn[c] = cur_val[c] + dn;
         if (a.cheb_last) acc[c] = own_s ? fma(rr[c], zn[c], acc[c]) : acc[c];
       }
-      if (own_s) {
-        if (!a.cheb_last) st<VEC>(a.d + e, dd);
-        st<VEC>(a.zout + e, zn);
-      }
+      if (own_s) st<VEC>(a.zout + e, zn);
     }
 #pragma unroll
     for (int c = 0; c < VEC; ++c) {

@@ -132,11 +132,12 @@ __global__ __launch_bounds__(kNT) void assemble_kernel(AsmArgs a) {
 // Then, per point and member, the nine-point product is taken from the ring
 // and the mode's fused updates follow:
 //   M_PCG_*: store p and q = A p, accumulate p^T q, apply the deferred
-//            x += alpha_prev p_old; the last workgroup turns p^T q into alpha
-//            (or freezes a member whose p^T A p is not a positive finite
-//            number -- the paper's guard).
-//   M_CHEB:  one Chebyshev step d = c1 d + c2 D^-1 (r - A z), z += d; the
-//            last step accumulates r^T z and the last workgroup forms beta.
+//            x += alpha_prev p_old (the finishing kernel then turns p^T q
+//            into alpha, or freezes a member whose p^T A p is not a positive
+//            finite number -- the paper's guard).
+//   M_CHEB:  one Chebyshev step d = c1 d_prev + c2 D^-1 (r - A z), z += d,
+//            with d_prev taken from the z iterates rather than stored; the
+//            last step accumulates r^T z.
 template <int VEC, int MODE, bool SYM>
 __global__ __launch_bounds__(kNT) void stencil_kernel(StencilArgs a) {
   __shared__ __attribute__((aligned(16))) double ring[4][kRing];
@@ -157,8 +158,8 @@ __global__ __launch_bounds__(kNT) void stencil_kernel(StencilArgs a) {
   tv.pnew = a.pnew;
   tv.q = a.q;
   tv.x = a.x;
-  tv.d = a.d;
   tv.zout = a.zout;
+  tv.zprev = a.zprev;
   tv.q_in = a.q_in;
   tv.r_out = a.r_out;
   tv.n = g.n;
@@ -169,6 +170,7 @@ __global__ __launch_bounds__(kNT) void stencil_kernel(StencilArgs a) {
   tv.nchunk = g.nchunk;
   tv.nelem = g.nelem;
   tv.vstride = g.vstride;
+  tv.cheb_step = a.cheb_step;
   tv.cheb_last = a.cheb_last;
   // Every workgroup sweeps the same spatial tiles for each member tile, so
   // each member's partial sums follow the same tree.
@@ -190,19 +192,24 @@ __global__ __launch_bounds__(kNT) void stencil_kernel(StencilArgs a) {
         aprev[c] = a.m.alpha_prev[sv + c];
       }
       if constexpr (MODE == M_CHEB1) {
-        // alpha of active members, theta
+        // alpha of active members
         beta[c] = a.m.active[sv + c] ? a.m.alpha[sv + c] : 0.0;
-        aprev[c] = a.m.cheb[(size_t)(sv + c) * kChebCoef];
       }
       if constexpr (MODE == M_CHEB || MODE == M_CHEB1) {
+        aprev[c] = a.m.cheb[(size_t)(sv + c) * kChebCoef];   // theta
         c1[c] = a.m.cheb[(size_t)(sv + c) * kChebCoef + 2 * a.cheb_step - 1];
         c2[c] = a.m.cheb[(size_t)(sv + c) * kChebCoef + 2 * a.cheb_step];
       }
     }
     int tile, tstep, tend;
     tile_range(g, tile, tstep, tend);
-    for (; tile < tend; tile += tstep)
-      stencil_tile<VEC, MODE, SYM>(tv, tile, ring, sym, beta, aprev, c1, c2, acc, acc2);
+    if (MODE == M_CHEB && a.cheb_step >= 3) {
+      for (; tile < tend; tile += tstep)
+        stencil_tile<VEC, MODE, SYM, true>(tv, tile, ring, sym, beta, aprev, c1, c2, acc, acc2);
+    } else {
+      for (; tile < tend; tile += tstep)
+        stencil_tile<VEC, MODE, SYM>(tv, tile, ring, sym, beta, aprev, c1, c2, acc, acc2);
+    }
     if constexpr (MODE == M_PCG_J || MODE == M_PCG_Z) {
       group_reduce<VEC>(acc, tpp, red);
       put_partial<VEC>(a.partial, g.Sp, tpp, acc, tv.s0);
@@ -358,7 +365,8 @@ __global__ __launch_bounds__(kNT) void init_kernel(InitArgs a) {
   }
 }
 
-// Chebyshev: d = z = D^-1 r / theta for every member (start of an application)
+// Chebyshev: z = D^-1 r / theta for every member (start of an application),
+// and d = z where the caller keeps the increment (the 3-D model)
 template <int VEC>
 __global__ __launch_bounds__(kNT) void cheb_start_kernel(const double* V, const double* r, double* d,
                                                          double* z, Members m, Geometry g) {
@@ -376,7 +384,7 @@ __global__ __launch_bounds__(kNT) void cheb_start_kernel(const double* V, const 
     ld<VEC>(dv, V + (size_t)g.cslot * g.vstride + e);
 #pragma unroll
     for (int c = 0; c < VEC; ++c) zz[c] = (rv[c] / dv[c]) / ith[c];
-    st<VEC>(d + e, zz);
+    if (d) st<VEC>(d + e, zz);
     st<VEC>(z + e, zz);
   }
 }
