@@ -351,6 +351,7 @@ static void mg_setup(const MgHierarchy& H, const Workspace& w, double ratio, hip
     ra.vstride_f = f.g.vstride;
     ra.vstride_c = c.g.vstride;
     launch_mg_rap(ra, s);
+    if (!H.levelwise && c.Vt) launch_mg_pack(c.V, c.g.vstride, c.Vt, c.m, c.g.S, s);
     MgGershArgs ga;
     std::memset(&ga, 0, sizeof(ga));
     ga.V = c.V;
@@ -429,9 +430,8 @@ static void mg_cycle(const MgHierarchy& H, int l, hipStream_t s, const double* d
     ta.nlev = H.L - (l + 1);
     for (int j = 0; j < ta.nlev; ++j) {
       const MgLevel& q = H.lv[l + 1 + j];
-      ta.lv[j].V = q.V;
+      ta.lv[j].Vt = q.Vt;
       ta.lv[j].cheb = q.mem.cheb;
-      ta.lv[j].vstride = q.g.vstride;
       ta.lv[j].m = q.m;
     }
     ta.b = c.b;

@@ -22,6 +22,8 @@ struct MgLevel {
   double* res;      // residual b - A x
   double* d;        // smoother increment
   double* za;       // smoother iterate (started by the caller)
+  double* Vt;       // levels of at most kMgTailNodes nodes per direction: the 27
+                    // slots member-major, [S][27][m^3], for the fused coarse tail
   Members mem;
 };
 
@@ -34,7 +36,9 @@ struct MgHierarchy {
 // nodes per direction of each level (n, (n - 1) / 2, ..., 1); 0 if n + 1 is
 // not a power of two >= 2 or there would be more than kMgMaxLevels levels
 int mg_levels(int n, int* ms);
-// bytes of the coarse levels (1 .. L - 1) for an ensemble of S members
+// bytes of the coarse levels (1 .. L - 1) for an ensemble of S members,
+// with the member-major operator copies of the levels of at most
+// kMgTailNodes nodes per direction
 size_t mg_bytes(int n, int S);
 // carve the coarse levels from `base` (mg_bytes(n, S) bytes); level 0's
 // fields are left for the caller
@@ -89,9 +93,8 @@ struct MgTransferArgs {
 constexpr int kMgTailNodes = 7;
 constexpr int kMgTailLevels = 3;
 struct MgTailLevel {
-  const double* V;     // 27 slots of stride vstride
+  const double* Vt;    // 27 slots member-major: [S][27][m^3]
   const double* cheb;  // [Sp][kChebCoef]: theta, c1, c2
-  size_t vstride;
   int m;
 };
 struct MgTailArgs {
@@ -105,6 +108,8 @@ struct MgTailArgs {
 
 void launch_mg_rap(const MgRapArgs& a, hipStream_t s);
 void launch_mg_tail(const MgTailArgs& a, hipStream_t s);
+// Vt[s][slot][r] = V[slot * vstride + r * S + s] for the m^3 rows of a level
+void launch_mg_pack(const double* V, size_t vstride, double* Vt, int m, int S, hipStream_t s);
 void launch_mg_gersh(const MgGershArgs& a, int groups, hipStream_t s);
 void launch_mg_coef(const MgCoefArgs& a, hipStream_t s);
 void launch_mg_transfer(const MgTransferArgs& a, hipStream_t s);

@@ -241,6 +241,8 @@ __global__ __launch_bounds__(kNT) void mg_prolong_kernel(MgTransferArgs a) {
 // the prolongation over cz, cy, cx, and x + (za + dd) for the post-smoother's
 // correction; so the results are the same bits.
 constexpr int kMgTailPool = 32 * (343 + 27 + 1);   // 27 slots + 5 vectors per node
+constexpr int kTailNT = 512;     // threads of the tail workgroup: one 7^3 node each
+constexpr int kTailStage = 21;   // staged elements a thread has in flight (one batch at 7^3)
 
 namespace {
 
@@ -272,7 +274,7 @@ __device__ __forceinline__ double tail_apply(const TailLv& L, const double* p, i
 // one Chebyshev step from src (d in place): out = src + dd, or x += src + dd
 __device__ __forceinline__ void tail_cheb(const TailLv& L, const double* rv, const double* src, double* out,
                                           bool accumulate) {
-  for (int r = threadIdx.x; r < L.nr; r += kNT) {
+  for (int r = threadIdx.x; r < L.nr; r += kTailNT) {
     const double q = tail_apply(L, src, r);
     const double dd = fma(L.c1, L.d[r], L.c2 * ((rv[r] - q) / L.A[13 * L.nr + r]));
     L.d[r] = dd;
@@ -284,7 +286,7 @@ __device__ __forceinline__ void tail_cheb(const TailLv& L, const double* rv, con
 
 // res = b - A x, with `start` also d = za = (res / diag) / theta
 __device__ __forceinline__ void tail_resid(const TailLv& L, bool start) {
-  for (int r = threadIdx.x; r < L.nr; r += kNT) {
+  for (int r = threadIdx.x; r < L.nr; r += kTailNT) {
     const double rr = L.b[r] - tail_apply(L, L.x, r);
     L.res[r] = rr;
     if (start) {
@@ -297,11 +299,12 @@ __device__ __forceinline__ void tail_resid(const TailLv& L, bool start) {
 
 }  // namespace
 
-// Workgroups go round-robin over the eight XCDs, and a cache line holds 16
-// consecutive members: with 8 or more members, workgroup b takes member
-// (b mod 8) ceil(S / 8) + b / 8, so each XCD stages a run of consecutive
-// members and fetches their shared lines once.
-__global__ __launch_bounds__(kNT) void mg_tail_kernel(MgTailArgs a) {
+// One workgroup of kTailNT threads per member.  Workgroups go round-robin
+// over the eight XCDs, and a cache line of b or x holds 16 consecutive
+// members: with 8 or more members, workgroup b takes member
+// (b mod 8) ceil(S / 8) + b / 8, so each XCD reads and writes a run of
+// consecutive members and fetches their shared lines once.
+__global__ __launch_bounds__(kTailNT) void mg_tail_kernel(MgTailArgs a) {
   __shared__ double pool[kMgTailPool];
   const int b = blockIdx.x, t = threadIdx.x, S = a.S, nlev = a.nlev;
   const int s = (S >= 8) ? (b & 7) * ((S + 7) >> 3) + (b >> 3) : b;
@@ -330,23 +333,52 @@ __global__ __launch_bounds__(kNT) void mg_tail_kernel(MgTailArgs a) {
       v.c2 = gload(&cf[2]);
     }
   }
-  // stage the operators and the first level's right-hand side
+  // Stage the operators (member-major copies: one contiguous run per
+  // level) and the first level's right-hand side: element idx of
+  // [A_0 | A_1 | A_2 | b_0] (empty segments for absent levels).  A thread
+  // issues the loads of kTailStage elements (at clamped indices, no branch)
+  // before it stores any, so staging costs a few memory round trips.
+  {
+    int end[kMgTailLevels + 1];
+    int tot = 0;
 #pragma unroll
-  for (int j = 0; j < kMgTailLevels; ++j) {
-    if (j >= nlev) break;
-    const TailLv& v = L[j];
-    const double* V = a.lv[j].V;
-    const size_t vs = a.lv[j].vstride;
-    for (int idx = t; idx < 27 * v.nr; idx += kNT) {
-      const int slot = idx / v.nr, r = idx - slot * v.nr;
-      v.A[idx] = gload(&V[(size_t)slot * vs + (size_t)r * S + s]);
+    for (int j = 0; j < kMgTailLevels; ++j) {
+      tot += j < nlev ? 27 * L[j].nr : 0;
+      end[j] = tot;
+    }
+    tot += L[0].nr;
+    end[kMgTailLevels] = tot;
+    const int off0 = (int)(L[0].A - pool), off1 = (int)(L[1].A - pool),
+              off2 = (int)(L[2].A - pool), offb = (int)(L[0].b - pool);
+    static_assert(kMgTailLevels == 3, "the staging map names three levels");
+    // level j's run for member s starts at Vt_j + s 27 nr_j; b_0 is strided
+    const double* V0 = a.lv[0].Vt + (size_t)s * 27 * L[0].nr;
+    const double* V1 = nlev > 1 ? a.lv[1].Vt + (size_t)s * 27 * L[1].nr : V0;
+    const double* V2 = nlev > 2 ? a.lv[2].Vt + (size_t)s * 27 * L[2].nr : V0;
+    for (int base = t; base < tot; base += kTailStage * kTailNT) {
+      double val[kTailStage];
+      int dst[kTailStage];
+#pragma unroll
+      for (int u = 0; u < kTailStage; ++u) {
+        const int idx = min(base + u * kTailNT, tot - 1);
+        const int j = (idx >= end[0]) + (idx >= end[1]) + (idx >= end[2]);   // 3: b
+        const int lo = j == 0 ? 0 : (j == 1 ? end[0] : (j == 2 ? end[1] : end[2]));
+        const int loc = idx - lo;
+        const double* src = j == 0 ? V0 + loc
+                                   : (j == 1 ? V1 + loc
+                                             : (j == 2 ? V2 + loc : a.b + (size_t)loc * S + s));
+        val[u] = gload(src);
+        dst[u] = (j == 0 ? off0 : (j == 1 ? off1 : (j == 2 ? off2 : offb))) + loc;
+      }
+#pragma unroll
+      for (int u = 0; u < kTailStage; ++u)
+        if (base + u * kTailNT < tot) pool[dst[u]] = val[u];
     }
   }
-  for (int r = t; r < L[0].nr; r += kNT) L[0].b[r] = gload(&a.b[(size_t)r * S + s]);
   __syncthreads();
   {
     const TailLv& v = L[0];
-    for (int r = t; r < v.nr; r += kNT) {
+    for (int r = t; r < v.nr; r += kTailNT) {
       const double z = (v.b[r] / v.A[13 * v.nr + r]) / v.th;
       v.d[r] = z;
       v.za[r] = z;
@@ -365,7 +397,7 @@ __global__ __launch_bounds__(kNT) void mg_tail_kernel(MgTailArgs a) {
     __syncthreads();
     const TailLv& c = L[j + 1];
     const int mc = c.m, mf = v.m;
-    for (int pc = t; pc < c.nr; pc += kNT) {
+    for (int pc = t; pc < c.nr; pc += kTailNT) {
       const int I = pc % mc + 1, J = (pc / mc) % mc + 1, K = pc / (mc * mc) + 1;
       double acc = 0.0;
       for (int fz = -1; fz <= 1; ++fz)
@@ -393,7 +425,7 @@ __global__ __launch_bounds__(kNT) void mg_tail_kernel(MgTailArgs a) {
     const TailLv& v = L[j];
     const TailLv& c = L[j + 1];
     const int mc = c.m, mf = v.m;
-    for (int pf = t; pf < v.nr; pf += kNT) {
+    for (int pf = t; pf < v.nr; pf += kTailNT) {
       const int i = pf % mf + 1, jj = (pf / mf) % mf + 1, k = pf / (mf * mf) + 1;
       double acc = 0.0;
       for (int cz = k / 2; cz <= (k + 1) / 2; ++cz)
@@ -411,7 +443,19 @@ __global__ __launch_bounds__(kNT) void mg_tail_kernel(MgTailArgs a) {
     tail_cheb(v, v.res, v.za, nullptr, true);
     __syncthreads();
   }
-  for (int r = t; r < L[0].nr; r += kNT) gstore(&a.x[(size_t)r * S + s], L[0].x[r]);
+  for (int r = t; r < L[0].nr; r += kTailNT) gstore(&a.x[(size_t)r * S + s], L[0].x[r]);
+}
+
+// The member-major copy of a level's operator for the fused tail:
+// Vt[s][slot][r] = V[slot * vstride + r * S + s].
+__global__ __launch_bounds__(kNT) void mg_pack_kernel(const double* V, size_t vstride, double* Vt,
+                                                      int nr, int S) {
+  const size_t per = (size_t)27 * nr, n = per * S;
+  for (size_t e = (size_t)blockIdx.x * kNT + threadIdx.x; e < n; e += (size_t)gridDim.x * kNT) {
+    const size_t s = e / per, rem = e - s * per;
+    const size_t slot = rem / nr, r = rem - slot * nr;
+    Vt[e] = V[slot * vstride + r * S + s];
+  }
 }
 
 // ------------------------------------------------------------ hierarchy
@@ -437,12 +481,18 @@ static size_t mg_level_doubles(int m, int S) {
   return slot_stride(nr * S) * (27 + 5);
 }
 
+// the member-major operator copy that the fused coarse tail stages
+static size_t mg_tail_copy_bytes(int m, int S) {
+  return m <= kMgTailNodes ? align256(sizeof(double) * 27 * (size_t)m * m * m * S) : 0;
+}
+
 size_t mg_bytes(int n, int S) {
   int ms[kMgMaxLevels];
   const int L = mg_levels(n, ms);
   if (L == 0) return 0;
   size_t b = mg_header_bytes();
-  for (int l = 1; l < L; ++l) b += sizeof(double) * mg_level_doubles(ms[l], S);
+  for (int l = 1; l < L; ++l)
+    b += sizeof(double) * mg_level_doubles(ms[l], S) + mg_tail_copy_bytes(ms[l], S);
   return b;
 }
 
@@ -471,6 +521,10 @@ void mg_carve(void* base, int n, int S, const int* ctl, MgHierarchy& H) {
     v.d = vec + 3 * vs;
     v.za = vec + 4 * vs;
     p += sizeof(double) * mg_level_doubles(ms[l], S);
+    if (ms[l] <= kMgTailNodes) {
+      v.Vt = reinterpret_cast<double*>(p);
+      p += mg_tail_copy_bytes(ms[l], S);
+    }
   }
 }
 
@@ -486,7 +540,13 @@ void launch_mg_rap(const MgRapArgs& a, hipStream_t s) {
 
 void launch_mg_tail(const MgTailArgs& a, hipStream_t s) {
   const int blocks = (a.S >= 8) ? 8 * ((a.S + 7) / 8) : a.S;
-  hipLaunchKernelGGL(mg_tail_kernel, dim3(blocks), dim3(kNT), 0, s, a);
+  hipLaunchKernelGGL(mg_tail_kernel, dim3(blocks), dim3(kTailNT), 0, s, a);
+}
+
+void launch_mg_pack(const double* V, size_t vstride, double* Vt, int m, int S, hipStream_t s) {
+  const size_t n = (size_t)27 * m * m * m * S;
+  const int groups = (int)std::min<size_t>((n + kNT - 1) / kNT, 1024);
+  hipLaunchKernelGGL(mg_pack_kernel, dim3(groups), dim3(kNT), 0, s, V, vstride, Vt, m * m * m, S);
 }
 
 void launch_mg_gersh(const MgGershArgs& a, int groups, hipStream_t s) {

@@ -285,6 +285,46 @@ def test_chebyshev_pcg_matches_oracle():
     assert worst <= 1e-9
 
 
+@pytest.mark.parametrize("degree,S,kw", [
+    (2, 8, {}), (3, 20, {}), (5, 64, {"member_tile": 16}), (6, 1, {}), (8, 5, {"tile_lines": 3}),
+])
+def test_chebyshev_degrees_match_oracle(degree, S, kw):
+    """Every polynomial degree the solver takes (2..8): the application
+    within 1e-13 of the oracle, and Chebyshev-PCG counts within +-1 and
+    equal-count solutions within 1e-9.  The oracle keeps the three-term
+    recurrence with a stored increment; the 2-D steps form the increment
+    from the iterates and, from the third step on, overwrite z_{k-2} with z_k
+    in place, so degrees above 4 run that alternation several times."""
+    ens = E()
+    n = 41
+    prob = ens.Problem(n, 8, 1, 0.45)
+    ys = np.random.default_rng(100 + degree).uniform(-1, 1, (S, 8))
+    V, b = gpu_stencil(prob, ys)
+    log_case(test="cheb_degree", degree=degree, S=S, **kw)
+    opts = ens.SolverOptions(precond="chebyshev", cheb_degree=degree, **kw)
+    R = np.random.default_rng(7).standard_normal((n * n, S))
+    z, lmax = ens.cheb_apply(prob, V, to_dev(R), opts)
+    z = z.cpu().numpy()
+    res = ens.solve(prob, V, b, opts)
+    xg = res.x.cpu().numpy()
+    for s in sorted({0, S // 2, S - 1}):
+        A, bo, dg = oracle_system(ys[s], n, 1, 0.45)
+        lm = opcg.gershgorin_lmax(A, dg)
+        assert lmax[s] == pytest.approx(lm, rel=1e-14)
+        ref = opcg.chebyshev_apply(A, dg, R[:, s], lm, degree=degree)
+        assert np.linalg.norm(z[:, s] - ref) <= 1e-13 * np.linalg.norm(ref)
+
+        def M(v, A=A, dg=dg, lm=lm):
+            return opcg.chebyshev_apply(A, dg, v, lm, degree=degree)
+
+        xo, Io, so, _ = opcg.pcg(A, bo, dg, 1e-8, 20000, M)
+        assert so == CONVERGED and res.status[s] == CONVERGED
+        assert abs(int(res.iters[s]) - Io) <= 1, (s, res.iters[s], Io)
+        xe, _, _, _ = opcg.pcg(A, bo, dg, 0.0, int(res.iters[s]), M)
+        assert np.linalg.norm(xg[:, s] - xe) <= 1e-9 * np.linalg.norm(xe)
+        assert np.abs(xg[:, s] - xe).max() <= 1e-9 * np.abs(xe).max()
+
+
 def test_member_dot():
     ens = E()
     rng = np.random.default_rng(17)
