@@ -226,9 +226,9 @@ int ens_pcg_solve(const ens_problem* prob, const ens_opts* opts, int32_t S,
  * it to the host and synchronising `stream` once per poll interval.
  * Arguments and outputs as ens_pcg_solve (without stats).
  * Errors: as ens_pcg_solve; ENS_ENOMEM when ens_pcg_workspace_bytes(prob,
- * opts, S) exceeds ENS_NOALLOC_SCRATCH_BYTES (Jacobi: up to about 1.6e6
- * member-rows N_r * S; Chebyshev: about 1.0e6; multigrid, whose coarse
- * levels add about 4.4 vectors: about 0.63e6, e.g. 31^3 nodes at S = 21).
+ * opts, S) exceeds ENS_NOALLOC_SCRATCH_BYTES (Jacobi: up to about 1.5e6
+ * member-rows N_r * S; Chebyshev: about 1.1e6; multigrid, whose coarse
+ * levels add about 4.2 vectors: about 0.68e6, e.g. 31^3 nodes at S = 23).
  * Every call on one device uses that device's array and leaves its contents
  * behind (the solve clears what must start at zero): calls that overlap on
  * one device, from several threads or streams, race and give wrong results.

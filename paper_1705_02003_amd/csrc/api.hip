@@ -37,7 +37,7 @@ static size_t header_bytes() {
   return b;
 }
 
-static int n_vectors(bool cheb) { return cheb ? 8 : 5; }
+static int n_vectors(bool cheb) { return cheb ? 7 : 5; }
 
 // bytes from one workspace vector to the next (see slot_stride)
 static size_t vector_bytes(size_t nr, int S) { return sizeof(double) * slot_stride(nr * S); }
@@ -76,7 +76,7 @@ Workspace carve_workspace(void* base, size_t nr, int S, bool cheb) {
   p += align256(sizeof(int) * CTL_COUNT);
   if (nr > 0) {
     const size_t vec = vector_bytes(nr, S);
-    double** slots[8] = {&w.p[0], &w.p[1], &w.q, &w.r, &w.aux, &w.z[0], &w.z[1], &w.d};
+    double** slots[7] = {&w.p[0], &w.p[1], &w.q, &w.r, &w.aux, &w.z[0], &w.z[1]};
     for (int k = 0; k < n_vectors(cheb); ++k) {
       *slots[k] = reinterpret_cast<double*>(p);
       p += vec;
@@ -273,16 +273,15 @@ static void finish(const Workspace& w, const Geometry& g, int G, int kind, hipSt
 
 // One preconditioner application z = p(D^-1 A) D^-1 r: the start step
 // z_0 = D^-1 r / theta (already done by the caller when `started`), then
-// degree-1 stencil steps; z_k is in w.z[k & 1].  The 3-D steps keep the
-// increment in w.d (the start writes d = z_0); the 2-D steps form it from
-// the iterates, from the third step on reading z_{k-2} from the buffer that
-// z_k then overwrites.  Returns the buffer holding z.
+// degree-1 stencil steps; z_k is in w.z[k & 1].  The steps form the
+// increment from the iterates (no vector of it is kept), from the third step
+// on reading z_{k-2} from the buffer that z_k then overwrites.  Returns the
+// buffer holding z.
 static double* cheb_apply(const double* V, const Workspace& w, const Geometry& g, int degree,
                           bool init, bool started, hipStream_t s, const double* r = nullptr,
                           int first_step = 1) {
   if (!r) r = w.r;
-  if (!started)
-    launch_cheb_start(V, r, g.dim == 3 ? w.d : nullptr, w.z[0], w.m, g, init_groups(g), s);
+  if (!started) launch_cheb_start(V, r, w.z[0], w.m, g, init_groups(g), s);
   for (int k = first_step; k < degree; ++k) {
     StencilArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -291,7 +290,6 @@ static double* cheb_apply(const double* V, const Workspace& w, const Geometry& g
     a.src = w.z[(k - 1) & 1];
     a.zout = w.z[k & 1];
     a.zprev = k >= 3 ? w.z[k & 1] : nullptr;
-    a.d = w.d;
     a.partial = w.partial;
     a.m = w.m;
     a.g = g;
@@ -319,8 +317,8 @@ static Geometry geometry_for(const ens_problem* prob, const Opts& o, int S) {
 // ------------------------------------------------------------ multigrid
 // Level 0 of the V-cycle works in the solve's own vectors: its right-hand
 // side is the PCG residual r, its output z[1] (the direction source of the
-// next step), its smoother start d, z[0] (written by the residual update)
-// and its residual aux.  Its smoother coefficients are the solve's (the
+// next step), its smoother start z[0] (written by the residual update) and
+// its residual aux.  Its smoother coefficients are the solve's (the
 // initialisation computes them with degree 2).
 static void mg_bind_fine(MgHierarchy& H, const double* V, const Workspace& w, const Geometry& g) {
   MgLevel& f = H.lv[0];
@@ -329,7 +327,6 @@ static void mg_bind_fine(MgHierarchy& H, const double* V, const Workspace& w, co
   f.b = w.r;
   f.x = w.z[1];
   f.res = w.aux;
-  f.d = w.d;
   f.za = w.z[0];
   f.mem = w.m;
 }
@@ -376,7 +373,7 @@ static void mg_setup(const MgHierarchy& H, const Workspace& w, double ratio, hip
 }
 
 // x_l = V_l(b_l) for a level above the coarsest, whose pre-smoother start
-// (d, za) is in place: pre-smoothing, residual, restriction (starting the
+// za is in place: pre-smoothing, residual, restriction (starting the
 // next level's smoother, or solving the one-node coarsest level), the
 // coarse cycle, prolongation, the residual with the post-smoother's start,
 // and post-smoothing with its result added to x in place (on level 0 with
@@ -393,7 +390,6 @@ static void mg_cycle(const MgHierarchy& H, int l, hipStream_t s, const double* d
   a.g = v.g;
   a.r = v.b;
   a.src = v.za;
-  a.d = v.d;
   a.zout = v.x;
   a.cheb_step = 1;
   launch_fe3d<M_CHEB>(a, s);
@@ -414,7 +410,6 @@ static void mg_cycle(const MgHierarchy& H, int l, hipStream_t s, const double* d
   t.coarse_out = const_cast<double*>(c.b);
   t.Vc = c.V;
   t.cheb = c.mem.cheb;
-  t.d = c.d;
   t.z = c.za;
   t.x = c.x;
   t.done = done;
@@ -458,7 +453,6 @@ static void mg_cycle(const MgHierarchy& H, int l, hipStream_t s, const double* d
   a.r = v.b;
   a.src = v.x;
   a.q = v.res;
-  a.d = v.d;
   a.zout = v.za;
   a.cheb_init = 1;
   launch_fe3d<M_RESID>(a, s);
@@ -468,7 +462,6 @@ static void mg_cycle(const MgHierarchy& H, int l, hipStream_t s, const double* d
   a.g = v.g;
   a.r = v.res;
   a.src = v.za;
-  a.d = v.d;
   a.x = v.x;
   a.dotv = dotv;
   a.partial = partial;
@@ -623,7 +616,7 @@ static int run_solve(const ens_problem* prob, const Opts& o, int S, const double
   }
   double* zfinal = nullptr;
   if (mg) {
-    launch_cheb_start(V, w.r, w.d, w.z[0], w.m, g, ge, s);
+    launch_cheb_start(V, w.r, w.z[0], w.m, g, ge, s);
     mg_apply(H, w, true, s);
     zfinal = w.z[1];
   } else if (cheb) {
@@ -706,7 +699,6 @@ static int run_solve(const ens_problem* prob, const Opts& o, int S, const double
         u.V = V;
         u.r = w.r;
         u.q = w.q;
-        u.d = w.d;
         u.z = w.z[0];
         u.partial = w.partial;
         u.m = w.m;
@@ -1137,7 +1129,7 @@ int ens_mg_apply(const ens_problem* prob, const ens_opts* opts, int32_t S, const
   }
   // every member is preconditioned, whatever its residual
   hipLaunchKernelGGL(clear_ctl_kernel, dim3(1), dim3(64), 0, s, w.m.ctl);
-  launch_cheb_start(V_dev, w.r, w.d, w.z[0], w.m, g, init_groups(g), s);
+  launch_cheb_start(V_dev, w.r, w.z[0], w.m, g, init_groups(g), s);
   mg_apply(H, w, true, s);
   HIPCHECK(hipGetLastError());
   HIPCHECK(hipMemcpyAsync(z_dev, w.z[1], sizeof(double) * g.nelem, hipMemcpyDeviceToDevice, s));

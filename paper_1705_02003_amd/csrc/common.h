@@ -50,7 +50,6 @@ struct Workspace {
   double* q;      // A p
   double* r;      // residual
   double* z[2];   // preconditioned residual (Chebyshev ping-pong)
-  double* d;      // Chebyshev increment
   double* aux;    // one extra vector (adjoint right-hand side)
   double* partial;  // [3][kMaxGroups][S]
   Members m;
@@ -114,9 +113,8 @@ struct StencilArgs {
   double* pnew;        // new direction (PCG)
   double* q;           // A p (PCG, SPMV)
   double* x;           // solution, deferred update (PCG)
-  double* d;           // Chebyshev increment (3-D model; the 2-D sweep stores none)
   double* zout;        // Chebyshev output z
-  const double* zprev; // 2-D Chebyshev step k >= 3: z_{k-2}, read at the own point (may be zout)
+  const double* zprev; // Chebyshev step k >= 3: z_{k-2}, read at the own point (may be zout)
   const double* q_in;  // M_CHEB1: A p of the current step
   double* r_out;       // M_CHEB1: the updated residual
   double* partial;     // [groups][Sp]; M_CHEB1: [2][groups][Sp] (r^T z on a last step, r^T r)
@@ -132,8 +130,7 @@ struct UpdateArgs {
   const double* V;
   double* r;
   const double* q;
-  double* d;        // Chebyshev: D^-1 r / theta
-  double* z;        // Chebyshev: z = d
+  double* z;        // Chebyshev: z_0 = D^-1 r / theta
   double* partial;  // [2][groups][Sp]: r^T z (Jacobi), r^T r
   Members m;
   Geometry g;
@@ -192,7 +189,7 @@ template <int MODE>
 void launch_stencil(const StencilArgs& a, hipStream_t s);
 void launch_update(const UpdateArgs& a, bool cheb, int groups, hipStream_t s);
 void launch_init(const InitArgs& a, int groups, hipStream_t s);
-void launch_cheb_start(const double* V, const double* r, double* d, double* z, const Members& m,
+void launch_cheb_start(const double* V, const double* r, double* z, const Members& m,
                        const Geometry& g, int groups, hipStream_t s);
 void launch_final(double* x, const double* p0, const double* p1, const Members& m,
                   const Geometry& g, int groups, hipStream_t s);

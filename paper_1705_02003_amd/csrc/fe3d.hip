@@ -17,10 +17,11 @@
 //            and the deferred x += alpha_prev p_old), then the product
 //            q = A p with the partial sums of p^T q;
 //   M_SPMV:  q = A p;
-//   M_CHEB:  one Chebyshev step d = c1 d + c2 D^-1 (r - A z), z_out = z + d,
-//            on the last step with the partial sums of r^T z_out;
+//   M_CHEB:  one Chebyshev step d = c1 d_prev + c2 D^-1 (r - A z),
+//            z_out = z + d (d_prev formed from the iterates), on the last step
+//            with the partial sums of r^T z_out;
 //   M_RESID: the residual q = r - A x of a multigrid level, optionally with
-//            its smoother's start d = z_out = D^-1 q / theta;
+//            its smoother's start z_out = D^-1 q / theta;
 //   M_CHEBX: a multigrid post-smoother's Chebyshev step added to the
 //            level's x in place, optionally with the partial sums of
 //            dotv^T x.
@@ -507,32 +508,41 @@ void fe3d_stencil_kernel(StencilArgs a) {
 #pragma unroll
           for (int c = 0; c < VEC; ++c)
             zn[c] = (rr[c] / dg[c]) / gload(&a.m.cheb[(size_t)(sv + c) * kChebCoef]);
-          st<VEC>(a.d + e, zn);
           st<VEC>(a.zout + e, zn);
         }
       } else {  // M_CHEB, M_CHEBX
         // the step's coefficients and the diagonal are loaded again here
         // (cached) rather than held in registers across the sweep, which
-        // keeps the kernel at three waves per SIMD without spilling
-        double rr[VEC], dd[VEC], zn[VEC], dg[VEC], c1[VEC], c2[VEC], xv[VEC], dv[VEC];
+        // keeps the kernel at three waves per SIMD without spilling.  No
+        // increment vector is kept: d_0 = z_0 is the source itself (M_CHEBX
+        // is always a first step), d_1 = z_1 - z_0 with z_0 = D^-1 r / theta
+        // formed again, and from the third step on d_{k-1} = z_{k-1} - z_{k-2}
+        // with z_{k-2} read at the own point (zprev, which zout overwrites).
+        const int step = (MODE == M_CHEBX) ? 1 : a.cheb_step;
+        double rr[VEC], zp[VEC], zn[VEC], dg[VEC], c1[VEC], c2[VEC], xv[VEC], dv[VEC];
         ld<VEC>(rr, a.r + e);
-        ld<VEC>(dd, a.d + e);
         ld<VEC>(dg, a.V + (size_t)g.cslot * vs + e);
+#pragma unroll
+        for (int c = 0; c < VEC; ++c) zp[c] = 0.0;
+        if (step >= 3) ld<VEC>(zp, a.zprev + e);
         if constexpr (MODE == M_CHEBX) {
           ld<VEC>(xv, a.x + e);
           if (a.dotv) ld<VEC>(dv, a.dotv + e);
         }
 #pragma unroll
         for (int c = 0; c < VEC; ++c) {
-          c1[c] = gload(&a.m.cheb[(size_t)(sv + c) * kChebCoef + 2 * a.cheb_step - 1]);
-          c2[c] = gload(&a.m.cheb[(size_t)(sv + c) * kChebCoef + 2 * a.cheb_step]);
+          c1[c] = gload(&a.m.cheb[(size_t)(sv + c) * kChebCoef + 2 * step - 1]);
+          c2[c] = gload(&a.m.cheb[(size_t)(sv + c) * kChebCoef + 2 * step]);
         }
 #pragma unroll
         for (int c = 0; c < VEC; ++c) {
+          double dp = own[u][c];   // d_{k-1}
+          if (step == 2) dp = own[u][c] - (rr[c] / dg[c]) / gload(&a.m.cheb[(size_t)(sv + c) * kChebCoef]);
+          else if (step >= 3) dp = own[u][c] - zp[c];
           // explicit fma: the same rounding in every instantiation (and in
           // the multigrid tail kernel, which repeats this step)
-          dd[c] = fma(c1[c], dd[c], c2[c] * ((rr[c] - q[u][c]) / dg[c]));
-          zn[c] = own[u][c] + dd[c];
+          const double dd = fma(c1[c], dp, c2[c] * ((rr[c] - q[u][c]) / dg[c]));
+          zn[c] = own[u][c] + dd;
           if constexpr (MODE == M_CHEBX) {
             xv[c] = xv[c] + zn[c];
             if (a.dotv) acc[c] = fma(dv[c], xv[c], acc[c]);
@@ -540,12 +550,8 @@ void fe3d_stencil_kernel(StencilArgs a) {
             acc[c] = fma(rr[c], zn[c], acc[c]);
           }
         }
-        if constexpr (MODE == M_CHEBX) {
-          st<VEC>(a.x + e, xv);
-        } else {
-          st<VEC>(a.d + e, dd);
-          st<VEC>(a.zout + e, zn);
-        }
+        if constexpr (MODE == M_CHEBX) st<VEC>(a.x + e, xv);
+        else st<VEC>(a.zout + e, zn);
       }
     }
   }

@@ -290,7 +290,6 @@ __global__ __launch_bounds__(kNT) void update_kernel(UpdateArgs a) {
         double zz[VEC];
 #pragma unroll
         for (int c = 0; c < VEC; ++c) zz[c] = (rv[u][c] / dv[u][c]) / ith[c];
-        st<VEC>(a.d + e, zz);
         st<VEC>(a.z + e, zz);
       }
     }
@@ -365,10 +364,10 @@ __global__ __launch_bounds__(kNT) void init_kernel(InitArgs a) {
   }
 }
 
-// Chebyshev: z = D^-1 r / theta for every member (start of an application),
-// and d = z where the caller keeps the increment (the 3-D model)
+// Chebyshev: z_0 = D^-1 r / theta for every member (start of an application;
+// the first step's increment d_0 is z_0 itself)
 template <int VEC>
-__global__ __launch_bounds__(kNT) void cheb_start_kernel(const double* V, const double* r, double* d,
+__global__ __launch_bounds__(kNT) void cheb_start_kernel(const double* V, const double* r,
                                                          double* z, Members m, Geometry g) {
   const int t = threadIdx.x, sv = (t % g.tpp) * VEC;
   if (sv >= g.S) return;
@@ -384,7 +383,6 @@ __global__ __launch_bounds__(kNT) void cheb_start_kernel(const double* V, const 
     ld<VEC>(dv, V + (size_t)g.cslot * g.vstride + e);
 #pragma unroll
     for (int c = 0; c < VEC; ++c) zz[c] = (rv[c] / dv[c]) / ith[c];
-    if (d) st<VEC>(d + e, zz);
     st<VEC>(z + e, zz);
   }
 }
@@ -509,9 +507,9 @@ void launch_init(const InitArgs& a, int groups, hipStream_t s) {
   ENS_LAUNCH_VEC(a.g.vec, init_kernel, dim3(groups), s, a);
 }
 
-void launch_cheb_start(const double* V, const double* r, double* d, double* z, const Members& m,
+void launch_cheb_start(const double* V, const double* r, double* z, const Members& m,
                        const Geometry& g, int groups, hipStream_t s) {
-  ENS_LAUNCH_VEC(g.vec, cheb_start_kernel, dim3(groups), s, V, r, d, z, m, g);
+  ENS_LAUNCH_VEC(g.vec, cheb_start_kernel, dim3(groups), s, V, r, z, m, g);
 }
 
 void launch_final(double* x, const double* p0, const double* p1, const Members& m,

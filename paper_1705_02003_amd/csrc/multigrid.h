@@ -20,7 +20,6 @@ struct MgLevel {
   const double* b;  // right-hand side of the level's correction equation
   double* x;        // the level's V-cycle output
   double* res;      // residual b - A x
-  double* d;        // smoother increment
   double* za;       // smoother iterate (started by the caller)
   double* Vt;       // levels of at most kMgTailNodes nodes per direction: the 27
                     // slots member-major, [S][27][m^3], for the fused coarse tail
@@ -75,8 +74,7 @@ struct MgTransferArgs {
   double* fine_x;          // prolongation: the fine iterate, corrected in place
   const double* Vc;        // restriction with start or solve: the coarse operator (diagonal slot)
   const double* cheb;      // restriction with start: the coarse smoother's theta per member
-  double* d;               // restriction with start: d = z = D^-1 b / theta
-  double* z;
+  double* z;               // restriction with start: z = D^-1 b / theta
   double* x;               // restriction with solve: x = b / a (one node)
   const int* done;
   int op;                  // MgTransfer

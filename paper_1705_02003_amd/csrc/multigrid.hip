@@ -197,7 +197,6 @@ __global__ __launch_bounds__(kNT) void mg_restrict_kernel(MgTransferArgs a) {
     gstore(&a.coarse_out[e], acc);
     if (a.op == MG_RESTRICT_START) {
       const double z = (acc / gload(&a.Vc[(size_t)13 * a.vstride_c + e])) / th;
-      gstore(&a.d[e], z);
       gstore(&a.z[e], z);
     } else if (a.op == MG_RESTRICT_SOLVE) {
       gstore(&a.x[e], acc / gload(&a.Vc[(size_t)13 * a.vstride_c + e]));
@@ -475,10 +474,10 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 static size_t mg_header_bytes() {
   return align256(sizeof(double) * (size_t)kMgMaxLevels * kMaxS * (kChebCoef + 1));
 }
-// the coarse level's 27 slots and five vectors
+// the coarse level's 27 slots and four vectors
 static size_t mg_level_doubles(int m, int S) {
   const size_t nr = (size_t)m * m * m;
-  return slot_stride(nr * S) * (27 + 5);
+  return slot_stride(nr * S) * (27 + 4);
 }
 
 // the member-major operator copy that the fused coarse tail stages
@@ -518,8 +517,7 @@ void mg_carve(void* base, int n, int S, const int* ctl, MgHierarchy& H) {
     v.b = vec;
     v.x = vec + vs;
     v.res = vec + 2 * vs;
-    v.d = vec + 3 * vs;
-    v.za = vec + 4 * vs;
+    v.za = vec + 3 * vs;
     p += sizeof(double) * mg_level_doubles(ms[l], S);
     if (ms[l] <= kMgTailNodes) {
       v.Vt = reinterpret_cast<double*>(p);

@@ -397,7 +397,7 @@ def test_non_finite_parameters_rejected_before_device_work(L, bad):
 
 def test_multigrid_descriptor_without_gpu(L):
     """ENS_PRECOND_MULTIGRID: the workspace adds the coarse levels (a header of
-    per-level smoother coefficients, then per level 27 matrix slots and five
+    per-level smoother coefficients, then per level 27 matrix slots and four
     vectors of the level's slot stride, and for levels of at most 7 nodes per
     direction a member-major copy of the 27 slots); the 2-D model and grids
     with n + 1 not a power of two are refused before any device work."""
@@ -420,7 +420,7 @@ def test_multigrid_descriptor_without_gpu(L):
             levels.append(m)
         head = ((8 * 12 * 64 * (2 * 8 + 2 + 1) + 255) // 256) * 256
         copy = sum(((8 * 27 * m ** 3 * S + 255) // 256) * 256 for m in levels if m <= 7)
-        assert ws - wc == head + sum(8 * 32 * stride(m, S) for m in levels) + copy, (n, S)
+        assert ws - wc == head + sum(8 * 31 * stride(m, S) for m in levels) + copy, (n, S)
     a = C.c_void_p(4096)
     for bad in (L.ens_problem(10, 4, 0, 3, 0.0), L.ens_problem(31, 4, 0, 2, 0.4),
                 L.ens_problem(16, 4, 0, 3, 0.0)):
