@@ -99,10 +99,10 @@ struct AsmArgs {
 // step (the ring holds z_0 = D^-1 r / theta formed from r, q and the
 // diagonal; r is written to a second buffer, since neighbouring tiles still
 // read the old one).  M_RESID (3-D): q = r - A src, and with cheb_init the
-// smoother start d = zout = D^-1 q / theta.  M_CHEBX (3-D): the Chebyshev
-// step of a multigrid post-smoother, its result added to the level's x in
-// place (x += src + d; neither d nor z stored), with dotv the partial sums
-// of dotv^T x.
+// smoother start zout = D^-1 q / theta.  M_CHEBX (3-D): the Chebyshev step
+// of a multigrid post-smoother, its result added to the level's x in place
+// (x += src + d, d = c1 src + c2 D^-1 (r - A src); nothing else stored),
+// with dotv the partial sums of dotv^T x.
 enum Mode { M_SPMV = 0, M_PCG_J = 1, M_PCG_Z = 2, M_CHEB = 3, M_CHEB1 = 4, M_RESID = 5, M_CHEBX = 6 };
 
 struct StencilArgs {

@@ -18,7 +18,7 @@
 // Reductions: every per-member inner product is reduced in a fixed tree
 // (per-thread sequential sums, xor-shuffles across lanes that hold the same
 // members, a fixed-order sum across the four waves, then a fixed-order sum
-// over workgroup partials in the last workgroup to finish).  The tree does
+// over the workgroup partials in a one-workgroup finishing kernel).  The tree does
 // not depend on the member index, so results are deterministic and
 // permuting members permutes results bit for bit.  No floating-point
 // atomics are used.
@@ -233,10 +233,11 @@ __global__ __launch_bounds__(kNT) void stencil_kernel(StencilArgs a) {
 
 // ------------------------------------------------------------ update
 // r -= alpha q for active members; then (Jacobi) z = D^-1 r and partial
-// r^T z, r^T r, or (Chebyshev) the first semi-iteration step d = z =
-// D^-1 r / theta.  The last workgroup applies the convergence test
-// ||r_k|| <= rtol ||b|| per member, records the member's iteration count,
-// forms beta (Jacobi) and raises the done flag when no member is active.
+// r^T z, r^T r, or (Chebyshev, the 3-D model and multigrid) the start of the
+// preconditioner application z_0 = D^-1 r / theta and partial r^T r.  The
+// finishing kernel then applies the convergence test ||r_k|| <= rtol ||b||
+// per member, records the member's iteration count, forms beta (Jacobi) and
+// raises the done flag when no member is active.
 template <int VEC, bool CHEB>
 __global__ __launch_bounds__(kNT) void update_kernel(UpdateArgs a) {
   __shared__ double red[kWaves * 64 * 2];

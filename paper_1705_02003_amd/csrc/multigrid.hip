@@ -181,7 +181,7 @@ __global__ __launch_bounds__(kFinNT) void mg_coef_kernel(MgCoefArgs a) {
 // ------------------------------------------------------------ grid transfer
 // Restriction b_c(I) = sum_f w(f) res(2I + f), one thread per (coarse node,
 // member).  MG_RESTRICT_START also starts the coarse pre-smoother,
-// d = z = D_c^-1 b_c / theta; MG_RESTRICT_SOLVE solves the one-node coarsest
+// z = D_c^-1 b_c / theta; MG_RESTRICT_SOLVE solves the one-node coarsest
 // level, x = b_c / a.
 __global__ __launch_bounds__(kNT) void mg_restrict_kernel(MgTransferArgs a) {
   if (is_done(a.done)) return;
