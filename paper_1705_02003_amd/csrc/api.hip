@@ -156,10 +156,19 @@ Geometry make_geometry3(int m, int S) {
   g.dim = 3;
   g.nslot = 27;
   g.cslot = 13;
-  // the product kernel takes kFe3dPair x-neighbouring points per thread
+  // The product kernel takes g.np x-neighbouring points per thread: pairs
+  // (a third fewer loads of p per point) when they still give every CU a
+  // workgroup, single points on grids too small for that (coarse multigrid
+  // levels, narrow ensembles), which doubles the workgroups.
   const size_t ppb = (size_t)(kNT / g.tpp);
   const size_t npair = (size_t)((m + kFe3dPair - 1) / kFe3dPair) * m * m;
-  g.groups = (int)std::min<size_t>((npair + ppb - 1) / ppb, 512);
+  size_t need = (npair + ppb - 1) / ppb;
+  g.np = kFe3dPair;
+  if (need < 256) {
+    g.np = 1;
+    need = (g.nr + ppb - 1) / ppb;
+  }
+  g.groups = (int)std::min<size_t>(need, 512);
   return g;
 }
 

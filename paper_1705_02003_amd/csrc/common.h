@@ -72,6 +72,7 @@ struct Geometry {
   int full;                  // 1: the sweep reads all nine matrix values per row
   int dim;                   // 2: nine-point grid n x n; 3: 27-point grid n x n x n
   int nslot, cslot;          // matrix slots per row and the diagonal's slot
+  int np;                    // 3-D product: x-neighbouring points per thread (1 or 2)
 };
 
 

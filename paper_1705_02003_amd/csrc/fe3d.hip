@@ -370,8 +370,9 @@ __global__ __launch_bounds__(kNT) void fe3d_dir_kernel(StencilArgs a) {
   }
 }
 
-// The 27-point product, grid-strided over pairs of x-neighbouring points
-// (i0, i0 + 1) with VEC members per thread; the mode's fused work follows
+// The 27-point product, grid-strided over runs of NP x-neighbouring points
+// (pairs, or single points on grids too small to fill the chip with pairs)
+// with VEC members per thread; the mode's fused work follows
 // (see the top of this file).  A pair shares the p values of a 4-wide window
 // on each of its nine (dj, dk) rows, loaded once: 36 loads of p per pair
 // instead of 54.  Neighbour offsets are the pair's offset plus a uniform row
@@ -391,12 +392,11 @@ __global__ __launch_bounds__(kNT) void fe3d_dir_kernel(StencilArgs a) {
 // and the matrix streams from memory about once at 14 words per row.  The
 // products are formed in the same order, so on a bitwise-symmetric matrix
 // both reads give the same bits.
-template <int VEC, int MODE, bool SYM>
+template <int VEC, int MODE, bool SYM, int NP>
 __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3)))
 void fe3d_stencil_kernel(StencilArgs a) {
   __shared__ double red[kWaves * 64 * 2];
   constexpr bool PCG = (MODE == M_PCG_J || MODE == M_PCG_Z);
-  constexpr int NP = kFe3dPair;
   const Geometry& g = a.g;
   if constexpr (MODE != M_SPMV) {
     if (gload(&a.m.ctl[CTL_DONE])) return;
@@ -582,10 +582,15 @@ template <int VEC, int MODE>
 static void fe3d_step(const StencilArgs& a, hipStream_t s) {
   if constexpr (MODE == M_PCG_J || MODE == M_PCG_Z)
     hipLaunchKernelGGL((fe3d_dir_kernel<VEC, MODE>), dim3(init_groups(a.g)), dim3(kNT), 0, s, a);
-  if (a.g.full)
-    hipLaunchKernelGGL((fe3d_stencil_kernel<VEC, MODE, false>), dim3(a.g.groups), dim3(kNT), 0, s, a);
-  else
-    hipLaunchKernelGGL((fe3d_stencil_kernel<VEC, MODE, true>), dim3(a.g.groups), dim3(kNT), 0, s, a);
+  // g.np points per thread (pairs on grids that fill the chip with them)
+  const dim3 grid(a.g.groups), block(kNT);
+  if (a.g.np == 1) {
+    if (a.g.full) hipLaunchKernelGGL((fe3d_stencil_kernel<VEC, MODE, false, 1>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((fe3d_stencil_kernel<VEC, MODE, true, 1>), grid, block, 0, s, a);
+  } else {
+    if (a.g.full) hipLaunchKernelGGL((fe3d_stencil_kernel<VEC, MODE, false, kFe3dPair>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((fe3d_stencil_kernel<VEC, MODE, true, kFe3dPair>), grid, block, 0, s, a);
+  }
 }
 
 template <int MODE>
