@@ -30,6 +30,7 @@ import workloads
 from oracle import CONVERGED
 from oracle import adjoint as oadj
 from oracle import fe3d as ofe
+from oracle import multigrid as omg
 from oracle import pcg as opcg
 from oracle import problem as oprob
 from oracle import sparse_grid as sg
@@ -162,6 +163,46 @@ def test_fe3d_size_31cube_s32():
         xe, _, _, _ = opcg.pcg(A, bo, dg, 0.0, int(res.iters[s]))
         assert np.linalg.norm(x[:, s] - xe) <= 1e-9 * np.linalg.norm(xe)
         assert np.linalg.norm(bo - A @ x[:, s]) <= 2 * w.rtol * np.linalg.norm(bo)
+
+
+@pytest.mark.parametrize("precond", ["chebyshev", "multigrid"])
+def test_fe3d_size_31cube_s32_polynomial_and_multigrid(precond):
+    """The 3-D workload's own size and width (31^3, S = 32), where the
+    product kernel takes pairs of points per thread (smaller grids and
+    narrower ensembles take single points): Chebyshev-4 and multigrid PCG
+    against the oracle for two members (counts +-1, equal-count solutions
+    1e-9, true residual), and for multigrid the fused coarse tail against
+    the level-by-level launches bit for bit."""
+    ens = E()
+    w = workloads.FE3D_32
+    m, S = w.n, 32
+    log_case(test="fullsize-fe3d-" + precond, m=m, S=S)
+    ys = workloads.uniform_samples(w.seed, S, w.d)
+    prob = ens.Problem(m, w.d, dim=3)
+    V, b = ens.assemble(prob, to_dev(ys))
+    res = ens.solve(prob, V, b, ens.SolverOptions(precond=precond, rtol=w.rtol, max_iter=w.max_iter))
+    assert np.all(res.status == CONVERGED)
+    x = res.x.cpu().numpy()
+    for s in (3, 30):
+        A, bo, dg = ofe.assemble(ys[s], m)
+        if precond == "multigrid":
+            _, I, st, _ = omg.pcg(A, bo, m, w.rtol, 2000)
+            xe, _, _, _ = omg.pcg(A, bo, m, 0.0, int(res.iters[s]))
+        else:
+            lm = opcg.gershgorin_lmax(A, dg)
+
+            def M(v, A=A, dg=dg, lm=lm):
+                return opcg.chebyshev_apply(A, dg, v, lm)
+
+            _, I, st, _ = opcg.pcg(A, bo, dg, w.rtol, 20000, M)
+            xe, _, _, _ = opcg.pcg(A, bo, dg, 0.0, int(res.iters[s]), M)
+        assert st == CONVERGED and abs(int(res.iters[s]) - I) <= 1, (s, res.iters[s], I)
+        assert np.linalg.norm(x[:, s] - xe) <= 1e-9 * np.linalg.norm(xe)
+        assert np.linalg.norm(bo - A @ x[:, s]) <= 2 * w.rtol * np.linalg.norm(bo)
+    if precond == "multigrid":
+        lw = ens.solve(prob, V, b, ens.SolverOptions(precond=precond, rtol=w.rtol, max_iter=w.max_iter,
+                                                     mg_levelwise=True))
+        assert np.array_equal(lw.iters, res.iters) and torch.equal(lw.x, res.x)
 
 
 def test_batch_full_grid_sizes():
