@@ -157,14 +157,17 @@ Geometry make_geometry3(int m, int S) {
   g.nslot = 27;
   g.cslot = 13;
   // The product kernel takes g.np x-neighbouring points per thread: pairs
-  // (a third fewer loads of p per point) when they still give every CU a
-  // workgroup, single points on grids too small for that (coarse multigrid
-  // levels, narrow ensembles), which doubles the workgroups.
+  // (a third fewer loads of p per point) when they give at least half the
+  // 256 CUs a workgroup, single points on grids too small for that (coarse
+  // multigrid levels, an S = 1 solve), which doubles the workgroups.  (At
+  // 31^3, S = 8 pairs give 241 workgroups and single points were 2-4 %
+  // slower; at 15^3, S = 32 pairs give 113 and single points were 25 %
+  // faster.)
   const size_t ppb = (size_t)(kNT / g.tpp);
   const size_t npair = (size_t)((m + kFe3dPair - 1) / kFe3dPair) * m * m;
   size_t need = (npair + ppb - 1) / ppb;
   g.np = kFe3dPair;
-  if (need < 256) {
+  if (need < 128) {
     g.np = 1;
     need = (g.nr + ppb - 1) / ppb;
   }
